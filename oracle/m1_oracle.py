@@ -1,0 +1,312 @@
+"""FP64 CPU oracle of the M1 Lyman-alpha transfer step -- TEST INFRASTRUCTURE.
+
+Only the tests, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import or call this module.  It shares no code with the GPU
+library (it has its own constants, frequency grid, Voigt averages, geometry
+and step), and never imports it.
+
+Split of work:
+  * this file: setup in numpy/scipy FP64 (frequency grid of Section 2.1,
+    bin-averaged Voigt profile of Appendix A with scipy's erf/erfc/dawsn,
+    per-cell opacities, the RT time step of Section 2.1) and the driver;
+  * ``m1_oracle_core.c``: the time step itself as plain C loops.
+
+Readings of the paper that this oracle takes (the same list is kept in the
+design notes of the repository):
+  * state E = 4 pi J / c, F = 4 pi H / c per Hz; emission j_s = l phi / (4 pi);
+  * frequency grid: half-width min(1e5 dnu_D(T_min), 0.99 nu_Lya,
+    nu_LyC - nu_Lya), widths dnu_D(T_min) q^m until the half-width is reached,
+    the last edge clipped to it; bin centres are arithmetic midpoints;
+  * sigma0 = 5.9e-14 T4^-1/2 cm^2 and a_v = 4.7e-4 T4^-1/2 exactly;
+  * emission profile <phi>_k = <H>_k / sum_j dnu_j <H>_j (integral over the grid);
+  * interface opacity depth from volume centroids (cylindrical R) or midpoints;
+  * vacuum ghosts E = F = 0, alpha_F = 0; reflecting ghosts are mirror images;
+  * face velocity = mean of the two cell velocities (no hydro star states);
+  * one emission/absorption substep per RT step;
+  * radiation force f = sum_k dnu_k alpha_F,k F**_k (equal to the H-change form);
+  * the frequency step uses D from the post-source state; zero frequency flux
+    at both grid ends; cells without line opacity use the upwind limit.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+import time
+
+import numpy as np
+from scipy import special
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle_m1.so")
+SRC_PATH = os.path.join(HERE, "m1_oracle_core.c")
+
+# ---------------------------------------------------------------- constants
+C_LIGHT = 2.99792458e10          # cm/s
+K_B = 1.380649e-16               # erg/K
+H_PLANCK = 6.62607015e-27        # erg s
+M_H = 1.6735575e-24              # g
+LAMBDA_LYA = 1215.67e-8          # cm
+NU_LYA = C_LIGHT / LAMBDA_LYA    # Hz
+EV = 1.602176634e-12             # erg
+NU_LYC = 13.6057 * EV / H_PLANCK # Hz
+SQRT_PI = math.sqrt(math.pi)
+
+
+def doppler_width(T):
+    """Delta nu_D = nu_Lya sqrt(2 k_B T / (m_H c^2))."""
+    return NU_LYA * np.sqrt(2.0 * K_B * np.asarray(T, dtype=np.float64) / (M_H * C_LIGHT ** 2))
+
+
+def voigt_a(T):
+    """a_v = 4.7e-4 (T / 1e4 K)^-1/2 (Section 2.1)."""
+    return 4.7e-4 / np.sqrt(np.asarray(T, dtype=np.float64) / 1.0e4)
+
+
+def sigma0(T):
+    """Line-centre cross-section 5.9e-14 (T / 1e4 K)^-1/2 cm^2 (Section 2.1)."""
+    return 5.9e-14 / np.sqrt(np.asarray(T, dtype=np.float64) / 1.0e4)
+
+
+# ---------------------------------------------------------- frequency grid
+def frequency_grid(T_min=30.0, q=1.1, half_width=1.0e5):
+    """Symmetric geometric grid in dnu = nu - nu_Lya (Section 2.1).
+
+    Returns dict with dnu_edges (nb+1, relative to nu_Lya), dnu (widths),
+    nu_c (absolute bin centres) and nb."""
+    w0 = float(doppler_width(T_min))
+    X = min(half_width * w0, 0.99 * NU_LYA, NU_LYC - NU_LYA)
+    widths = []
+    s, w = 0.0, w0
+    while s < X:
+        widths.append(w)
+        s += w
+        w *= q
+    pos = np.concatenate([[0.0], np.cumsum(widths)])
+    pos[-1] = X                                  # last bin clipped to the half-width
+    edges = np.concatenate([-pos[::-1], pos[1:]])
+    dnu = np.diff(edges)
+    nu_c = NU_LYA + 0.5 * (edges[:-1] + edges[1:])
+    return dict(dnu_edges=edges, dnu=dnu, nu_c=nu_c, nb=len(dnu), X=X, w0=w0)
+
+
+# ------------------------------------------------------- Voigt bin averages
+def voigt_integral_difference(x_lo, x_hi, a):
+    """I(x_hi, a) - I(x_lo, a) for the second-order Voigt expansion (Appendix A):
+    I(x, a) = sqrt(pi)/2 erf(x) - (2a/sqrt(pi)) Dawson(x) + a^2 x exp(-x^2).
+    The erf difference is taken through erfc on each side of the line so far
+    wings do not cancel."""
+    x_lo = np.asarray(x_lo, dtype=np.float64)
+    x_hi = np.asarray(x_hi, dtype=np.float64)
+    erf_part = np.where(
+        x_lo >= 0.0, special.erfc(x_lo) - special.erfc(x_hi),
+        np.where(x_hi <= 0.0, special.erfc(-x_hi) - special.erfc(-x_lo),
+                 special.erf(x_hi) - special.erf(x_lo)))
+    return (0.5 * SQRT_PI * erf_part
+            - (2.0 * a / SQRT_PI) * (special.dawsn(x_hi) - special.dawsn(x_lo))
+            + a * a * (x_hi * np.exp(-x_hi * x_hi) - x_lo * np.exp(-x_lo * x_lo)))
+
+
+def voigt_bin_average(grid, T):
+    """<H>_k = [I(x_{k+1/2}) - I(x_{k-1/2})] / dx_k at temperature T."""
+    dD = float(doppler_width(T))
+    a = float(voigt_a(T))
+    x = grid["dnu_edges"] / dD
+    return voigt_integral_difference(x[:-1], x[1:], a) / (grid["dnu"] / dD)
+
+
+# --------------------------------------------------------------- the setup
+BC_CODE = {"vacuum": 0, "reflect": 1}
+
+
+def rt_time_step(p):
+    """dt = CFL (1/D) min over cells of min(dR, dZ)/(c_tilde + |u|), D = 2."""
+    f = p["fields"]
+    dx = (p["x1"] - p["x0"]) / p["nx"]
+    dy = (p["y1"] - p["y0"]) / p["ny"]
+    speed = p["c_tilde"] + np.sqrt(f["u_x"] ** 2 + f["u_y"] ** 2)
+    return float(p["cfl"] * 0.5 * np.min(min(dx, dy) / speed))
+
+
+class OracleSetup:
+    """All FP64 arrays the C core needs for one problem."""
+
+    def __init__(self, p):
+        self.p = p
+        f = p["fields"]
+        self.nx, self.ny = p["nx"], p["ny"]
+        self.grid = frequency_grid(p["T_min"], p["q"], p["half_width"])
+        self.nb = self.grid["nb"]
+        T = np.ascontiguousarray(f["T"], dtype=np.float64).ravel()
+        Tu, inv = np.unique(T, return_inverse=True)
+        self.cls = inv.astype(np.int32)
+        self.hbar = np.stack([voigt_bin_average(self.grid, t) for t in Tu])
+        norm = self.hbar @ self.grid["dnu"]        # integral of H over the grid [Hz]
+        self.phi = self.hbar / norm[:, None]
+        self.T = T
+        self.alpha = np.ascontiguousarray(f["n_HI"], dtype=np.float64).ravel() * sigma0(T)
+        self.dnuD = doppler_width(T)
+        self.hkT = H_PLANCK / (K_B * T)
+        cont = lambda k: np.ascontiguousarray(f[k], dtype=np.float64).ravel()
+        self.acabs, self.acF, self.pd = cont("alpha_abs"), cont("alpha_flux"), cont("p_d")
+        self.ux, self.uy, self.emis = cont("u_x"), cont("u_y"), cont("emis")
+        self.xe = p["x0"] + (p["x1"] - p["x0"]) * np.arange(self.nx + 1) / self.nx
+        self.ye = p["y0"] + (p["y1"] - p["y0"]) * np.arange(self.ny + 1) / self.ny
+        self.dt = rt_time_step(p)
+        self.c_tilde = float(p["c_tilde"])
+        self.geom = 1 if p["geom"] == "cyl" else 0
+        self.bc = [BC_CODE[b] for b in p["bc"]]
+        self.recoil = int(p.get("recoil", 1))
+        self.doppler = int(p.get("doppler", 1))
+
+
+# ------------------------------------------------------------- the C core
+class _Prob(ctypes.Structure):
+    _fields_ = ([("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nb", ctypes.c_int),
+                 ("geom", ctypes.c_int), ("bc", ctypes.c_int * 4),
+                 ("recoil", ctypes.c_int), ("doppler", ctypes.c_int),
+                 ("c_tilde", ctypes.c_double), ("dt", ctypes.c_double)]
+                + [(n, ctypes.c_void_p) for n in
+                   ("xe", "ye", "nu_c", "dnu", "alpha", "acabs", "acF", "pd", "ux",
+                    "uy", "dnuD", "hkT", "emis", "cls", "hbar", "phi")])
+
+
+def build(force=False):
+    """Compile the C core with gcc (no fast-math, no FMA contraction)."""
+    if not force and os.path.exists(LIB_PATH) and \
+            os.path.getmtime(LIB_PATH) >= os.path.getmtime(SRC_PATH):
+        return LIB_PATH
+    tmp = LIB_PATH + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                           "-ffp-contract=off", "-fno-fast-math", "-o", tmp, SRC_PATH, "-lm"])
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB_PATH)
+        L.oracle_step.restype = ctypes.c_int
+        L.oracle_step.argtypes = [ctypes.POINTER(_Prob)] + [ctypes.c_void_p] * 7
+        L.oracle_eddington.argtypes = [ctypes.c_double] * 3 + [ctypes.c_void_p]
+        L.oracle_interface_rates.argtypes = [ctypes.c_double] * 6 + [ctypes.c_void_p]
+        L.oracle_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Oracle:
+    """Steps one problem on the CPU in FP64.  State arrays are [nb, ny, nx]."""
+
+    def __init__(self, p, dt=None):
+        self.s = OracleSetup(p)
+        if dt is not None:
+            self.s.dt = float(dt)
+        s = self.s
+        shape = (s.nb, s.ny, s.nx)
+        self.E = np.zeros(shape)
+        self.Fx = np.zeros(shape)
+        self.Fy = np.zeros(shape)
+        self.force = np.zeros((4, s.ny, s.nx))
+        self._scratch = [np.zeros(shape) for _ in range(3)]
+        self.t = 0.0
+        self.steps = 0
+        self._keep = []
+        P = _Prob()
+        P.nx, P.ny, P.nb, P.geom = s.nx, s.ny, s.nb, s.geom
+        for i in range(4):
+            P.bc[i] = s.bc[i]
+        P.recoil, P.doppler = s.recoil, s.doppler
+        P.c_tilde, P.dt = s.c_tilde, s.dt
+        for name, arr in (("xe", s.xe), ("ye", s.ye), ("nu_c", s.grid["nu_c"]),
+                          ("dnu", s.grid["dnu"]), ("alpha", s.alpha), ("acabs", s.acabs),
+                          ("acF", s.acF), ("pd", s.pd), ("ux", s.ux), ("uy", s.uy),
+                          ("dnuD", s.dnuD), ("hkT", s.hkT), ("emis", s.emis),
+                          ("cls", s.cls), ("hbar", s.hbar), ("phi", s.phi)):
+            a = np.ascontiguousarray(arr)
+            self._keep.append(a)
+            setattr(P, name, a.ctypes.data)
+        self.P = P
+
+    @property
+    def dt(self):
+        return self.s.dt
+
+    def set_state(self, E, Fx, Fy):
+        self.E[...] = E
+        self.Fx[...] = Fx
+        self.Fy[...] = Fy
+
+    def step(self, n=1):
+        L = lib()
+        a, b, c = self._scratch
+        for _ in range(n):
+            L.oracle_step(ctypes.byref(self.P), _ptr(self.E), _ptr(self.Fx), _ptr(self.Fy),
+                          _ptr(self.force), _ptr(a), _ptr(b), _ptr(c))
+            self.t += self.s.dt
+            self.steps += 1
+        return self
+
+    def post_source_state(self):
+        """E**, F** of the last step (the state the force is computed from)."""
+        return tuple(x.copy() for x in self._scratch)
+
+    def solve_steady(self, rel_tol=1e-6, max_steps=100000, check_every=16):
+        """Step until r = ||E^{n+1} - E^n||_2 / ||E^{n+1}||_2 < rel_tol, checked on
+        every check_every-th step.  Returns (converged, steps, r)."""
+        r = float("inf")
+        while self.steps < max_steps:
+            n = min(check_every - 1, max_steps - self.steps - 1)
+            if n > 0:
+                self.step(n)
+            prev = self.E.copy()
+            self.step(1)
+            num = float(np.sqrt(np.sum((self.E - prev) ** 2)))
+            den = float(np.sqrt(np.sum(self.E ** 2)))
+            r = num / den if den > 0 else (0.0 if num == 0 else float("inf"))
+            if r < rel_tol:
+                return True, self.steps, r
+        return False, self.steps, r
+
+
+def eddington(E, Fx, Fy):
+    out = np.zeros(4)
+    lib().oracle_eddington(E, Fx, Fy, _ptr(out))
+    return out
+
+
+def interface_rates(Kl, Cl, dl, Kr, Cr, dr):
+    out = np.zeros(2)
+    lib().oracle_interface_rates(Kl, Cl, dl, Kr, Cr, dr, _ptr(out))
+    return out
+
+
+def run(p, steps=None, dt=None):
+    o = Oracle(p, dt=dt)
+    o.step(p["steps"] if steps is None else steps)
+    return o
+
+
+def num_threads():
+    return lib().oracle_num_threads()
+
+
+if __name__ == "__main__":
+    import sys
+    sys.path.insert(0, os.path.dirname(HERE))
+    from paper_2606_02711_amd import inputs
+    p = inputs.config1()
+    t0 = time.time()
+    o = run(p, steps=int(sys.argv[1]) if len(sys.argv) > 1 else 20)
+    print("steps", o.steps, "time", time.time() - t0, "threads", num_threads())
+    print("E max", o.E.max(), "force max", np.abs(o.force).max())

@@ -1,0 +1,316 @@
+"""Seeded synthetic inputs for the M1 Lyman-alpha transfer step.
+
+This module only *builds problems*: grids, per-cell physical fields and run
+parameters.  It holds none of the transfer method's arithmetic (no closure,
+flux, source or frequency-step formula), so both the FP64 CPU oracle and the
+GPU library can consume what it produces without sharing method code.
+
+A problem is a plain dict:
+
+  geom        "cart" (2D slab, unit depth) or "cyl" (axisymmetric R, z)
+  nx, ny      cells along x (or R) and y (or z)
+  x0,x1,y0,y1 domain edges [cm]
+  bc          (x-, x+, y-, y+), each "vacuum" or "reflect"
+  T_min, q, half_width   frequency-grid parameters (Section 2.1: 30 K, 1.1,
+                         1e5 Doppler widths of T_min)
+  c_tilde, cfl           reduced speed of light [cm/s], CFL factor
+  recoil, doppler        0/1 switches for the recoil and Doppler terms
+  steps                  number of explicit RT steps the workload runs
+  fields      dict of float64 arrays of shape (ny, nx) (index [j, i]):
+              n_HI [cm^-3], T [K], u_x, u_y [cm/s],
+              alpha_abs  = continuum absorption alpha_c (1 - omega)  [cm^-1]
+              alpha_flux = continuum flux opacity alpha_c (1 - omega g) [cm^-1]
+              p_d        = Lya destruction probability per scattering
+              emis       = Lya luminosity density [erg s^-1 cm^-3]
+
+Workload recipes (the paper runs no public dataset on this path; these
+seeded fields stand in for its test clouds and star-forming clouds):
+
+  config 1  Cartesian 64^2 unit box, uniform neutral gas, line-centre depth
+            1e4 across the box, T = 1e4 K, Gaussian source, 200 steps.
+  config 2  cylindrical 512 x 1024 (R, z) = 1 pc x 2 pc, ionised bubble in a
+            log-normal neutral shell with a k^-2 random field, radial outflow
+            to 30 km/s, dust 0.01 solar, p_d = 1e-6, point source on the axis.
+  config 3  64 uniform clouds of log-uniform size 64..512 cells per side.
+  config 4  request stream of clouds of size 128..2048 per side.
+  config 5  cylindrical 4096 x 8192 turbulent cloud with 16 ring sources.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# Physical constants used to *construct* inputs (cgs).
+PC = 3.0856775814913673e18          # parsec [cm]
+KMS = 1.0e5                         # km/s [cm/s]
+C_LIGHT = 2.99792458e10
+M_H = 1.6735575e-24
+# Line-centre cross-section scaling quoted in Section 2.1 (5.9e-14 T4^-1/2 cm^2);
+# used only to turn a requested optical depth into a neutral density.
+SIGMA0_1E4 = 5.9e-14
+# Table 2, Lya row, mass-weighted over the three grain bins (f_Sil, f_C, f_PAH).
+F_SIL, F_C, F_PAH = 0.7264, 0.2517, 0.0218
+KAPPA_ABS_LYA = F_SIL * 1.84e4 + F_C * 2.48e4 + F_PAH * 3.31e5   # cm^2/g of dust
+KAPPA_F_LYA = F_SIL * 2.22e4 + F_C * 2.84e4 + F_PAH * 3.31e5
+DUST_TO_GAS_SOLAR = 1.0 / 162.0
+
+SEED_BASE = 260602711
+
+FIELD_NAMES = ("n_HI", "T", "u_x", "u_y", "alpha_abs", "alpha_flux", "p_d", "emis")
+
+
+def rng_for(config_id: int, sub: int = 0) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([SEED_BASE + config_id, sub]))
+
+
+# --------------------------------------------------------------------------
+# geometry of the *input recipe* (cell volumes, used to normalise luminosity)
+# --------------------------------------------------------------------------
+def edges(p):
+    xe = p["x0"] + (p["x1"] - p["x0"]) * np.arange(p["nx"] + 1) / p["nx"]
+    ye = p["y0"] + (p["y1"] - p["y0"]) * np.arange(p["ny"] + 1) / p["ny"]
+    return xe, ye
+
+
+def cell_volumes(p) -> np.ndarray:
+    xe, ye = edges(p)
+    dy = np.diff(ye)
+    if p["geom"] == "cyl":
+        ring = math.pi * (xe[1:] ** 2 - xe[:-1] ** 2)
+        return dy[:, None] * ring[None, :]
+    return dy[:, None] * np.diff(xe)[None, :]
+
+
+def cell_centres(p):
+    """Plain midpoints: used only to place sources and density structure."""
+    xe, ye = edges(p)
+    return 0.5 * (xe[1:] + xe[:-1]), 0.5 * (ye[1:] + ye[:-1])
+
+
+def gaussian_source(p, cx, cy, sigma, L=1.0) -> np.ndarray:
+    """Gaussian luminosity density centred at (cx, cy), sigma in cm; its
+    volume integral over the grid is L [erg/s]."""
+    xc, yc = cell_centres(p)
+    r2 = (xc[None, :] - cx) ** 2 + (yc[:, None] - cy) ** 2
+    shape = np.exp(-0.5 * r2 / sigma ** 2)
+    vol = cell_volumes(p)
+    return shape * (L / float(np.sum(shape * vol)))
+
+
+def point_source_cells(p, cells, L=1.0) -> np.ndarray:
+    """Split luminosity L equally over the listed (i, j) cells."""
+    vol = cell_volumes(p)
+    em = np.zeros((p["ny"], p["nx"]))
+    share = L / len(cells)
+    for (i, j) in cells:
+        em[j, i] += share / vol[j, i]
+    return em
+
+
+def dust_opacities(n_H, dust_solar):
+    """Continuum opacities of dust at Lya (Table 2 Lya row; rho = n_H m_H/0.75,
+    solar dust-to-gas ratio 1/162)."""
+    rho = np.asarray(n_H) * M_H / 0.75
+    D = np.asarray(dust_solar) * DUST_TO_GAS_SOLAR
+    return D * rho * KAPPA_ABS_LYA, D * rho * KAPPA_F_LYA
+
+
+def gaussian_random_field(rng, ny, nx, slope=-2.0) -> np.ndarray:
+    """Zero-mean, unit-variance Gaussian random field on the index grid with
+    power spectrum P(k) ~ k^slope (k = 0 removed)."""
+    white = rng.standard_normal((ny, nx))
+    ky = np.fft.fftfreq(ny)[:, None]
+    kx = np.fft.rfftfreq(nx)[None, :]
+    k = np.sqrt(kx * kx + ky * ky)
+    amp = np.zeros_like(k)
+    nz = k > 0
+    amp[nz] = k[nz] ** (0.5 * slope)
+    g = np.fft.irfft2(np.fft.rfft2(white) * amp, s=(ny, nx))
+    g -= g.mean()
+    g /= g.std()
+    return g
+
+
+def base_problem(geom, nx, ny, x0, x1, y0, y1, bc, c_tilde_frac=0.01, steps=1):
+    return dict(
+        geom=geom, nx=int(nx), ny=int(ny),
+        x0=float(x0), x1=float(x1), y0=float(y0), y1=float(y1),
+        bc=tuple(bc), T_min=30.0, q=1.1, half_width=1.0e5,
+        c_tilde=c_tilde_frac * C_LIGHT, cfl=0.4, recoil=1, doppler=1,
+        steps=int(steps), fields={},
+    )
+
+
+def uniform_fields(p, n_HI, T, dust_solar=0.0, p_d=0.0, n_H=None):
+    sh = (p["ny"], p["nx"])
+    n_H = n_HI if n_H is None else n_H
+    a_abs, a_F = dust_opacities(np.full(sh, n_H), dust_solar)
+    return dict(
+        n_HI=np.full(sh, float(n_HI)), T=np.full(sh, float(T)),
+        u_x=np.zeros(sh), u_y=np.zeros(sh),
+        alpha_abs=a_abs, alpha_flux=a_F, p_d=np.full(sh, float(p_d)),
+        emis=np.zeros(sh),
+    )
+
+
+# --------------------------------------------------------------------------
+# the five workloads
+# --------------------------------------------------------------------------
+def config1():
+    """64^2 Cartesian unit box, tau0 = 1e4 across, T = 1e4 K, Gaussian source."""
+    p = base_problem("cart", 64, 64, 0.0, 1.0, 0.0, 1.0, ("vacuum",) * 4, steps=200)
+    n_HI = 1.0e4 / SIGMA0_1E4          # alpha * 1 cm = 1e4 at T = 1e4 K
+    f = uniform_fields(p, n_HI, 1.0e4)
+    f["emis"] = gaussian_source(p, 0.5, 0.5, 2.0 / 64.0, 1.0)
+    p["fields"] = f
+    return p
+
+
+def config2(nx=512, ny=1024, steps=1000):
+    """Cylindrical (R, z) bubble + log-normal neutral shell, radial outflow."""
+    p = base_problem("cyl", nx, ny, 0.0, PC, -PC, PC,
+                     ("reflect", "vacuum", "vacuum", "vacuum"), steps=steps)
+    rng = rng_for(2)
+    R, Z = cell_centres(p)
+    r = np.sqrt(R[None, :] ** 2 + Z[:, None] ** 2)
+    g = gaussian_random_field(rng, ny, nx)
+    sig = 1.0
+    n_shell = 1.0e3 * np.exp(sig * g - 0.5 * sig * sig)
+    bubble = r < 0.3 * PC
+    n_H = np.where(bubble, 10.0, n_shell)
+    n_HI = np.where(bubble, 10.0 * 1.0e-4, n_shell)
+    T = np.where(bubble, 1.0e4, 100.0)
+    a_abs, a_F = dust_opacities(n_H, 0.01)
+    vr = 30.0 * KMS * np.minimum(r / PC, 1.0)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        ux = np.where(r > 0, vr * R[None, :] / r, 0.0)
+        uy = np.where(r > 0, vr * Z[:, None] / r, 0.0)
+    jz = ny // 2
+    em = point_source_cells(p, [(0, jz - 1), (0, jz)], 1.0)
+    p["fields"] = dict(n_HI=n_HI, T=T, u_x=ux, u_y=uy, alpha_abs=a_abs,
+                       alpha_flux=a_F, p_d=np.full(n_H.shape, 1.0e-6), emis=em)
+    return p
+
+
+def uniform_cloud(geom, n, log10_NHI, T, dust_solar, L_box=PC, steps=500):
+    """Uniform neutral cloud with a Gaussian sigma = 2 cells central source.
+    Cartesian: [-L/2, L/2]^2, all vacuum.  Cylindrical: R, z in [0, L/2] with
+    the axis and the z = 0 midplane reflecting."""
+    half = 0.5 * L_box
+    if geom == "cart":
+        p = base_problem("cart", n, n, -half, half, -half, half,
+                         ("vacuum",) * 4, steps=steps)
+    else:
+        p = base_problem("cyl", n, n, 0.0, half, 0.0, half,
+                         ("reflect", "vacuum", "reflect", "vacuum"), steps=steps)
+    n_HI = 10.0 ** log10_NHI / half
+    f = uniform_fields(p, n_HI, T, dust_solar=dust_solar, p_d=0.0)
+    dx = (p["x1"] - p["x0"]) / n
+    f["emis"] = gaussian_source(p, 0.0, 0.0, 2.0 * dx, 1.0)
+    p["fields"] = f
+    return p
+
+
+def config3(n_grids=64, lo=64, hi=512, config_id=3, steps=500):
+    rng = rng_for(config_id)
+    probs = []
+    for g in range(n_grids):
+        n = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+        geom = "cart" if g < n_grids // 2 else "cyl"
+        lN = rng.uniform(19.0, 23.0)
+        T = 10.0 ** rng.uniform(2.0, 4.0)
+        dust = rng.uniform(0.0, 0.01)
+        probs.append(uniform_cloud(geom, n, lN, T, dust, steps=steps))
+    return probs
+
+
+def config4_requests(rate=50.0, duration=120.0, lo=128, hi=2048, seed_sub=0):
+    """Poisson request stream: list of (arrival_time_s, problem_factory_args)."""
+    rng = rng_for(4, seed_sub)
+    t = 0.0
+    reqs = []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            break
+        n = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+        geom = "cart" if rng.uniform() < 0.5 else "cyl"
+        lN = rng.uniform(19.0, 23.0)
+        T = 10.0 ** rng.uniform(2.0, 4.0)
+        dust = rng.uniform(0.0, 0.01)
+        reqs.append((t, dict(geom=geom, n=n, log10_NHI=lN, T=T, dust_solar=dust)))
+    return reqs
+
+
+def config5(nx=4096, ny=8192, steps=10000):
+    p = base_problem("cyl", nx, ny, 0.0, PC, -PC, PC,
+                     ("reflect", "vacuum", "vacuum", "vacuum"), steps=steps)
+    rng = rng_for(5)
+    R, Z = cell_centres(p)
+    r = np.sqrt(R[None, :] ** 2 + Z[:, None] ** 2)
+    sig = 1.5
+    g = gaussian_random_field(rng, ny, nx)
+    n_H = 1.0e4 * np.exp(sig * g - 0.5 * sig * sig)
+    del g
+    hii = r < 0.2 * PC
+    n_HI = np.where(hii, n_H * 1.0e-4, n_H)
+    T = np.where(hii, 1.0e4, 100.0)
+    a_abs, a_F = dust_opacities(n_H, 0.01)
+    ux = gaussian_random_field(rng, ny, nx)
+    uy = gaussian_random_field(rng, ny, nx)
+    vmax = float(np.sqrt(ux * ux + uy * uy).max())
+    ux *= 50.0 * KMS / vmax
+    uy *= 50.0 * KMS / vmax
+    cells = []
+    dx = (p["x1"] - p["x0"]) / nx
+    dy = (p["y1"] - p["y0"]) / ny
+    while len(cells) < 16:
+        rr = 0.2 * PC * math.sqrt(rng.uniform())
+        th = rng.uniform(0.0, math.pi)
+        sx, sz = rr * math.sin(th), rr * math.cos(th)
+        i = min(int(sx / dx), nx - 1)
+        j = min(int((sz - p["y0"]) / dy), ny - 1)
+        if (i, j) not in cells:
+            cells.append((i, j))
+    em = point_source_cells(p, cells, 1.0)
+    p["fields"] = dict(n_HI=n_HI, T=T, u_x=ux, u_y=uy, alpha_abs=a_abs,
+                       alpha_flux=a_F, p_d=np.full(n_H.shape, 1.0e-7), emis=em)
+    return p
+
+
+def random_small(geom, nx, ny, seed, with_velocity=True, with_dust=True,
+                 half_width=1.0e5, T_range=(100.0, 1.0e4), log_nHI=(-6.0, -2.0),
+                 L_box=1.0e16, bc=None):
+    """Small random heterogeneous problem for parity tests (all physics on)."""
+    rng = np.random.default_rng(np.random.SeedSequence([SEED_BASE, 99, seed]))
+    if geom == "cart":
+        p = base_problem("cart", nx, ny, 0.0, L_box, 0.0, L_box * ny / nx,
+                         bc or ("vacuum",) * 4)
+    else:
+        p = base_problem("cyl", nx, ny, 0.0, L_box, -0.5 * L_box * ny / nx,
+                         0.5 * L_box * ny / nx,
+                         bc or ("reflect", "vacuum", "vacuum", "vacuum"))
+    p["half_width"] = half_width
+    sh = (ny, nx)
+    n_HI = 10.0 ** rng.uniform(*log_nHI, size=sh)
+    T = 10.0 ** rng.uniform(math.log10(T_range[0]), math.log10(T_range[1]), size=sh)
+    if with_dust:
+        a_abs, a_F = dust_opacities(n_HI, rng.uniform(0.0, 0.05, size=sh))
+    else:
+        a_abs, a_F = np.zeros(sh), np.zeros(sh)
+    if with_velocity:
+        ux = rng.uniform(-50.0, 50.0, size=sh) * KMS
+        uy = rng.uniform(-50.0, 50.0, size=sh) * KMS
+    else:
+        ux, uy = np.zeros(sh), np.zeros(sh)
+    pd = 10.0 ** rng.uniform(-8.0, -3.0, size=sh)
+    em = rng.uniform(0.0, 1.0, size=sh) ** 4
+    em *= 1.0 / float(np.sum(em * cell_volumes(p)))
+    p["fields"] = dict(n_HI=n_HI, T=T, u_x=ux, u_y=uy, alpha_abs=a_abs,
+                       alpha_flux=a_F, p_d=pd, emis=em)
+    return p
+
+
+def get_config(cid: int, **kw):
+    return {1: config1, 2: config2, 5: config5}[cid](**kw)
