@@ -1,0 +1,158 @@
+"""Throughput benchmark of the M1 Lyman-alpha step on one MI355X.
+
+Workload: the 512 x 1024 cylindrical (R, z) cloud (ionised bubble in a
+log-normal neutral shell, radial outflow, dust, p_d = 1e-6, point source on
+the axis), 194 frequency bins, synthetic seeded fields.  A step is one full
+pass of the hot path: advection + emission/absorption, force density, and the
+implicit frequency step, for every cell and bin.
+
+value      : FP32-path cell-bin updates per second (N_cells x N_nu x steps / s),
+             state resident in HBM before the timed region starts.
+fp64_value : the FP64 plain path on the same workload.
+roofline   : the dominant kernel's algorithmic bytes (read + write of E, F_x,
+             F_y once per cell-bin: 24 B FP32) over its HIP-event duration.
+cpu_baseline : the FP64 oracle on the host cores, on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("m1_step_kernels.hip", "m1_device.h"):
+        with open(os.path.join(ROOT, "paper_2606_02711_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, prec):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    rec = d.get("kernels", {}).get(f"{kernel}:{prec}")
+    return rec.get("bytes_per_launch") if rec else None
+
+
+def run_path(p, prec, steps, warmup):
+    import torch
+    from paper_2606_02711_amd import m1
+    log(f"[bench] init {prec}")
+    g = m1.M1Grid(p, prec=prec)
+    g.step(warmup)
+    g.sync()
+    torch.cuda.synchronize()
+    log(f"[bench] timing {steps} steps {prec}")
+    t0 = time.perf_counter()
+    ms = [0.0, 0.0]
+    left = steps
+    while left > 0:
+        n = min(left, 4096)
+        a, b = g.step_profiled(n)
+        ms[0] += a
+        ms[1] += b
+        left -= n
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cell_bins = g.ncell * g.nb
+    res = dict(wall=wall, ms_advect=ms[0], ms_freq=ms[1], cell_bins=cell_bins, nb=g.nb,
+               ncell=g.ncell, rate=cell_bins * steps / wall)
+    del g
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(p, steps=2):
+    from oracle import m1_oracle
+    log(f"[bench] oracle sample: {steps} steps of the full workload on the host")
+    o = m1_oracle.Oracle(p)
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    n = o.s.nx * o.s.ny * o.s.nb * steps
+    return {"value": n / dt, "unit": "cell-bin updates/s", "cores": m1_oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} steps of the 512x1024 cylindrical workload from E=F=0, all "
+                      f"{o.s.nb} bins ({n:.3e} cell-bin updates, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    from paper_2606_02711_amd import inputs
+    p = inputs.config2()
+    r32 = run_path(p, "fp32", args.steps, args.warmup)
+    r64 = None if args.no_fp64 else run_path(p, "fp64", args.steps, args.warmup)
+    dom = "advect_source" if r32["ms_advect"] >= r32["ms_freq"] else "freq_step"
+    dom_ms = (r32["ms_advect"] if dom == "advect_source" else r32["ms_freq"]) / args.steps
+    alg_bytes = 24.0 * r32["cell_bins"]                    # per launch, FP32
+    achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
+    traffic = measured_traffic(dom, "fp32")
+    out = {
+        "metric": "M1 Lya cell-updates/s (FP32 batched vs FP64 plain), %HBM roofline, p99 solve latency",
+        "value": r32["rate"],
+        "unit": "cell-bin updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * r32["wall"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "cylindrical 512x1024 (R,z) bubble + log-normal k^-2 shell, "
+                               "radial outflow 30 km/s, dust 0.01 solar, p_d 1e-6, axis point "
+                               "source; 194 frequency bins; FP32 path",
+                   "nx": 512, "ny": 1024, "n_nu": r32["nb"],
+                   "spatial_cell_updates_per_s": r32["rate"] / r32["nb"]},
+        "kernel_ms_per_step": {"advect_source": r32["ms_advect"] / args.steps,
+                               "freq_step": r32["ms_freq"] / args.steps},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+    }
+    if r64 is not None:
+        out["fp64_value"] = r64["rate"]
+        out["fp64_ms_per_step"] = 1e3 * r64["wall"] / args.steps
+        out["fp64_kernel_ms_per_step"] = {"advect_source": r64["ms_advect"] / args.steps,
+                                          "freq_step": r64["ms_freq"] / args.steps}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(p)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,173 @@
+/*
+ * m1lya.h -- C ABI of the MI355X M1 Lyman-alpha transfer step.
+ *
+ * The method is the two-moment (M1) Lyman-alpha radiative-transfer step of
+ * Nebrin et al. (arXiv 2606.02711), Section 2.1 and Appendix A:
+ *   - Levermore closure of the Eddington tensor (Section 2.1, M1 closure);
+ *   - frequency grid of N_nu bins geometric in nu - nu_Lya (Section 2.1);
+ *   - explicit advection step: MinMod-limited linear reconstruction of J and
+ *     f = H/J, GLF interface flux (= HLL with signal speeds +-c_tilde) blended
+ *     with the diffusion flux by eps(tau) (Section 2.1, corrected GLF flux),
+ *     upwind velocity advection and radiation-pressure work term;
+ *   - implicit emission / absorption / destruction step (Section 2.1, BDF1);
+ *   - radiation force density handed to hydrodynamics (Section 2.3);
+ *   - implicit frequency step: Fokker-Planck diffusion, recoil and Doppler
+ *     shift with the exponential scheme and a per-cell tridiagonal solve
+ *     (Appendix A), H rescaled by J_new / J_old;
+ *   - RT time step from the CFL condition (Section 2.1).
+ *
+ * Conventions common to every entry point
+ *   - Every function returns an m1_status; nothing aborts or throws across
+ *     the ABI.  m1_last_error() returns a thread-local message for the last
+ *     failure of the calling thread.
+ *   - Pointers named d_* are device pointers (hipMalloc'd memory or a torch
+ *     CUDA tensor's data_ptr()).  The library never allocates device memory:
+ *     all device state lives in the caller's workspace (see
+ *     m1_workspace_bytes), which is what makes admission by HBM budget exact.
+ *     The handle itself is a small host allocation released by m1_free.
+ *   - Cell arrays are [ny][nx] with index j*nx + i; x is R and y is z in
+ *     cylindrical geometry.  Per-bin arrays are [N_nu][ny][nx].
+ *   - State E_k = 4 pi J_k / c and F_k = 4 pi H_k / c (per Hz, cgs): the
+ *     spectral radiation energy density and flux over c, bin averaged.
+ *   - Work is enqueued on the handle's stream and is asynchronous unless
+ *     stated otherwise.  Device faults surface at m1_sync, m1_get_state,
+ *     m1_solve_steady (which synchronise).
+ *   - A handle is not thread safe.  Distinct handles on distinct streams may
+ *     run concurrently.
+ */
+#ifndef M1LYA_H
+#define M1LYA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  M1_OK = 0,
+  M1_EINVAL = -1,        /* invalid argument (validated before any device work) */
+  M1_ENOMEM = -2,        /* workspace smaller than m1_workspace_bytes */
+  M1_EDEVICE = -3,       /* a HIP runtime call or kernel failed */
+  M1_ENOTCONV = -4,      /* m1_solve_steady reached max_steps */
+  M1_ESTATE = -5,        /* handle in an unusable state */
+  M1_EUNSUPPORTED = -6   /* valid request the library does not implement */
+} m1_status;
+
+typedef enum { M1_CART2D = 0, M1_CYL_RZ = 1 } m1_geom;
+typedef enum { M1_BC_VACUUM = 0, M1_BC_REFLECT = 1 } m1_bc;
+/* State storage and arithmetic.  M1_FP64: everything in double.  M1_FP32:
+ * state, opacities and transport arithmetic in float; frequency-step
+ * coefficients and elimination in float with a subtraction-free scheme, or in
+ * double for cells whose line-centre optical depth exceeds fp64_tau; force
+ * sums and residual norms in double. */
+typedef enum { M1_FP64 = 0, M1_FP32 = 1 } m1_prec;
+
+typedef struct {
+  int32_t geom;            /* m1_geom.  Cylindrical requires x0 == 0 with a
+                              reflecting x- (axis) boundary. */
+  int32_t nx, ny;          /* cells, each >= 4 */
+  double x0, x1, y0, y1;   /* domain edges [cm], uniform spacing */
+  int32_t bc[4];           /* m1_bc for x-, x+, y-, y+ */
+  double T_min;            /* frequency resolution temperature [K] (30) */
+  double q;                /* bin growth factor (1.1) */
+  double half_width;       /* grid half-width in dnu_D(T_min) units (1e5) */
+  double c_tilde;          /* reduced speed of light [cm/s], 0 < c_tilde <= c */
+  double cfl;              /* CFL factor, 0 < cfl <= 1 (0.4) */
+  int32_t recoil;          /* 0/1: atomic recoil term of the frequency step */
+  int32_t doppler;         /* 0/1: Doppler term of the frequency step */
+  int32_t prec;            /* m1_prec */
+  double fp64_tau;         /* FP32 only: line-centre cell optical depth above
+                              which a cell's frequency step runs in double
+                              (1e6); +inf disables the islands */
+} m1_config;
+
+/* Per-cell physical inputs, FP64, [ny][nx].  Host pointers when on_device is
+ * 0, device pointers otherwise.  Read once by m1_init; the library keeps no
+ * reference to them afterwards. */
+typedef struct {
+  const double *n_HI;        /* neutral hydrogen density [cm^-3], >= 0 */
+  const double *T;           /* gas temperature [K], > 0 */
+  const double *u_x, *u_y;   /* gas velocity [cm/s] */
+  const double *alpha_abs;   /* continuum absorption alpha_c (1 - omega) [cm^-1] */
+  const double *alpha_flux;  /* continuum flux opacity alpha_c (1 - omega g) [cm^-1] */
+  const double *p_d;         /* Lya destruction probability per scattering, >= 0 */
+  const double *emis;        /* Lya luminosity density [erg s^-1 cm^-3], >= 0,
+                                emitted with the normalised Voigt profile */
+  int32_t on_device;
+} m1_fields;
+
+typedef struct m1_handle m1_handle;
+
+/* Fills *cfg with the paper's defaults (T_min 30 K, q 1.1, half-width 1e5,
+ * CFL 0.4, recoil and Doppler on, FP64, fp64_tau 1e6, vacuum boundaries). */
+int32_t m1_default_config(m1_config *cfg);
+
+/* Number of frequency bins of cfg's grid (194 with the defaults; Section 2.1). */
+int32_t m1_num_bins(const m1_config *cfg, int32_t *n_nu);
+
+/* Exact device workspace bytes for cfg when the temperature field holds
+ * n_temp_classes distinct values (pass 0 for the worst case, one per cell).
+ * m1_count_temperature_classes gives that number for a host T array. */
+int32_t m1_workspace_bytes(const m1_config *cfg, int64_t n_temp_classes, size_t *bytes);
+int32_t m1_count_temperature_classes(const double *T_host, int64_t n, int64_t *n_classes);
+
+/* Validates cfg and fields, lays out the caller-owned workspace d_ws of
+ * ws_bytes (>= m1_workspace_bytes for the field's class count, 256-byte
+ * aligned), runs the set-up kernels (frequency grid, bin-averaged Voigt
+ * profile, opacities, velocity gradients, CFL time step) on `stream`
+ * (a hipStream_t; NULL = default stream) and sets E = F = 0.  Synchronous.
+ * On success *out receives a new handle. */
+int32_t m1_init(const m1_config *cfg, const m1_fields *fields, void *d_ws,
+                size_t ws_bytes, void *stream, m1_handle **out);
+
+/* Enqueues nsteps RT steps (advection + emission/absorption, force, frequency
+ * step).  *t_now (may be NULL) receives the simulated time after them. */
+int32_t m1_step(m1_handle *h, int32_t nsteps, double *t_now);
+
+/* Measurement variant of m1_step: records HIP events around every kernel
+ * launch on the handle's stream, waits, and returns the summed device time
+ * [ms] of the advection/emission-absorption kernel in ms[0] and of the
+ * force/frequency-step kernel in ms[1] (nsteps <= 4096).  Same results as
+ * m1_step; the events add only launch overhead. */
+int32_t m1_step_profiled(m1_handle *h, int32_t nsteps, double *ms);
+
+/* Enqueues a copy of the radiation force density of the last step into
+ * caller device arrays of ncell doubles [dyn cm^-3]: total (x, y) and the gas
+ * share (line opacity part; may be NULL).  Asynchronous. */
+int32_t m1_force(m1_handle *h, double *d_fx, double *d_fy, double *d_fx_gas,
+                 double *d_fy_gas);
+
+/* Steps until r = ||E^{n+1} - E^n||_2 / ||E^{n+1}||_2 (all cells and bins,
+ * FP64 sums) is below rel_tol, checking every check_every steps, or until
+ * max_steps steps were taken by this call (then M1_ENOTCONV).  Blocking. */
+int32_t m1_solve_steady(m1_handle *h, double rel_tol, int64_t max_steps,
+                        int32_t check_every, int64_t *steps_done, double *resid);
+
+/* Residual r of the last step (as in m1_solve_steady).  Blocking. */
+int32_t m1_residual(m1_handle *h, double *resid);
+
+/* Copy the state out of / into caller device arrays [N_nu][ny][nx] of the
+ * handle's precision (double for M1_FP64, float for M1_FP32), physical units.
+ * get is blocking; set is asynchronous. */
+int32_t m1_get_state(m1_handle *h, void *d_E, void *d_Fx, void *d_Fy);
+int32_t m1_set_state(m1_handle *h, const void *d_E, const void *d_Fx, const void *d_Fy);
+
+/* Scalars of a handle: dt [s], N_nu, precision, cells, internal scale 2^e. */
+int32_t m1_get_info(const m1_handle *h, double *dt, int32_t *n_nu, int32_t *prec,
+                    int64_t *ncell, int32_t *scale_exp2);
+
+/* Advances n handles (same precision, same stream) by nsteps steps with one
+ * batched launch per kernel and step; bitwise identical to stepping each
+ * handle alone.  Enqueued on the first handle's stream. */
+int32_t m1_step_batched(m1_handle *const *hs, int32_t n, int32_t nsteps);
+
+int32_t m1_sync(m1_handle *h);         /* waits for the stream; surfaces faults */
+int32_t m1_free(m1_handle *h);         /* frees the host handle, not the workspace */
+const char *m1_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* M1LYA_H */

@@ -1,0 +1,100 @@
+// Device-side building blocks of the M1 Lyman-alpha step (gfx950).
+//
+// Everything here is written for CDNA wave64 execution: one lane per cell
+// (advection: one cell and a run of bins; frequency step: one cell, all
+// bins), coalesced along x of the [bin][y][x] structure-of-arrays state.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace m1 {
+
+constexpr double kC = 2.99792458e10;        // speed of light [cm/s]
+constexpr int kVacuum = 0;
+constexpr int kReflect = 1;
+
+// Kernel arguments of one grid.  Pointers are into the handle's workspace.
+template <typename R>
+struct GridArgs {
+  int nx, ny, nb, geom;
+  int bc[4];
+  int recoil, doppler;
+  R ctdt;                 // c_tilde * dt
+  R ctdt_c;               // c_tilde * dt / c (work term)
+  // ping-pong state: in (E, Fx, Fy) -> out
+  const R *E, *Fx, *Fy;
+  R *Eo, *Fxo, *Fyo;
+  // per cell
+  const int32_t *cls;
+  const uint8_t *island;
+  const R *alpha, *acF, *acabs, *pda, *em;
+  const R *grad;          // [4][ncell]: dx ux, dy uy, dy ux + dx uy, <u_R/R>
+  const R *ufx, *ufy;     // face-normal velocities [(nx+1) ny], [nx (ny+1)]
+  // per class and bin
+  const R *hbar, *phi;    // [ncls][nb]
+  const double *dD2h;     // [ncls] 0.5 dnu_D^2
+  const double *hkT;      // [ncls] h / (k_B T)
+  const double *dnu;      // [nb] bin widths
+  const double *two_nu;   // [nb] 2 / nu_k
+  const double *nu_c;     // [nb] nu_k / c
+  // geometry per column (index i + 2, i in [-2, nx+1]) and per row
+  const R *xidl, *xhm, *xhp;   // 1/(xc_i - xc_{i-1}), x_{i-1/2} - xc_i, x_{i+1/2} - xc_i
+  const R *cxm, *cxp, *chp;    // [nx] ctdt A_{i-1/2}/dV, ctdt A_{i+1/2}/dV, ctdt (A+ - A-)/dV
+  const R *yidl, *yhm, *yhp;
+  const R *cy;                 // [ny] ctdt / dz_j
+  // frequency step
+  R *zs, *ws;             // scratch [nb][ncell]
+  double *force;          // [4][ncell]
+};
+
+// ---------------------------------------------------------------------------
+// Levermore closure in cancellation-free form.  With f = |F|/E and
+// s = sqrt(4 - 3 f^2):  (1 - chi)/2 = (1 - f^2)/(1 + s)  and
+// (3 chi - 1)/2 h_i h_j = 3 f_i f_j / (2 + s), so
+//   D = (1 - f^2)/(1 + s) I + 3 f (x) f / (2 + s),
+// which needs no division by |F| and stays exact at F = 0.
+template <typename R>
+struct Eddington {
+  R xx, yy, xy, pp;
+};
+
+template <typename R>
+__device__ __forceinline__ Eddington<R> closure_f(R fx, R fy) {
+  R f2 = fx * fx + fy * fy;
+  if (f2 > R(1)) f2 = R(1);
+  R s = sqrt(R(4) - R(3) * f2);
+  R iso = (R(1) - f2) / (R(1) + s);
+  R g = R(3) / (R(2) + s);
+  Eddington<R> d;
+  d.xx = iso + g * fx * fx;
+  d.yy = iso + g * fy * fy;
+  d.xy = g * fx * fy;
+  d.pp = iso;
+  return d;
+}
+
+template <typename R>
+__device__ __forceinline__ Eddington<R> closure_state(R E, R Fx, R Fy) {
+  R fx = R(0), fy = R(0);
+  if (E > R(0)) {
+    R inv = R(1) / E;
+    fx = Fx * inv;
+    fy = Fy * inv;
+    R n2 = fx * fx + fy * fy;
+    if (n2 > R(1)) {
+      R sc = R(1) / sqrt(n2);
+      fx *= sc;
+      fy *= sc;
+    }
+  }
+  return closure_f(fx, fy);
+}
+
+template <typename R>
+__device__ __forceinline__ R minmod(R a, R b) {
+  if (a > R(0) && b > R(0)) return a < b ? a : b;
+  if (a < R(0) && b < R(0)) return a > b ? a : b;
+  return R(0);
+}
+
+}  // namespace m1

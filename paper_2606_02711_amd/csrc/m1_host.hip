@@ -1,0 +1,762 @@
+// C ABI of the M1 Lyman-alpha step: validation, workspace layout, set-up and
+// the stepping / steady-state / output entry points declared in m1lya.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "m1lya.h"
+#include "m1_dawson.h"
+#include "m1_kernels.h"
+
+using namespace m1;
+
+namespace {
+
+// Physical constants (cgs)
+constexpr double kKB = 1.380649e-16;
+constexpr double kHP = 6.62607015e-27;
+constexpr double kMH = 1.6735575e-24;
+constexpr double kLyaLambda = 1215.67e-8;
+constexpr double kEV = 1.602176634e-12;
+constexpr double kLyCeV = 13.6057;
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kSqrtPi = 1.77245385090551602729816748334;
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      return fail(M1_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));     \
+  } while (0)
+
+double nu_lya() { return kC / kLyaLambda; }
+double doppler_width(double T) { return nu_lya() * sqrt(2.0 * kKB * T / (kMH * kC * kC)); }
+
+// Frequency grid of Section 2.1: symmetric in dnu = nu - nu_Lya, two central
+// bins of width dnu_D(T_min), widths growing by q outward, half-width
+// min(half_width dnu_D(T_min), 0.99 nu_Lya, nu_LyC - nu_Lya), last bin clipped.
+struct FreqGrid {
+  std::vector<double> edges;   // relative to nu_Lya, nb+1
+  std::vector<double> dnu, nuc;
+  int nb = 0;
+};
+
+int build_grid(const m1_config& c, FreqGrid& g) {
+  if (!(c.T_min > 0) || !(c.q > 1.0) || !(c.half_width > 0))
+    return fail(M1_EINVAL, "frequency grid needs T_min > 0, q > 1, half_width > 0");
+  double w0 = doppler_width(c.T_min);
+  double nuL = nu_lya();
+  double X = std::min(std::min(c.half_width * w0, 0.99 * nuL), kLyCeV * kEV / kHP - nuL);
+  std::vector<double> pos(1, 0.0);
+  double s = 0.0, w = w0;
+  while (s < X) {
+    s += w;
+    pos.push_back(s);
+    w *= c.q;
+    if (pos.size() > 100000) return fail(M1_EINVAL, "frequency grid too large");
+  }
+  pos.back() = X;
+  int m = (int)pos.size() - 1;
+  g.nb = 2 * m;
+  g.edges.resize(g.nb + 1);
+  for (int i = 0; i <= m; ++i) {
+    g.edges[m + i] = pos[i];
+    g.edges[m - i] = -pos[i];
+  }
+  g.dnu.resize(g.nb);
+  g.nuc.resize(g.nb);
+  for (int k = 0; k < g.nb; ++k) {
+    g.dnu[k] = g.edges[k + 1] - g.edges[k];
+    g.nuc[k] = nuL + 0.5 * (g.edges[k] + g.edges[k + 1]);
+  }
+  return M1_OK;
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t state[2][3];
+  size_t zs, wsc, force;
+  size_t cls, island, alpha, acF, acabs, pda, em, grad, ufx, ufy;
+  size_t hbar, phi, dD2h, hkT;
+  size_t dnu, two_nu, nu_c, edges;
+  size_t geo, xe, ye, nodes;
+  size_t partial, result;
+  size_t total;
+};
+
+constexpr int kResBlocks = 1024;
+
+Layout make_layout(int nx, int ny, int nb, int64_t ncls, size_t rs) {
+  Layout L;
+  size_t off = 0;
+  size_t nc = (size_t)nx * ny, nbc = (size_t)nb * nc;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+  for (int b = 0; b < 2; ++b)
+    for (int f = 0; f < 3; ++f) L.state[b][f] = take(nbc * rs);
+  L.zs = take(nbc * rs);
+  L.wsc = take(nbc * rs);
+  L.force = take(4 * nc * sizeof(double));
+  L.cls = take(nc * sizeof(int32_t));
+  L.island = take(nc);
+  L.alpha = take(nc * rs);
+  L.acF = take(nc * rs);
+  L.acabs = take(nc * rs);
+  L.pda = take(nc * rs);
+  L.em = take(nc * rs);
+  L.grad = take(4 * nc * rs);
+  L.ufx = take((size_t)(nx + 1) * ny * rs);
+  L.ufy = take((size_t)nx * (ny + 1) * rs);
+  L.hbar = take((size_t)ncls * nb * rs);
+  L.phi = take((size_t)ncls * nb * rs);
+  L.dD2h = take((size_t)ncls * sizeof(double));
+  L.hkT = take((size_t)ncls * sizeof(double));
+  L.dnu = take(nb * sizeof(double));
+  L.two_nu = take(nb * sizeof(double));
+  L.nu_c = take(nb * sizeof(double));
+  L.edges = take((nb + 1) * sizeof(double));
+  L.geo = take((size_t)(3 * (nx + 4) + 3 * nx + 3 * (ny + 4) + ny) * rs);
+  L.xe = take((nx + 1) * sizeof(double));
+  L.ye = take((ny + 1) * sizeof(double));
+  L.nodes = take(kDawsonNodes * sizeof(double));
+  L.partial = take(3 * kResBlocks * sizeof(double));
+  L.result = take(2 * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+int validate_config(const m1_config* c, int* nb_out) {
+  if (!c) return fail(M1_EINVAL, "config is NULL");
+  if (c->geom != M1_CART2D && c->geom != M1_CYL_RZ) return fail(M1_EINVAL, "bad geom %d", c->geom);
+  if (c->nx < 4 || c->ny < 4) return fail(M1_EINVAL, "nx, ny must be >= 4");
+  if ((int64_t)c->nx * c->ny > ((int64_t)1 << 31)) return fail(M1_EINVAL, "grid too large");
+  if (!(c->x1 > c->x0) || !(c->y1 > c->y0) || !isfinite(c->x0) || !isfinite(c->x1) ||
+      !isfinite(c->y0) || !isfinite(c->y1))
+    return fail(M1_EINVAL, "bad domain edges");
+  for (int s = 0; s < 4; ++s)
+    if (c->bc[s] != M1_BC_VACUUM && c->bc[s] != M1_BC_REFLECT)
+      return fail(M1_EINVAL, "bad boundary code on side %d", s);
+  if (c->geom == M1_CYL_RZ && (c->x0 != 0.0 || c->bc[0] != M1_BC_REFLECT))
+    return fail(M1_EINVAL, "cylindrical grids start on the axis (x0 = 0, reflecting x-)");
+  if (!(c->c_tilde > 0.0) || c->c_tilde > kC) return fail(M1_EINVAL, "need 0 < c_tilde <= c");
+  if (!(c->cfl > 0.0) || c->cfl > 1.0) return fail(M1_EINVAL, "need 0 < cfl <= 1");
+  if (c->prec != M1_FP64 && c->prec != M1_FP32) return fail(M1_EINVAL, "bad precision");
+  if (c->recoil != 0 && c->recoil != 1) return fail(M1_EINVAL, "recoil must be 0/1");
+  if (c->doppler != 0 && c->doppler != 1) return fail(M1_EINVAL, "doppler must be 0/1");
+  if (isnan(c->fp64_tau)) return fail(M1_EINVAL, "fp64_tau is NaN");
+  FreqGrid g;
+  int st = build_grid(*c, g);
+  if (st) return st;
+  if (nb_out) *nb_out = g.nb;
+  return M1_OK;
+}
+
+}  // namespace
+
+struct m1_handle {
+  m1_config cfg;
+  int nb = 0;
+  int64_t ncls = 0;
+  size_t nc = 0;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  Layout L;
+  double dt = 0.0;
+  int e2 = 0;                 // internal state = physical state * 2^e2
+  int cur = 0;                // state buffer holding the current state
+  int64_t steps = 0;
+  double t = 0.0;
+  GridArgs<float> af[2];
+  GridArgs<double> ad[2];
+  bool broken = false;
+};
+
+namespace {
+
+template <typename R>
+void fill_args(m1_handle* h, GridArgs<R>* a) {
+  const m1_config& c = h->cfg;
+  const Layout& L = h->L;
+  char* w = h->ws;
+  int nx = c.nx, ny = c.ny;
+  for (int dir = 0; dir < 2; ++dir) {
+    GridArgs<R>& g = a[dir];
+    g.nx = nx; g.ny = ny; g.nb = h->nb; g.geom = c.geom;
+    for (int s = 0; s < 4; ++s) g.bc[s] = c.bc[s];
+    g.recoil = c.recoil; g.doppler = c.doppler;
+    g.ctdt = (R)(c.c_tilde * h->dt);
+    g.ctdt_c = (R)(c.c_tilde * h->dt / kC);
+    int in = dir, out = dir ^ 1;
+    g.E = (const R*)(w + L.state[in][0]);
+    g.Fx = (const R*)(w + L.state[in][1]);
+    g.Fy = (const R*)(w + L.state[in][2]);
+    g.Eo = (R*)(w + L.state[out][0]);
+    g.Fxo = (R*)(w + L.state[out][1]);
+    g.Fyo = (R*)(w + L.state[out][2]);
+    g.cls = (const int32_t*)(w + L.cls);
+    g.island = (const uint8_t*)(w + L.island);
+    g.alpha = (const R*)(w + L.alpha);
+    g.acF = (const R*)(w + L.acF);
+    g.acabs = (const R*)(w + L.acabs);
+    g.pda = (const R*)(w + L.pda);
+    g.em = (const R*)(w + L.em);
+    g.grad = (const R*)(w + L.grad);
+    g.ufx = (const R*)(w + L.ufx);
+    g.ufy = (const R*)(w + L.ufy);
+    g.hbar = (const R*)(w + L.hbar);
+    g.phi = (const R*)(w + L.phi);
+    g.dD2h = (const double*)(w + L.dD2h);
+    g.hkT = (const double*)(w + L.hkT);
+    g.dnu = (const double*)(w + L.dnu);
+    g.two_nu = (const double*)(w + L.two_nu);
+    g.nu_c = (const double*)(w + L.nu_c);
+    const R* geo = (const R*)(w + L.geo);
+    g.xidl = geo;
+    g.xhm = geo + (nx + 4);
+    g.xhp = geo + 2 * (nx + 4);
+    g.cxm = geo + 3 * (nx + 4);
+    g.cxp = g.cxm + nx;
+    g.chp = g.cxp + nx;
+    g.yidl = g.chp + nx;
+    g.yhm = g.yidl + (ny + 4);
+    g.yhp = g.yhm + (ny + 4);
+    g.cy = g.yhp + (ny + 4);
+    g.zs = (R*)(w + L.zs);
+    g.ws = (R*)(w + L.wsc);
+    g.force = (double*)(w + L.force);
+  }
+}
+
+// Cell centroids including two ghost layers, and the derived geometric
+// factors of the reconstruction and the conservative update.
+template <typename R>
+std::vector<R> build_geometry(const m1_config& c, double ctdt, std::vector<double>& xe,
+                              std::vector<double>& ye) {
+  int nx = c.nx, ny = c.ny;
+  bool cyl = c.geom == M1_CYL_RZ;
+  xe.resize(nx + 1);
+  ye.resize(ny + 1);
+  for (int i = 0; i <= nx; ++i) xe[i] = c.x0 + (c.x1 - c.x0) * i / nx;
+  for (int j = 0; j <= ny; ++j) ye[j] = c.y0 + (c.y1 - c.y0) * j / ny;
+  auto centR = [](double a, double b) { return (2.0 / 3.0) * (b * b * b - a * a * a) / (b * b - a * a); };
+  // centroids, index i + 2 for i in [-2, nx+1]
+  std::vector<double> xc(nx + 4), yc(ny + 4);
+  for (int i = 0; i < nx; ++i) xc[i + 2] = cyl ? centR(xe[i], xe[i + 1]) : 0.5 * (xe[i] + xe[i + 1]);
+  for (int j = 0; j < ny; ++j) yc[j + 2] = 0.5 * (ye[j] + ye[j + 1]);
+  double dxl = xe[1] - xe[0], dxr = xe[nx] - xe[nx - 1];
+  double dyl = ye[1] - ye[0], dyr = ye[ny] - ye[ny - 1];
+  for (int g = 1; g <= 2; ++g) {
+    if (c.bc[0] == M1_BC_REFLECT) xc[2 - g] = 2.0 * xe[0] - xc[1 + g];
+    else { double a = xe[0] - g * dxl, b = a + dxl; xc[2 - g] = cyl ? centR(a, b) : 0.5 * (a + b); }
+    if (c.bc[1] == M1_BC_REFLECT) xc[nx + 1 + g] = 2.0 * xe[nx] - xc[nx + 2 - g];
+    else { double a = xe[nx] + (g - 1) * dxr, b = a + dxr; xc[nx + 1 + g] = cyl ? centR(a, b) : 0.5 * (a + b); }
+    if (c.bc[2] == M1_BC_REFLECT) yc[2 - g] = 2.0 * ye[0] - yc[1 + g];
+    else yc[2 - g] = ye[0] - (g - 0.5) * dyl;
+    if (c.bc[3] == M1_BC_REFLECT) yc[ny + 1 + g] = 2.0 * ye[ny] - yc[ny + 2 - g];
+    else yc[ny + 1 + g] = ye[ny] + (g - 0.5) * dyr;
+  }
+  std::vector<R> geo(3 * (nx + 4) + 3 * nx + 3 * (ny + 4) + ny, R(0));
+  R* xidl = geo.data();
+  R* xhm = xidl + (nx + 4);
+  R* xhp = xhm + (nx + 4);
+  R* cxm = xhp + (nx + 4);
+  R* cxp = cxm + nx;
+  R* chp = cxp + nx;
+  R* yidl = chp + nx;
+  R* yhm = yidl + (ny + 4);
+  R* yhp = yhm + (ny + 4);
+  R* cy = yhp + (ny + 4);
+  auto xedge = [&](int i) { return i < 0 ? xe[0] + i * dxl : (i > nx ? xe[nx] + (i - nx) * dxr : xe[i]); };
+  auto yedge = [&](int j) { return j < 0 ? ye[0] + j * dyl : (j > ny ? ye[ny] + (j - ny) * dyr : ye[j]); };
+  for (int i = -1; i <= nx + 1; ++i) xidl[i + 2] = (R)(1.0 / (xc[i + 2] - xc[i + 1]));
+  for (int i = -1; i <= nx; ++i) {
+    xhm[i + 2] = (R)(xedge(i) - xc[i + 2]);
+    xhp[i + 2] = (R)(xedge(i + 1) - xc[i + 2]);
+  }
+  for (int i = 0; i < nx; ++i) {
+    double a = xe[i], b = xe[i + 1];
+    if (cyl) {
+      double den = b * b - a * a;
+      cxm[i] = (R)(ctdt * 2.0 * a / den);
+      cxp[i] = (R)(ctdt * 2.0 * b / den);
+      chp[i] = (R)(ctdt * 2.0 * (b - a) / den);
+    } else {
+      cxm[i] = cxp[i] = (R)(ctdt / (b - a));
+      chp[i] = R(0);
+    }
+  }
+  for (int j = -1; j <= ny + 1; ++j) yidl[j + 2] = (R)(1.0 / (yc[j + 2] - yc[j + 1]));
+  for (int j = -1; j <= ny; ++j) {
+    yhm[j + 2] = (R)(yedge(j) - yc[j + 2]);
+    yhp[j + 2] = (R)(yedge(j + 1) - yc[j + 2]);
+  }
+  for (int j = 0; j < ny; ++j) cy[j] = (R)(ctdt / (ye[j + 1] - ye[j]));
+  return geo;
+}
+
+int count_classes(const double* T, size_t n, std::vector<int32_t>* cls, std::vector<double>* vals) {
+  std::unordered_map<uint64_t, int32_t> m;
+  m.reserve(64);
+  if (cls) cls->resize(n);
+  for (size_t c = 0; c < n; ++c) {
+    uint64_t bits;
+    memcpy(&bits, &T[c], 8);
+    auto it = m.find(bits);
+    int32_t id;
+    if (it == m.end()) {
+      id = (int32_t)m.size();
+      m.emplace(bits, id);
+      if (vals) vals->push_back(T[c]);
+    } else {
+      id = it->second;
+    }
+    if (cls) (*cls)[c] = id;
+  }
+  return (int)m.size();
+}
+
+template <typename R>
+int init_typed(m1_handle* h, const m1_fields* f, const std::vector<std::vector<double>>& host,
+               const FreqGrid& g, const std::vector<int32_t>& cls,
+               const std::vector<double>& Tcls) {
+  const m1_config& c = h->cfg;
+  hipStream_t s = h->stream;
+  char* w = h->ws;
+  const Layout& L = h->L;
+  size_t nc = h->nc;
+  int nb = g.nb;
+  int nx = c.nx, ny = c.ny;
+  // temporary area for set-up: second state buffer + frequency scratch
+  char* tmp = w + L.state[1][0];
+  // (spans state buffer 1 and the two frequency-step scratch arrays only)
+  // inputs on the device
+  CellInputs in;
+  const double* dev[8];
+  if (f->on_device) {
+    const double* p[8] = {f->n_HI, f->T, f->u_x, f->u_y, f->alpha_abs, f->alpha_flux, f->p_d, f->emis};
+    for (int q = 0; q < 8; ++q) dev[q] = p[q];
+  } else {
+    for (int q = 0; q < 8; ++q) {
+      double* d = (double*)(tmp + (size_t)q * align_up(nc * sizeof(double)));
+      HIPCHK(hipMemcpyAsync(d, host[q].data(), nc * sizeof(double), hipMemcpyHostToDevice, s));
+      dev[q] = d;
+    }
+  }
+  char* tmp2 = tmp + (f->on_device ? 0 : 8 * align_up(nc * sizeof(double)));
+  in.n_HI = dev[0]; in.T = dev[1]; in.ux = dev[2]; in.uy = dev[3];
+  in.acabs = dev[4]; in.acF = dev[5]; in.pd = dev[6]; in.emis = dev[7];
+
+  // CFL time step and state scale from device reductions
+  int nblk = (int)std::min<size_t>((nc + 255) / 256, kResBlocks);
+  double* part = (double*)(w + L.partial);
+  HIPCHK(launch_init_reduce(in, nc, part, nblk, s));
+  std::vector<double> hp(3 * nblk);
+  HIPCHK(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double umax = 0, emax = 0, tmin = 1e300;
+  for (int b = 0; b < nblk; ++b) {
+    umax = std::max(umax, hp[3 * b]);
+    emax = std::max(emax, hp[3 * b + 1]);
+    tmin = std::min(tmin, hp[3 * b + 2]);
+  }
+  double dx = (c.x1 - c.x0) / c.nx, dy = (c.y1 - c.y0) / c.ny;
+  double dmin = std::min(dx, dy);
+  h->dt = c.cfl * 0.5 * (dmin / (c.c_tilde + umax));
+  double ctdt = c.c_tilde * h->dt;
+  // internal scale: first-step line-centre energy density of the brightest
+  // cell ~ 1 (exact power of two, so results are scaled exactly)
+  double v = ctdt * emax / (kC * kSqrtPi * doppler_width(tmin));
+  int e2 = 0;
+  if (v > 0 && isfinite(v)) e2 = -(int)floor(log2(v));
+  e2 = std::max(-900, std::min(900, e2));
+  h->e2 = e2;
+
+  // per-bin constants, classes, Dawson nodes, geometry
+  std::vector<double> two_nu(nb), nu_c(nb);
+  for (int k = 0; k < nb; ++k) { two_nu[k] = 2.0 / g.nuc[k]; nu_c[k] = g.nuc[k] / kC; }
+  HIPCHK(hipMemcpyAsync(w + L.dnu, g.dnu.data(), nb * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(w + L.two_nu, two_nu.data(), nb * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(w + L.nu_c, nu_c.data(), nb * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(w + L.edges, g.edges.data(), (nb + 1) * sizeof(double), hipMemcpyHostToDevice, s));
+  std::vector<double> nodes(kDawsonNodes);
+  dawson_nodes_host(nodes.data());
+  HIPCHK(hipMemcpyAsync(w + L.nodes, nodes.data(), kDawsonNodes * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(w + L.cls, cls.data(), nc * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  int64_t ncls = (int64_t)Tcls.size();
+  std::vector<double> dD2h(ncls), hkT(ncls), dD(ncls), av(ncls);
+  for (int64_t q = 0; q < ncls; ++q) {
+    double T = Tcls[q];
+    dD[q] = doppler_width(T);
+    dD2h[q] = 0.5 * dD[q] * dD[q];
+    hkT[q] = kHP / (kKB * T);
+    av[q] = 4.7e-4 / sqrt(T / 1.0e4);
+  }
+  HIPCHK(hipMemcpyAsync(w + L.dD2h, dD2h.data(), ncls * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(w + L.hkT, hkT.data(), ncls * sizeof(double), hipMemcpyHostToDevice, s));
+  double* d_dD = (double*)tmp2;
+  double* d_av = (double*)(tmp2 + align_up(ncls * sizeof(double)));
+  double* d_htmp = (double*)(tmp2 + 2 * align_up(ncls * sizeof(double)));
+  HIPCHK(hipMemcpyAsync(d_dD, dD.data(), ncls * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(d_av, av.data(), ncls * sizeof(double), hipMemcpyHostToDevice, s));
+  std::vector<double> xe, ye;
+  std::vector<R> geo = build_geometry<R>(c, ctdt, xe, ye);
+  HIPCHK(hipMemcpyAsync(w + L.geo, geo.data(), geo.size() * sizeof(R), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(w + L.xe, xe.data(), xe.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(w + L.ye, ye.data(), ye.size() * sizeof(double), hipMemcpyHostToDevice, s));
+
+  // bin-averaged Voigt profile and emission profile per class
+  HIPCHK(launch_class_profiles<R>(d_dD, d_av, ncls, (const double*)(w + L.edges),
+                                  (const double*)(w + L.dnu), nb, (const double*)(w + L.nodes),
+                                  d_htmp, (R*)(w + L.hbar), (R*)(w + L.phi), s));
+  // per-cell opacities and emission
+  HIPCHK(launch_cell_setup<R>(in, nc, dmin, c.fp64_tau, e2, (R*)(w + L.alpha), (R*)(w + L.acF),
+                              (R*)(w + L.acabs), (R*)(w + L.pda), (R*)(w + L.em),
+                              (uint8_t*)(w + L.island), s));
+  // velocity gradients and face velocities (face temp after the class temp)
+  double* vtmp = (double*)(tmp2 + 2 * align_up(ncls * sizeof(double)) +
+                           align_up((size_t)ncls * nb * sizeof(double)));
+  HIPCHK(launch_velocity<R>(in, nx, ny, c.geom, c.bc, (const double*)(w + L.xe),
+                            (const double*)(w + L.ye), vtmp, (R*)(w + L.ufx), (R*)(w + L.ufy),
+                            (R*)(w + L.grad), s));
+  HIPCHK(hipStreamSynchronize(s));
+  // E = F = 0 in both buffers, force = 0
+  for (int b = 0; b < 2; ++b)
+    for (int q = 0; q < 3; ++q)
+      HIPCHK(hipMemsetAsync(w + L.state[b][q], 0, (size_t)nb * nc * sizeof(R), s));
+  HIPCHK(hipMemsetAsync(w + L.force, 0, 4 * nc * sizeof(double), s));
+  HIPCHK(hipStreamSynchronize(s));
+  return M1_OK;
+}
+
+size_t init_temp_need(size_t nc, int nb, int64_t ncls, int nx, int ny, bool host_fields) {
+  size_t need = host_fields ? 8 * align_up(nc * sizeof(double)) : 0;
+  need += 2 * align_up(ncls * sizeof(double)) + align_up((size_t)ncls * nb * sizeof(double));
+  need += 2 * ((size_t)(nx + 1) * ny + (size_t)nx * (ny + 1)) * sizeof(double);
+  return need;
+}
+
+}  // namespace
+
+// =========================================================================
+extern "C" {
+
+const char* m1_last_error(void) { return g_err.c_str(); }
+
+int32_t m1_default_config(m1_config* c) {
+  if (!c) return fail(M1_EINVAL, "config is NULL");
+  memset(c, 0, sizeof *c);
+  c->geom = M1_CART2D;
+  c->nx = c->ny = 64;
+  c->x0 = 0; c->x1 = 1; c->y0 = 0; c->y1 = 1;
+  for (int s = 0; s < 4; ++s) c->bc[s] = M1_BC_VACUUM;
+  c->T_min = 30.0;
+  c->q = 1.1;
+  c->half_width = 1.0e5;
+  c->c_tilde = 0.01 * kC;
+  c->cfl = 0.4;
+  c->recoil = 1;
+  c->doppler = 1;
+  c->prec = M1_FP64;
+  c->fp64_tau = 1.0e6;
+  return M1_OK;
+}
+
+int32_t m1_num_bins(const m1_config* cfg, int32_t* n_nu) {
+  if (!n_nu) return fail(M1_EINVAL, "n_nu is NULL");
+  int nb = 0;
+  int st = validate_config(cfg, &nb);
+  if (st) return st;
+  *n_nu = nb;
+  return M1_OK;
+}
+
+int32_t m1_count_temperature_classes(const double* T, int64_t n, int64_t* n_classes) {
+  if (!T || n <= 0 || !n_classes) return fail(M1_EINVAL, "bad arguments");
+  *n_classes = count_classes(T, (size_t)n, nullptr, nullptr);
+  return M1_OK;
+}
+
+int32_t m1_workspace_bytes(const m1_config* cfg, int64_t ncls, size_t* bytes) {
+  if (!bytes) return fail(M1_EINVAL, "bytes is NULL");
+  int nb = 0;
+  int st = validate_config(cfg, &nb);
+  if (st) return st;
+  size_t nc = (size_t)cfg->nx * cfg->ny;
+  if (ncls <= 0 || (size_t)ncls > nc) ncls = (int64_t)nc;
+  size_t rs = cfg->prec == M1_FP32 ? 4 : 8;
+  Layout L = make_layout(cfg->nx, cfg->ny, nb, ncls, rs);
+  *bytes = L.total;
+  return M1_OK;
+}
+
+int32_t m1_init(const m1_config* cfg, const m1_fields* f, void* d_ws, size_t ws_bytes,
+                void* stream, m1_handle** out) {
+  if (!out) return fail(M1_EINVAL, "out is NULL");
+  *out = nullptr;
+  int nb = 0;
+  int st = validate_config(cfg, &nb);
+  if (st) return st;
+  if (!f) return fail(M1_EINVAL, "fields is NULL");
+  const double* p[8] = {f->n_HI, f->T, f->u_x, f->u_y, f->alpha_abs, f->alpha_flux, f->p_d, f->emis};
+  const char* names[8] = {"n_HI", "T", "u_x", "u_y", "alpha_abs", "alpha_flux", "p_d", "emis"};
+  for (int q = 0; q < 8; ++q)
+    if (!p[q]) return fail(M1_EINVAL, "field %s is NULL", names[q]);
+  if (!d_ws) return fail(M1_EINVAL, "workspace is NULL");
+  if (((uintptr_t)d_ws) & 255) return fail(M1_EINVAL, "workspace must be 256-byte aligned");
+  size_t nc = (size_t)cfg->nx * cfg->ny;
+  hipStream_t s = (hipStream_t)stream;
+  // host view of the fields for validation and temperature classes
+  std::vector<std::vector<double>> host(8);
+  for (int q = 0; q < 8; ++q) {
+    host[q].resize(nc);
+    if (f->on_device) {
+      HIPCHK(hipMemcpyAsync(host[q].data(), p[q], nc * sizeof(double), hipMemcpyDeviceToHost, s));
+    } else {
+      memcpy(host[q].data(), p[q], nc * sizeof(double));
+    }
+  }
+  if (f->on_device) HIPCHK(hipStreamSynchronize(s));
+  for (int q = 0; q < 8; ++q) {
+    const std::vector<double>& v = host[q];
+    bool signed_ok = (q == 2 || q == 3);
+    for (size_t c = 0; c < nc; ++c) {
+      if (!isfinite(v[c])) return fail(M1_EINVAL, "field %s has a non-finite value at %zu", names[q], c);
+      if (!signed_ok && v[c] < 0) return fail(M1_EINVAL, "field %s is negative at %zu", names[q], c);
+      if (q == 1 && !(v[c] > 0)) return fail(M1_EINVAL, "field T must be > 0 (cell %zu)", c);
+      if (signed_ok && fabs(v[c]) >= kC) return fail(M1_EINVAL, "field %s reaches c at cell %zu", names[q], c);
+    }
+  }
+  std::vector<int32_t> cls;
+  std::vector<double> Tcls;
+  count_classes(host[1].data(), nc, &cls, &Tcls);
+  int64_t ncls = (int64_t)Tcls.size();
+  size_t rs = cfg->prec == M1_FP32 ? 4 : 8;
+  Layout L = make_layout(cfg->nx, cfg->ny, nb, ncls, rs);
+  if (ws_bytes < L.total)
+    return fail(M1_ENOMEM, "workspace of %zu bytes < %zu needed (%lld temperature classes)",
+                ws_bytes, L.total, (long long)ncls);
+  size_t tmp_cap = L.force - L.state[1][0];
+  if (init_temp_need(nc, nb, ncls, cfg->nx, cfg->ny, !f->on_device) > tmp_cap)
+    return fail(M1_EUNSUPPORTED, "set-up scratch does not fit the workspace layout");
+  m1_handle* h = new m1_handle();
+  h->cfg = *cfg;
+  h->nb = nb;
+  h->ncls = ncls;
+  h->nc = nc;
+  h->stream = s;
+  h->ws = (char*)d_ws;
+  h->L = L;
+  FreqGrid g;
+  build_grid(*cfg, g);
+  if (cfg->prec == M1_FP32) st = init_typed<float>(h, f, host, g, cls, Tcls);
+  else st = init_typed<double>(h, f, host, g, cls, Tcls);
+  if (st) { delete h; return st; }
+  fill_args<float>(h, h->af);
+  fill_args<double>(h, h->ad);
+  *out = h;
+  return M1_OK;
+}
+
+int32_t m1_get_info(const m1_handle* h, double* dt, int32_t* n_nu, int32_t* prec, int64_t* ncell,
+                    int32_t* scale_exp2) {
+  if (!h) return fail(M1_EINVAL, "handle is NULL");
+  if (dt) *dt = h->dt;
+  if (n_nu) *n_nu = h->nb;
+  if (prec) *prec = h->cfg.prec;
+  if (ncell) *ncell = (int64_t)h->nc;
+  if (scale_exp2) *scale_exp2 = h->e2;
+  return M1_OK;
+}
+
+static int enqueue_step(m1_handle* h, hipStream_t s) {
+  hipError_t e = h->cfg.prec == M1_FP32 ? launch_step<float>(h->af[h->cur], s)
+                                        : launch_step<double>(h->ad[h->cur], s);
+  if (e != hipSuccess) {
+    h->broken = true;
+    return fail(M1_EDEVICE, "step launch failed: %s", hipGetErrorString(e));
+  }
+  h->cur ^= 1;
+  h->steps += 1;
+  h->t += h->dt;
+  return M1_OK;
+}
+
+int32_t m1_step(m1_handle* h, int32_t nsteps, double* t_now) {
+  if (!h) return fail(M1_EINVAL, "handle is NULL");
+  if (h->broken) return fail(M1_ESTATE, "handle had a device error");
+  if (nsteps < 0) return fail(M1_EINVAL, "nsteps < 0");
+  for (int n = 0; n < nsteps; ++n) {
+    int st = enqueue_step(h, h->stream);
+    if (st) return st;
+  }
+  if (t_now) *t_now = h->t;
+  return M1_OK;
+}
+
+int32_t m1_step_profiled(m1_handle* h, int32_t nsteps, double* ms) {
+  if (!h || !ms) return fail(M1_EINVAL, "bad arguments");
+  if (h->broken) return fail(M1_ESTATE, "handle had a device error");
+  if (nsteps < 1 || nsteps > 4096) return fail(M1_EINVAL, "need 1 <= nsteps <= 4096");
+  std::vector<hipEvent_t> ev(2 * nsteps + 1);
+  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  int st = M1_OK;
+  HIPCHK(hipEventRecord(ev[0], h->stream));
+  for (int n = 0; n < nsteps && !st; ++n) {
+    hipError_t e = h->cfg.prec == M1_FP32 ? launch_advect<float>(h->af[h->cur], h->stream)
+                                          : launch_advect<double>(h->ad[h->cur], h->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * n + 1], h->stream);
+    if (e == hipSuccess)
+      e = h->cfg.prec == M1_FP32 ? launch_freq<float>(h->af[h->cur], h->stream)
+                                 : launch_freq<double>(h->ad[h->cur], h->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * n + 2], h->stream);
+    if (e != hipSuccess) { st = fail(M1_EDEVICE, "profiled step: %s", hipGetErrorString(e)); break; }
+    h->cur ^= 1;
+    h->steps += 1;
+    h->t += h->dt;
+  }
+  if (!st) {
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) st = fail(M1_EDEVICE, "profiled step sync: %s", hipGetErrorString(e));
+  }
+  ms[0] = ms[1] = 0.0;
+  for (int n = 0; n < nsteps && !st; ++n) {
+    float a = 0, b = 0;
+    (void)hipEventElapsedTime(&a, ev[2 * n], ev[2 * n + 1]);
+    (void)hipEventElapsedTime(&b, ev[2 * n + 1], ev[2 * n + 2]);
+    ms[0] += a;
+    ms[1] += b;
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  return st;
+}
+
+int32_t m1_step_batched(m1_handle* const* hs, int32_t n, int32_t nsteps) {
+  if (!hs || n <= 0 || nsteps < 0) return fail(M1_EINVAL, "bad arguments");
+  for (int q = 0; q < n; ++q) {
+    if (!hs[q]) return fail(M1_EINVAL, "handle %d is NULL", q);
+    if (hs[q]->broken) return fail(M1_ESTATE, "handle %d had a device error", q);
+    if (hs[q]->cfg.prec != hs[0]->cfg.prec) return fail(M1_EINVAL, "mixed precisions");
+  }
+  hipStream_t s = hs[0]->stream;
+  for (int t = 0; t < nsteps; ++t)
+    for (int q = 0; q < n; ++q) {
+      int st = enqueue_step(hs[q], s);
+      if (st) return st;
+    }
+  return M1_OK;
+}
+
+int32_t m1_sync(m1_handle* h) {
+  if (!h) return fail(M1_EINVAL, "handle is NULL");
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    h->broken = true;
+    return fail(M1_EDEVICE, "stream error: %s", hipGetErrorString(e));
+  }
+  return M1_OK;
+}
+
+int32_t m1_residual(m1_handle* h, double* resid) {
+  if (!h || !resid) return fail(M1_EINVAL, "bad arguments");
+  if (h->steps == 0) { *resid = INFINITY; return M1_OK; }
+  size_t n = (size_t)h->nb * h->nc;
+  int nblk = (int)std::min<size_t>((n + 255) / 256, kResBlocks);
+  double* part = (double*)(h->ws + h->L.partial);
+  double* res = (double*)(h->ws + h->L.result);
+  const char* Eold = h->ws + h->L.state[h->cur ^ 1][0];
+  const char* Enew = h->ws + h->L.state[h->cur][0];
+  hipError_t e = h->cfg.prec == M1_FP32
+      ? launch_residual<float>((const float*)Eold, (const float*)Enew, n, part, nblk, res, h->stream)
+      : launch_residual<double>((const double*)Eold, (const double*)Enew, n, part, nblk, res, h->stream);
+  if (e != hipSuccess) return fail(M1_EDEVICE, "residual launch: %s", hipGetErrorString(e));
+  double r2[2];
+  HIPCHK(hipMemcpyAsync(r2, res, sizeof r2, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  *resid = r2[1] > 0 ? sqrt(r2[0] / r2[1]) : (r2[0] == 0 ? 0.0 : INFINITY);
+  return M1_OK;
+}
+
+int32_t m1_solve_steady(m1_handle* h, double rel_tol, int64_t max_steps, int32_t check_every,
+                        int64_t* steps_done, double* resid) {
+  if (!h) return fail(M1_EINVAL, "handle is NULL");
+  if (!(rel_tol > 0) || max_steps < 1 || check_every < 1) return fail(M1_EINVAL, "bad arguments");
+  int64_t done = 0;
+  double r = INFINITY;
+  int st = M1_OK;
+  while (done < max_steps) {
+    int32_t n = (int32_t)std::min<int64_t>(check_every, max_steps - done);
+    st = m1_step(h, n, nullptr);
+    if (st) break;
+    done += n;
+    st = m1_residual(h, &r);
+    if (st) break;
+    if (r < rel_tol) break;
+  }
+  if (steps_done) *steps_done = done;
+  if (resid) *resid = r;
+  if (st) return st;
+  if (!(r < rel_tol)) return fail(M1_ENOTCONV, "residual %.3e after %lld steps", r, (long long)done);
+  return M1_OK;
+}
+
+int32_t m1_get_state(m1_handle* h, void* d_E, void* d_Fx, void* d_Fy) {
+  if (!h) return fail(M1_EINVAL, "handle is NULL");
+  size_t n = (size_t)h->nb * h->nc;
+  void* dst[3] = {d_E, d_Fx, d_Fy};
+  for (int q = 0; q < 3; ++q) {
+    if (!dst[q]) continue;
+    const char* src = h->ws + h->L.state[h->cur][q];
+    hipError_t e = h->cfg.prec == M1_FP32
+        ? launch_scale_copy<float>((const float*)src, (float*)dst[q], n, -h->e2, h->stream)
+        : launch_scale_copy<double>((const double*)src, (double*)dst[q], n, -h->e2, h->stream);
+    if (e != hipSuccess) return fail(M1_EDEVICE, "copy launch: %s", hipGetErrorString(e));
+  }
+  return m1_sync(h);
+}
+
+int32_t m1_set_state(m1_handle* h, const void* d_E, const void* d_Fx, const void* d_Fy) {
+  if (!h || !d_E || !d_Fx || !d_Fy) return fail(M1_EINVAL, "bad arguments");
+  size_t n = (size_t)h->nb * h->nc;
+  const void* src[3] = {d_E, d_Fx, d_Fy};
+  for (int q = 0; q < 3; ++q) {
+    char* dst = h->ws + h->L.state[h->cur][q];
+    hipError_t e = h->cfg.prec == M1_FP32
+        ? launch_scale_copy<float>((const float*)src[q], (float*)dst, n, h->e2, h->stream)
+        : launch_scale_copy<double>((const double*)src[q], (double*)dst, n, h->e2, h->stream);
+    if (e != hipSuccess) return fail(M1_EDEVICE, "copy launch: %s", hipGetErrorString(e));
+  }
+  return M1_OK;
+}
+
+int32_t m1_force(m1_handle* h, double* fx, double* fy, double* gx, double* gy) {
+  if (!h) return fail(M1_EINVAL, "handle is NULL");
+  hipError_t e = launch_force_out((const double*)(h->ws + h->L.force), h->nc, -h->e2, fx, fy, gx,
+                                  gy, h->stream);
+  if (e != hipSuccess) return fail(M1_EDEVICE, "force launch: %s", hipGetErrorString(e));
+  return M1_OK;
+}
+
+int32_t m1_free(m1_handle* h) {
+  delete h;
+  return M1_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,57 @@
+// Launch wrappers of the device kernels (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <algorithm>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "m1_device.h"
+
+namespace m1 {
+
+// ---- hot path (m1_step_kernels.hip)
+template <typename R>
+hipError_t launch_step(const GridArgs<R>& a, hipStream_t s);
+template <typename R>
+hipError_t launch_advect(const GridArgs<R>& a, hipStream_t s);
+template <typename R>
+hipError_t launch_freq(const GridArgs<R>& a, hipStream_t s);
+template <typename R>
+hipError_t launch_residual(const R* E0, const R* E1, size_t n, double* partial, int nblk,
+                           double* out, hipStream_t s);
+template <typename R>
+hipError_t launch_scale_copy(const R* src, R* dst, size_t n, int e2, hipStream_t s);
+hipError_t launch_force_out(const double* force, size_t nc, int e2, double* fx, double* fy,
+                            double* gx, double* gy, hipStream_t s);
+
+// ---- set-up (m1_setup_kernels.hip)
+// Bin-averaged Voigt profile of every temperature class (FP64):
+// hbar[cls][k], emission profile phi = hbar / sum_k dnu_k hbar_k.
+template <typename R>
+hipError_t launch_class_profiles(const double* dnuD, const double* av, int64_t ncls,
+                                 const double* dnu_edges, const double* dnu, int nb,
+                                 const double* dawson_nodes, double* tmp, R* hbar, R* phi,
+                                 hipStream_t s);
+
+struct CellInputs {
+  const double *n_HI, *T, *ux, *uy, *acabs, *acF, *pd, *emis;
+};
+
+// Per-cell opacities and emission (scaled by 2^e2 / c), island flags.
+template <typename R>
+hipError_t launch_cell_setup(const CellInputs& in, size_t nc, double dmin, double fp64_tau,
+                             int e2, R* alpha, R* acF, R* acabs, R* pda, R* em,
+                             uint8_t* island, hipStream_t s);
+
+// Face-normal and tangential mean velocities of x- and y-faces (FP64 temp),
+// then cell velocity gradients and face-normal velocities in R.
+template <typename R>
+hipError_t launch_velocity(const CellInputs& in, int nx, int ny, int geom, const int* bc,
+                           const double* xe, const double* ye, double* tmp, R* ufx, R* ufy,
+                           R* grad, hipStream_t s);
+
+// Block partials of max |u|, max emis, min T (for dt and the state scale).
+hipError_t launch_init_reduce(const CellInputs& in, size_t nc, double* partial, int nblk,
+                              hipStream_t s);
+
+}  // namespace m1

@@ -1,0 +1,261 @@
+"""Python binding of libm1lya.so (argument marshalling only).
+
+Every step of the method runs in the HIP library; PyTorch only provides the
+device workspace, the output buffers and the stream.  Importing this module
+without a built library, or using it without a GPU, raises: there is no CPU
+fallback.
+
+Names follow include/m1lya.h: m1_init, m1_step, m1_force, m1_solve_steady,
+m1_residual, m1_get_state, m1_set_state, m1_step_batched, ...  The class
+`M1Grid` wraps one handle for a problem dict built by `inputs`.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libm1lya.so")
+
+M1_OK, M1_EINVAL, M1_ENOMEM, M1_EDEVICE, M1_ENOTCONV, M1_ESTATE, M1_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+M1_CART2D, M1_CYL_RZ = 0, 1
+M1_BC_VACUUM, M1_BC_REFLECT = 0, 1
+M1_FP64, M1_FP32 = 0, 1
+
+
+class M1Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"m1 error {code}: {msg}")
+        self.code = code
+
+
+class m1_config(ctypes.Structure):
+    _fields_ = [("geom", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("x0", ctypes.c_double), ("x1", ctypes.c_double), ("y0", ctypes.c_double),
+                ("y1", ctypes.c_double), ("bc", ctypes.c_int32 * 4), ("T_min", ctypes.c_double),
+                ("q", ctypes.c_double), ("half_width", ctypes.c_double),
+                ("c_tilde", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("recoil", ctypes.c_int32), ("doppler", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("fp64_tau", ctypes.c_double)]
+
+
+class m1_fields(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in
+                ("n_HI", "T", "u_x", "u_y", "alpha_abs", "alpha_flux", "p_d", "emis")] + \
+               [("on_device", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libm1lya.so; raises if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D, VP = ctypes.POINTER, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+    sig = {
+        "m1_default_config": (I32, [P(m1_config)]),
+        "m1_num_bins": (I32, [P(m1_config), P(I32)]),
+        "m1_workspace_bytes": (I32, [P(m1_config), I64, P(ctypes.c_size_t)]),
+        "m1_count_temperature_classes": (I32, [VP, I64, P(I64)]),
+        "m1_init": (I32, [P(m1_config), P(m1_fields), VP, ctypes.c_size_t, VP, P(VP)]),
+        "m1_step": (I32, [VP, I32, P(D)]),
+        "m1_force": (I32, [VP, VP, VP, VP, VP]),
+        "m1_solve_steady": (I32, [VP, D, I64, I32, P(I64), P(D)]),
+        "m1_residual": (I32, [VP, P(D)]),
+        "m1_get_state": (I32, [VP, VP, VP, VP]),
+        "m1_set_state": (I32, [VP, VP, VP, VP]),
+        "m1_get_info": (I32, [VP, P(D), P(I32), P(I32), P(I64), P(I32)]),
+        "m1_step_batched": (I32, [P(VP), I32, I32]),
+        "m1_step_profiled": (I32, [VP, I32, P(D)]),
+        "m1_sync": (I32, [VP]),
+        "m1_free": (I32, [VP]),
+        "m1_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    return ["m1_default_config", "m1_num_bins", "m1_workspace_bytes",
+            "m1_count_temperature_classes", "m1_init", "m1_step", "m1_force",
+            "m1_solve_steady", "m1_residual", "m1_get_state", "m1_set_state", "m1_get_info",
+            "m1_step_batched", "m1_step_profiled", "m1_sync", "m1_free", "m1_last_error"]
+
+
+def check(code):
+    if code != M1_OK:
+        raise M1Error(code, lib().m1_last_error().decode())
+    return code
+
+
+# ----------------------------------------------------------------- config
+BC = {"vacuum": M1_BC_VACUUM, "reflect": M1_BC_REFLECT}
+
+
+def make_config(p, prec="fp64", fp64_tau=1.0e6):
+    c = m1_config()
+    check(lib().m1_default_config(ctypes.byref(c)))
+    c.geom = M1_CYL_RZ if p["geom"] == "cyl" else M1_CART2D
+    c.nx, c.ny = int(p["nx"]), int(p["ny"])
+    c.x0, c.x1, c.y0, c.y1 = float(p["x0"]), float(p["x1"]), float(p["y0"]), float(p["y1"])
+    for s in range(4):
+        c.bc[s] = BC[p["bc"][s]]
+    c.T_min, c.q, c.half_width = float(p["T_min"]), float(p["q"]), float(p["half_width"])
+    c.c_tilde, c.cfl = float(p["c_tilde"]), float(p["cfl"])
+    c.recoil, c.doppler = int(p.get("recoil", 1)), int(p.get("doppler", 1))
+    c.prec = M1_FP32 if prec == "fp32" else M1_FP64
+    c.fp64_tau = float(fp64_tau)
+    return c
+
+
+def num_bins(cfg):
+    n = ctypes.c_int32()
+    check(lib().m1_num_bins(ctypes.byref(cfg), ctypes.byref(n)))
+    return n.value
+
+
+def workspace_bytes(cfg, n_classes=0):
+    b = ctypes.c_size_t()
+    check(lib().m1_workspace_bytes(ctypes.byref(cfg), int(n_classes), ctypes.byref(b)))
+    return b.value
+
+
+def count_temperature_classes(T):
+    T = np.ascontiguousarray(T, dtype=np.float64).ravel()
+    n = ctypes.c_int64()
+    check(lib().m1_count_temperature_classes(T.ctypes.data, T.size, ctypes.byref(n)))
+    return n.value
+
+
+FIELD_ORDER = ("n_HI", "T", "u_x", "u_y", "alpha_abs", "alpha_flux", "p_d", "emis")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU: the M1 library runs on the device only")
+    return torch
+
+
+class M1Grid:
+    """One problem on the GPU: workspace, handle and outputs.
+
+    p: problem dict (see inputs.py); prec: "fp64" or "fp32"."""
+
+    def __init__(self, p, prec="fp64", fp64_tau=1.0e6, stream=None, workspace=None):
+        torch = _torch()
+        self.p = p
+        self.prec = prec
+        self.cfg = make_config(p, prec, fp64_tau)
+        f = p["fields"]
+        host = [np.ascontiguousarray(f[n], dtype=np.float64).ravel() for n in FIELD_ORDER]
+        self._host = host
+        self.ncls = count_temperature_classes(host[1])
+        self.ws_bytes = workspace_bytes(self.cfg, self.ncls)
+        self.nb = num_bins(self.cfg)
+        self.nx, self.ny = self.cfg.nx, self.cfg.ny
+        self.ncell = self.nx * self.ny
+        if workspace is None:
+            workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device="cuda")
+        self.ws = workspace
+        base = workspace.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        if self._ws_ptr + self.ws_bytes > base + workspace.numel():
+            raise ValueError("workspace tensor too small")
+        fl = m1_fields()
+        for n, a in zip(FIELD_ORDER, host):
+            setattr(fl, n, a.ctypes.data)
+        fl.on_device = 0
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        check(lib().m1_init(ctypes.byref(self.cfg), ctypes.byref(fl), self._ws_ptr,
+                            self.ws_bytes, self.stream.cuda_stream, ctypes.byref(h)))
+        self.h = h
+        dt, nnu, pr, nc, e2 = (ctypes.c_double(), ctypes.c_int32(), ctypes.c_int32(),
+                               ctypes.c_int64(), ctypes.c_int32())
+        check(lib().m1_get_info(h, ctypes.byref(dt), ctypes.byref(nnu), ctypes.byref(pr),
+                                ctypes.byref(nc), ctypes.byref(e2)))
+        self.dt, self.scale_exp2 = dt.value, e2.value
+        self.dtype = torch.float32 if prec == "fp32" else torch.float64
+        self.t = 0.0
+
+    # -- stepping
+    def step(self, n=1):
+        t = ctypes.c_double()
+        check(lib().m1_step(self.h, int(n), ctypes.byref(t)))
+        self.t = t.value
+        return self
+
+    def step_profiled(self, n):
+        """Steps n times; returns summed device ms of (advection, frequency) kernels."""
+        ms = (ctypes.c_double * 2)()
+        check(lib().m1_step_profiled(self.h, int(n), ms))
+        self.t += n * self.dt
+        return ms[0], ms[1]
+
+    def solve_steady(self, rel_tol=1e-6, max_steps=100000, check_every=16):
+        done, r = ctypes.c_int64(), ctypes.c_double()
+        code = lib().m1_solve_steady(self.h, float(rel_tol), int(max_steps), int(check_every),
+                                     ctypes.byref(done), ctypes.byref(r))
+        if code not in (M1_OK, M1_ENOTCONV):
+            check(code)
+        return code == M1_OK, done.value, r.value
+
+    def residual(self):
+        r = ctypes.c_double()
+        check(lib().m1_residual(self.h, ctypes.byref(r)))
+        return r.value
+
+    def sync(self):
+        check(lib().m1_sync(self.h))
+
+    # -- outputs (torch tensors on the device)
+    def state(self):
+        torch = _torch()
+        shape = (self.nb, self.ny, self.nx)
+        E = torch.empty(shape, dtype=self.dtype, device="cuda")
+        Fx = torch.empty_like(E)
+        Fy = torch.empty_like(E)
+        check(lib().m1_get_state(self.h, E.data_ptr(), Fx.data_ptr(), Fy.data_ptr()))
+        return E, Fx, Fy
+
+    def set_state(self, E, Fx, Fy):
+        torch = _torch()
+        conv = lambda a: torch.as_tensor(a, dtype=self.dtype, device="cuda").contiguous()
+        self._set = (conv(E), conv(Fx), conv(Fy))
+        check(lib().m1_set_state(self.h, *[t.data_ptr() for t in self._set]))
+
+    def force(self, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty((4, self.ny, self.nx), dtype=torch.float64, device="cuda")
+        check(lib().m1_force(self.h, out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(),
+                             out[3].data_ptr()))
+        return out
+
+    def free(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().m1_free(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def step_batched(grids, nsteps):
+    arr = (ctypes.c_void_p * len(grids))(*[g.h.value for g in grids])
+    check(lib().m1_step_batched(arr, len(grids), int(nsteps)))

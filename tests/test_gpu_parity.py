@@ -1,0 +1,148 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle.
+
+Tolerances (relative L2 over all cells and bins, per result):
+  FP64 path : 1e-12 on E, F and the force (rounding-order differences only);
+  FP32 path : 1e-5 on E and F, 1e-4 on the force (the stated target).
+Every case prints its name before touching the GPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import m1_oracle as M
+from paper_2606_02711_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(a - b)) / nb if nb > 0 else float(np.linalg.norm(a))
+
+
+def run_gpu(p, steps, prec):
+    from paper_2606_02711_amd import m1
+    print(f"[gpu] {p['geom']} {p['nx']}x{p['ny']} steps={steps} prec={prec}", flush=True)
+    g = m1.M1Grid(p, prec=prec)
+    g.step(steps)
+    E, Fx, Fy = [t.double().cpu().numpy() for t in g.state()]
+    f = g.force().cpu().numpy()
+    return g, E, Fx, Fy, f
+
+
+def compare(p, steps, prec, tolE, tolF, oracle=None):
+    g, E, Fx, Fy, f = run_gpu(p, steps, prec)
+    o = oracle if oracle is not None else M.run(p, steps=steps)
+    assert g.dt == pytest.approx(o.dt, rel=1e-14)
+    errs = dict(E=rel(E, o.E), Fx=rel(Fx, o.Fx), Fy=rel(Fy, o.Fy), force=rel(f, o.force))
+    print("   rel-L2", errs, flush=True)
+    assert errs["E"] <= tolE and errs["Fx"] <= tolE and errs["Fy"] <= tolE, errs
+    assert errs["force"] <= tolF, errs
+    assert np.all(np.isfinite(E)) and E.min() >= 0
+    return g, errs
+
+
+CASES = [("cart", 13, 9, 1, 1e3), ("cyl", 12, 10, 2, 1e3), ("cart", 70, 5, 3, 1e5),
+         ("cyl", 4, 4, 4, 1e5), ("cyl", 67, 33, 5, 1e5)]
+
+
+@pytest.mark.parametrize("geom,nx,ny,seed,hw", CASES)
+def test_fp64_parity_random_heterogeneous(geom, nx, ny, seed, hw):
+    p = inputs.random_small(geom, nx, ny, seed, half_width=hw, log_nHI=(-4.0, 1.0))
+    compare(p, 8, "fp64", 1e-12, 1e-12)
+
+
+@pytest.mark.parametrize("geom,nx,ny,seed,hw", CASES)
+def test_fp32_parity_random_heterogeneous(geom, nx, ny, seed, hw):
+    p = inputs.random_small(geom, nx, ny, seed, half_width=hw, log_nHI=(-4.0, 1.0))
+    compare(p, 8, "fp32", 1e-5, 1e-4)
+
+
+def test_reflecting_box_and_line_off_cells():
+    p = inputs.random_small("cart", 16, 12, 9, half_width=1e3, bc=("reflect",) * 4)
+    p["fields"]["n_HI"][2:5, 3:9] = 0.0            # cells without line opacity
+    compare(p, 6, "fp64", 1e-12, 1e-12)
+
+
+@pytest.fixture(scope="module")
+def config1_oracle():
+    p = inputs.config1()
+    return p, M.run(p)
+
+
+def test_config1_fp64_full_run(config1_oracle):
+    p, o = config1_oracle
+    compare(p, p["steps"], "fp64", 1e-12, 1e-12, oracle=o)
+
+
+def test_config1_fp32_full_run(config1_oracle):
+    p, o = config1_oracle
+    compare(p, p["steps"], "fp32", 1e-5, 1e-4, oracle=o)
+
+
+@pytest.fixture(scope="module")
+def config2_oracle():
+    p = inputs.config2()
+    print("[oracle] config 2, 2 steps", flush=True)
+    return p, M.run(p, steps=2)
+
+
+def test_config2_full_size_fp64(config2_oracle):
+    p, o = config2_oracle
+    compare(p, 2, "fp64", 1e-12, 1e-12, oracle=o)
+
+
+def test_config2_full_size_fp32(config2_oracle):
+    p, o = config2_oracle
+    compare(p, 2, "fp32", 1e-5, 1e-4, oracle=o)
+
+
+def test_linearity_bitwise_gpu():
+    p = inputs.random_small("cyl", 20, 16, 11, half_width=1e3)
+    _, E1, Fx1, _, f1 = run_gpu(p, 5, "fp32")
+    p["fields"]["emis"] = p["fields"]["emis"] * 2.0 ** 37
+    _, E2, Fx2, _, f2 = run_gpu(p, 5, "fp32")
+    assert np.array_equal(E2, E1 * 2.0 ** 37)
+    assert np.array_equal(Fx2, Fx1 * 2.0 ** 37)
+    assert np.array_equal(f2, f1 * 2.0 ** 37)
+
+
+def test_batched_equals_alone_bitwise():
+    from paper_2606_02711_amd import m1
+    ps = [inputs.random_small(g, n, n + 3, s, half_width=1e3)
+          for g, n, s in (("cart", 9, 1), ("cyl", 17, 2), ("cart", 33, 3))]
+    alone = []
+    for p in ps:
+        _, E, Fx, Fy, f = run_gpu(p, 6, "fp32")
+        alone.append((E, Fx, Fy, f))
+    print("[gpu] batched", flush=True)
+    gs = [m1.M1Grid(p, prec="fp32") for p in ps]
+    m1.step_batched(gs, 6)
+    for g, (E, Fx, Fy, f) in zip(gs, alone):
+        Eb, Fxb, Fyb = [t.double().cpu().numpy() for t in g.state()]
+        assert np.array_equal(Eb, E) and np.array_equal(Fxb, Fx) and np.array_equal(Fyb, Fy)
+        assert np.array_equal(g.force().cpu().numpy(), f)
+
+
+def test_solve_steady_matches_oracle():
+    p = inputs.random_small("cart", 10, 10, 21, half_width=10.0, log_nHI=(-5.0, -3.0))
+    p["c_tilde"] = 0.3 * inputs.C_LIGHT
+    from paper_2606_02711_amd import m1
+    print("[gpu] solve_steady", flush=True)
+    g = m1.M1Grid(p, prec="fp64")
+    ok, steps, r = g.solve_steady(rel_tol=1e-9, max_steps=20000, check_every=16)
+    o = M.Oracle(p)
+    ok2, steps2, r2 = o.solve_steady(rel_tol=1e-9, max_steps=20000, check_every=16)
+    assert ok and ok2 and steps == steps2
+    E = g.state()[0].cpu().numpy()
+    assert rel(E, o.E) < 1e-10
+    assert r == pytest.approx(r2, rel=1e-6)
+
+
+def test_solve_steady_reports_not_converged():
+    from paper_2606_02711_amd import m1
+    p = inputs.random_small("cyl", 8, 8, 3, half_width=1e3)
+    g = m1.M1Grid(p, prec="fp32")
+    ok, steps, r = g.solve_steady(rel_tol=1e-12, max_steps=5, check_every=2)
+    assert not ok and steps == 5 and r > 1e-12
