@@ -54,11 +54,11 @@ def measured_traffic(kernel, prec):
     return rec.get("bytes_per_launch") if rec else None
 
 
-def run_path(p, prec, steps, warmup):
+def run_path(p, prec, steps, warmup, fp64_tau=0.0):
     import torch
     from paper_2606_02711_amd import m1
-    log(f"[bench] init {prec}")
-    g = m1.M1Grid(p, prec=prec)
+    log(f"[bench] init {prec} fp64_tau={fp64_tau}")
+    g = m1.M1Grid(p, prec=prec, fp64_tau=fp64_tau)
     g.step(warmup)
     g.sync()
     torch.cuda.synchronize()
@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--fp64-tau", type=float, default=0.0,
+                    help="FP32 path: cells above this line-centre depth use a double frequency step")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -114,7 +116,7 @@ def main():
         sys.exit(2)
     from paper_2606_02711_amd import inputs
     p = inputs.config2()
-    r32 = run_path(p, "fp32", args.steps, args.warmup)
+    r32 = run_path(p, "fp32", args.steps, args.warmup, args.fp64_tau)
     r64 = None if args.no_fp64 else run_path(p, "fp64", args.steps, args.warmup)
     dom = "advect_source" if r32["ms_advect"] >= r32["ms_freq"] else "freq_step"
     dom_ms = (r32["ms_advect"] if dom == "advect_source" else r32["ms_freq"]) / args.steps

@@ -58,10 +58,14 @@ typedef enum {
 typedef enum { M1_CART2D = 0, M1_CYL_RZ = 1 } m1_geom;
 typedef enum { M1_BC_VACUUM = 0, M1_BC_REFLECT = 1 } m1_bc;
 /* State storage and arithmetic.  M1_FP64: everything in double.  M1_FP32:
- * state, opacities and transport arithmetic in float; frequency-step
- * coefficients and elimination in float with a subtraction-free scheme, or in
- * double for cells whose line-centre optical depth exceeds fp64_tau; force
- * sums and residual norms in double. */
+ * state, opacities and transport arithmetic in float; the frequency step
+ * (coefficients and subtraction-free elimination) in double for cells whose
+ * line-centre optical depth exceeds fp64_tau (default 0: every cell), else in
+ * float; force sums and residual norms in double.  A float frequency step
+ * drifts by about one float ulp per step (its matrix barely changes from step
+ * to step, so the rounding does not average out), which exceeds 1e-5 after a
+ * few hundred steps; double arithmetic there keeps the error at the level of
+ * the float storage. */
 typedef enum { M1_FP64 = 0, M1_FP32 = 1 } m1_prec;
 
 typedef struct {
@@ -80,7 +84,7 @@ typedef struct {
   int32_t prec;            /* m1_prec */
   double fp64_tau;         /* FP32 only: line-centre cell optical depth above
                               which a cell's frequency step runs in double
-                              (1e6); +inf disables the islands */
+                              (0: all cells; +inf: none) */
 } m1_config;
 
 /* Per-cell physical inputs, FP64, [ny][nx].  Host pointers when on_device is
@@ -101,7 +105,7 @@ typedef struct {
 typedef struct m1_handle m1_handle;
 
 /* Fills *cfg with the paper's defaults (T_min 30 K, q 1.1, half-width 1e5,
- * CFL 0.4, recoil and Doppler on, FP64, fp64_tau 1e6, vacuum boundaries). */
+ * CFL 0.4, recoil and Doppler on, FP64, fp64_tau 0, vacuum boundaries). */
 int32_t m1_default_config(m1_config *cfg);
 
 /* Number of frequency bins of cfg's grid (194 with the defaults; Section 2.1). */
@@ -148,11 +152,14 @@ int32_t m1_solve_steady(m1_handle *h, double rel_tol, int64_t max_steps,
 /* Residual r of the last step (as in m1_solve_steady).  Blocking. */
 int32_t m1_residual(m1_handle *h, double *resid);
 
-/* Copy the state out of / into caller device arrays [N_nu][ny][nx] of the
- * handle's precision (double for M1_FP64, float for M1_FP32), physical units.
- * get is blocking; set is asynchronous. */
-int32_t m1_get_state(m1_handle *h, void *d_E, void *d_Fx, void *d_Fy);
-int32_t m1_set_state(m1_handle *h, const void *d_E, const void *d_Fx, const void *d_Fy);
+/* Copy the state out of / into caller device arrays of doubles
+ * [N_nu][ny][nx] in physical units (E, F per Hz).  The FP32 path keeps its
+ * state scaled by 2^scale_exp2 internally (see m1_get_info), so physical
+ * values far below FLT_MIN are still exchanged exactly.  get is blocking;
+ * set is asynchronous. */
+int32_t m1_get_state(m1_handle *h, double *d_E, double *d_Fx, double *d_Fy);
+int32_t m1_set_state(m1_handle *h, const double *d_E, const double *d_Fx,
+                     const double *d_Fy);
 
 /* Scalars of a handle: dt [s], N_nu, precision, cells, internal scale 2^e. */
 int32_t m1_get_info(const m1_handle *h, double *dt, int32_t *n_nu, int32_t *prec,

@@ -73,13 +73,34 @@ __device__ __forceinline__ Eddington<R> closure_f(R fx, R fy) {
   return d;
 }
 
+// Smallest E whose reciprocal is finite with margin (2^-120 in float,
+// 2^-1000 in double).  Below it (subnormal far-wing values) f = F/E is formed
+// by true division, which stays bounded because |F| <= E.
 template <typename R>
-__device__ __forceinline__ Eddington<R> closure_state(R E, R Fx, R Fy) {
-  R fx = R(0), fy = R(0);
-  if (E > R(0)) {
+__device__ __forceinline__ R recip_floor() {
+  return sizeof(R) == 4 ? R(7.52316384526264e-37) : R(9.332636185032189e-302);
+}
+
+// Reduced flux f = F/E (0 where E <= 0).
+template <typename R>
+__device__ __forceinline__ void reduced_flux(R E, R Fx, R Fy, R& fx, R& fy) {
+  if (E >= recip_floor<R>()) {
     R inv = R(1) / E;
     fx = Fx * inv;
     fy = Fy * inv;
+  } else if (E > R(0)) {
+    fx = Fx / E;
+    fy = Fy / E;
+  } else {
+    fx = fy = R(0);
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ Eddington<R> closure_state(R E, R Fx, R Fy) {
+  R fx, fy;
+  reduced_flux(E, Fx, Fy, fx, fy);
+  {
     R n2 = fx * fx + fy * fy;
     if (n2 > R(1)) {
       R sc = R(1) / sqrt(n2);

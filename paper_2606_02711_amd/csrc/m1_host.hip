@@ -475,7 +475,7 @@ int32_t m1_default_config(m1_config* c) {
   c->recoil = 1;
   c->doppler = 1;
   c->prec = M1_FP64;
-  c->fp64_tau = 1.0e6;
+  c->fp64_tau = 0.0;
   return M1_OK;
 }
 
@@ -717,30 +717,30 @@ int32_t m1_solve_steady(m1_handle* h, double rel_tol, int64_t max_steps, int32_t
   return M1_OK;
 }
 
-int32_t m1_get_state(m1_handle* h, void* d_E, void* d_Fx, void* d_Fy) {
+int32_t m1_get_state(m1_handle* h, double* d_E, double* d_Fx, double* d_Fy) {
   if (!h) return fail(M1_EINVAL, "handle is NULL");
   size_t n = (size_t)h->nb * h->nc;
-  void* dst[3] = {d_E, d_Fx, d_Fy};
+  double* dst[3] = {d_E, d_Fx, d_Fy};
   for (int q = 0; q < 3; ++q) {
     if (!dst[q]) continue;
     const char* src = h->ws + h->L.state[h->cur][q];
     hipError_t e = h->cfg.prec == M1_FP32
-        ? launch_scale_copy<float>((const float*)src, (float*)dst[q], n, -h->e2, h->stream)
-        : launch_scale_copy<double>((const double*)src, (double*)dst[q], n, -h->e2, h->stream);
+        ? launch_scale_copy<float, double>((const float*)src, dst[q], n, -h->e2, h->stream)
+        : launch_scale_copy<double, double>((const double*)src, dst[q], n, -h->e2, h->stream);
     if (e != hipSuccess) return fail(M1_EDEVICE, "copy launch: %s", hipGetErrorString(e));
   }
   return m1_sync(h);
 }
 
-int32_t m1_set_state(m1_handle* h, const void* d_E, const void* d_Fx, const void* d_Fy) {
+int32_t m1_set_state(m1_handle* h, const double* d_E, const double* d_Fx, const double* d_Fy) {
   if (!h || !d_E || !d_Fx || !d_Fy) return fail(M1_EINVAL, "bad arguments");
   size_t n = (size_t)h->nb * h->nc;
-  const void* src[3] = {d_E, d_Fx, d_Fy};
+  const double* src[3] = {d_E, d_Fx, d_Fy};
   for (int q = 0; q < 3; ++q) {
     char* dst = h->ws + h->L.state[h->cur][q];
     hipError_t e = h->cfg.prec == M1_FP32
-        ? launch_scale_copy<float>((const float*)src[q], (float*)dst, n, h->e2, h->stream)
-        : launch_scale_copy<double>((const double*)src[q], (double*)dst, n, h->e2, h->stream);
+        ? launch_scale_copy<double, float>(src[q], (float*)dst, n, h->e2, h->stream)
+        : launch_scale_copy<double, double>(src[q], (double*)dst, n, h->e2, h->stream);
     if (e != hipSuccess) return fail(M1_EDEVICE, "copy launch: %s", hipGetErrorString(e));
   }
   return M1_OK;

@@ -74,7 +74,7 @@ __global__ void k_cell_setup(CellInputs in, size_t nc, double dmin, double fp64_
   acabs[c] = (R)in.acabs[c];
   pda[c] = (R)(in.pd[c] * a);
   em[c] = (R)(ldexp(in.emis[c], e2) / kC);
-  island[c] = (a * dmin > fp64_tau) ? 1 : 0;
+  island[c] = (a * dmin >= fp64_tau) ? 1 : 0;
 }
 
 template <typename R>

@@ -37,14 +37,9 @@ __device__ __forceinline__ void load_ef(const GridArgs<R>& a, size_t koff, int i
   }
   size_t q = koff + (size_t)sj * a.nx + si;
   e = a.E[q];
-  R X = a.Fx[q], Y = a.Fy[q];
-  if (e > R(0)) {
-    R inv = R(1) / e;
-    fx = sx * X * inv;
-    fy = sy * Y * inv;
-  } else {
-    fx = fy = R(0);
-  }
+  reduced_flux(e, a.Fx[q], a.Fy[q], fx, fy);
+  fx *= sx;
+  fy *= sy;
 }
 
 // Static opacity data of a neighbour (mirror cell at reflecting boundaries;
@@ -173,8 +168,7 @@ __global__ __launch_bounds__(256) void k_advect_source(GridArgs<R> a) {
     R eC, xC, yC;
     const R EC = a.E[koff + c], FXC = a.Fx[koff + c], FYC = a.Fy[koff + c];
     eC = EC;
-    if (EC > R(0)) { R inv = R(1) / EC; xC = FXC * inv; yC = FYC * inv; }
-    else { xC = yC = R(0); }
+    reduced_flux(EC, FXC, FYC, xC, yC);
     R eWW, xWW, yWW, eW, xW, yW, eE, xE, yE, eEE, xEE, yEE;
     load_ef(a, koff, i - 2, j, eWW, xWW, yWW);
     load_ef(a, koff, i - 1, j, eW, xW, yW);
@@ -340,10 +334,12 @@ __device__ void freq_cell(const GridArgs<R>& a, size_t c) {
     y = (T)a.zs[q] + (T)a.ws[q] * y;
     const T En = y / (T)a.dnu[k];
     const T Eo = (T)a.Eo[q];
-    const T ratio = Eo > T(0) ? En / Eo : T(0);
+    // F^{n+1} = (F**/E**) E^{n+1}, with |F**/E**| <= 1
+    T fxo, fyo;
+    reduced_flux<T>(Eo, (T)a.Fxo[q], (T)a.Fyo[q], fxo, fyo);
     a.Eo[q] = (R)En;
-    a.Fxo[q] = (R)((T)a.Fxo[q] * ratio);
-    a.Fyo[q] = (R)((T)a.Fyo[q] * ratio);
+    a.Fxo[q] = (R)(fxo * En);
+    a.Fyo[q] = (R)(fyo * En);
   }
   a.force[c] = fx;
   a.force[nc + c] = fy;
@@ -398,11 +394,11 @@ __global__ void k_residual_final(const double* __restrict__ partial, int nblk,
 }
 
 // ------------------------------------------------------- copies with scale
-template <typename R>
-__global__ void k_scale_copy(const R* __restrict__ src, R* __restrict__ dst, size_t n, int e2) {
+template <typename S, typename D>
+__global__ void k_scale_copy(const S* __restrict__ src, D* __restrict__ dst, size_t n, int e2) {
   for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
        q += (size_t)gridDim.x * blockDim.x)
-    dst[q] = ldexp(src[q], e2);
+    dst[q] = (D)ldexp((double)src[q], e2);
 }
 
 __global__ void k_force_out(const double* __restrict__ force, size_t nc, int e2,
@@ -449,10 +445,10 @@ hipError_t launch_residual(const R* E0, const R* E1, size_t n, double* partial, 
   return hipGetLastError();
 }
 
-template <typename R>
-hipError_t launch_scale_copy(const R* src, R* dst, size_t n, int e2, hipStream_t s) {
+template <typename S, typename D>
+hipError_t launch_scale_copy(const S* src, D* dst, size_t n, int e2, hipStream_t s) {
   unsigned g = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
-  hipLaunchKernelGGL((k_scale_copy<R>), dim3(g ? g : 1), dim3(256), 0, s, src, dst, n, e2);
+  hipLaunchKernelGGL((k_scale_copy<S, D>), dim3(g ? g : 1), dim3(256), 0, s, src, dst, n, e2);
   return hipGetLastError();
 }
 
@@ -471,7 +467,8 @@ template hipError_t launch_freq<double>(const GridArgs<double>&, hipStream_t);
 template hipError_t launch_step<double>(const GridArgs<double>&, hipStream_t);
 template hipError_t launch_residual<float>(const float*, const float*, size_t, double*, int, double*, hipStream_t);
 template hipError_t launch_residual<double>(const double*, const double*, size_t, double*, int, double*, hipStream_t);
-template hipError_t launch_scale_copy<float>(const float*, float*, size_t, int, hipStream_t);
-template hipError_t launch_scale_copy<double>(const double*, double*, size_t, int, hipStream_t);
+template hipError_t launch_scale_copy<float, double>(const float*, double*, size_t, int, hipStream_t);
+template hipError_t launch_scale_copy<double, float>(const double*, float*, size_t, int, hipStream_t);
+template hipError_t launch_scale_copy<double, double>(const double*, double*, size_t, int, hipStream_t);
 
 }  // namespace m1

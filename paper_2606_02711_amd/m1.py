@@ -103,7 +103,7 @@ def check(code):
 BC = {"vacuum": M1_BC_VACUUM, "reflect": M1_BC_REFLECT}
 
 
-def make_config(p, prec="fp64", fp64_tau=1.0e6):
+def make_config(p, prec="fp64", fp64_tau=0.0):
     c = m1_config()
     check(lib().m1_default_config(ctypes.byref(c)))
     c.geom = M1_CYL_RZ if p["geom"] == "cyl" else M1_CART2D
@@ -153,7 +153,7 @@ class M1Grid:
 
     p: problem dict (see inputs.py); prec: "fp64" or "fp32"."""
 
-    def __init__(self, p, prec="fp64", fp64_tau=1.0e6, stream=None, workspace=None):
+    def __init__(self, p, prec="fp64", fp64_tau=0.0, stream=None, workspace=None):
         torch = _torch()
         self.p = p
         self.prec = prec
@@ -224,7 +224,7 @@ class M1Grid:
     def state(self):
         torch = _torch()
         shape = (self.nb, self.ny, self.nx)
-        E = torch.empty(shape, dtype=self.dtype, device="cuda")
+        E = torch.empty(shape, dtype=torch.float64, device="cuda")
         Fx = torch.empty_like(E)
         Fy = torch.empty_like(E)
         check(lib().m1_get_state(self.h, E.data_ptr(), Fx.data_ptr(), Fy.data_ptr()))
@@ -232,7 +232,7 @@ class M1Grid:
 
     def set_state(self, E, Fx, Fy):
         torch = _torch()
-        conv = lambda a: torch.as_tensor(a, dtype=self.dtype, device="cuda").contiguous()
+        conv = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda").contiguous()
         self._set = (conv(E), conv(Fx), conv(Fy))
         check(lib().m1_set_state(self.h, *[t.data_ptr() for t in self._set]))
 
