@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--fp64-tau", type=float, default=0.0,
                     help="FP32 path: cells above this line-centre depth use a double frequency step")
     args = ap.parse_args()
@@ -115,6 +117,15 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     from paper_2606_02711_amd import inputs
+    if args.calibrate_copy:
+        # known traffic: reads 2^30 B and writes 2^30 B per copy
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] copy calibration: 3 copies of 1 GiB")
+        del src, dst
     p = inputs.config2()
     r32 = run_path(p, "fp32", args.steps, args.warmup, args.fp64_tau)
     r64 = None if args.no_fp64 else run_path(p, "fp64", args.steps, args.warmup)
