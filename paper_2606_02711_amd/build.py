@@ -14,6 +14,9 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
     # packed FP32 instructions stay off (hand-off to the compiler's scalar FP32)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # float divide and sqrt as the hardware's 1-ulp reciprocal/sqrt (the FP32
+    # path's error budget is 1e-5); double arithmetic stays IEEE
+    "-fno-hip-fp32-correctly-rounded-divide-sqrt",
     "-Wno-unused-command-line-argument",
 ]
 

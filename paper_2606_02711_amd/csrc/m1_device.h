@@ -58,13 +58,23 @@ struct Eddington {
   R xx, yy, xy, pp;
 };
 
+// Reciprocal, square root and reciprocal square root.  Float: the hardware's
+// 1-ulp instructions, used only on arguments that are normal numbers by
+// construction; double: IEEE operations.
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double frsq(double x) { return 1.0 / sqrt(x); }
+
 template <typename R>
 __device__ __forceinline__ Eddington<R> closure_f(R fx, R fy) {
   R f2 = fx * fx + fy * fy;
-  if (f2 > R(1)) f2 = R(1);
-  R s = sqrt(R(4) - R(3) * f2);
-  R iso = (R(1) - f2) / (R(1) + s);
-  R g = R(3) / (R(2) + s);
+  f2 = f2 > R(1) ? R(1) : f2;
+  R s = fsqrt(R(4) - R(3) * f2);          // in [1, 2]
+  R iso = (R(1) - f2) * frcp(R(1) + s);
+  R g = R(3) * frcp(R(2) + s);
   Eddington<R> d;
   d.xx = iso + g * fx * fx;
   d.yy = iso + g * fy * fy;
@@ -84,15 +94,13 @@ __device__ __forceinline__ R recip_floor() {
 // Reduced flux f = F/E (0 where E <= 0).
 template <typename R>
 __device__ __forceinline__ void reduced_flux(R E, R Fx, R Fy, R& fx, R& fy) {
-  if (E >= recip_floor<R>()) {
-    R inv = R(1) / E;
-    fx = Fx * inv;
-    fy = Fy * inv;
-  } else if (E > R(0)) {
+  const bool big = E >= recip_floor<R>();
+  const R inv = frcp(big ? E : R(1));
+  fx = big ? Fx * inv : R(0);
+  fy = big ? Fy * inv : R(0);
+  if (!big && E > R(0)) {            // subnormal far-wing values only
     fx = Fx / E;
     fy = Fy / E;
-  } else {
-    fx = fy = R(0);
   }
 }
 
@@ -100,22 +108,16 @@ template <typename R>
 __device__ __forceinline__ Eddington<R> closure_state(R E, R Fx, R Fy) {
   R fx, fy;
   reduced_flux(E, Fx, Fy, fx, fy);
-  {
-    R n2 = fx * fx + fy * fy;
-    if (n2 > R(1)) {
-      R sc = R(1) / sqrt(n2);
-      fx *= sc;
-      fy *= sc;
-    }
-  }
-  return closure_f(fx, fy);
+  const R n2 = fx * fx + fy * fy;
+  const R sc = n2 > R(1) ? frsq(n2) : R(1);
+  return closure_f(fx * sc, fy * sc);
 }
 
 template <typename R>
 __device__ __forceinline__ R minmod(R a, R b) {
-  if (a > R(0) && b > R(0)) return a < b ? a : b;
-  if (a < R(0) && b < R(0)) return a > b ? a : b;
-  return R(0);
+  const R m = fabs(a) < fabs(b) ? a : b;
+  const bool same = (a > R(0) && b > R(0)) || (a < R(0) && b < R(0));
+  return same ? m : R(0);
 }
 
 }  // namespace m1

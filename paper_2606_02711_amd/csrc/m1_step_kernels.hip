@@ -93,9 +93,9 @@ __device__ __forceinline__ Flux3<R> face_flux(R eLL, R xLL, R yLL, R eL, R xL, R
   R fxR = xR + minmod(dX, (xRR - xR) * iRR) * hR;
   R fyR = yR + minmod(dY, (yRR - yR) * iRR) * hR;
   // causality at the interface: |f| > 1 is scaled back to 1
-  R nL = fxL * fxL + fyL * fyL, nR = fxR * fxR + fyR * fyR;
-  if (nL > R(1)) { R s = R(1) / sqrt(nL); fxL *= s; fyL *= s; }
-  if (nR > R(1)) { R s = R(1) / sqrt(nR); fxR *= s; fyR *= s; }
+  const R nL = fxL * fxL + fyL * fyL, nR = fxR * fxR + fyR * fyR;
+  const R sL = nL > R(1) ? frsq(nL) : R(1), sR = nR > R(1) ? frsq(nR) : R(1);
+  fxL *= sL; fyL *= sL; fxR *= sR; fyR *= sR;
   Eddington<R> DL = closure_f(fxL, fyL), DR = closure_f(fxR, fyR);
   R FxL = fxL * EL, FyL = fyL * EL, FxR = fxR * ER, FyR = fyR * ER;
   R PxL, PyL, PxR, PyR;       // row n of the pressure tensor, P = D E
@@ -103,7 +103,7 @@ __device__ __forceinline__ Flux3<R> face_flux(R eLL, R xLL, R yLL, R eL, R xL, R
   else        { PxL = DL.xy * EL; PyL = DL.yy * EL; PxR = DR.xy * ER; PyR = DR.yy * ER; }
   // flux optical depth between the centroids and the blend eps(tau)
   R tau = aFL * hL - aFR * hR;
-  R inv = R(1) / (R(0.2) + tau + tau * tau);
+  R inv = frcp(R(0.2) + tau + tau * tau);
   R eps = (R(0.2) + tau) * inv;
   R dco = tau * inv * R(1.0 / 3.0);     // (1 - eps) / (3 tau)
   R FnL = (N == 0) ? FxL : FyL, FnR = (N == 0) ? FxR : FyR;
@@ -112,102 +112,263 @@ __device__ __forceinline__ Flux3<R> face_flux(R eLL, R xLL, R yLL, R eL, R xL, R
   r.x = R(0.5) * (PxL + PxR) - eps * R(0.5) * (FxR - FxL);
   r.y = R(0.5) * (PyL + PyR) - eps * R(0.5) * (FyR - FyL);
   // upwind advection by the face velocity with the upstream reconstruction
-  if (un_c > R(0)) { r.e += un_c * EL; r.x += un_c * FxL; r.y += un_c * FyL; }
-  else if (un_c < R(0)) { r.e += un_c * ER; r.x += un_c * FxR; r.y += un_c * FyR; }
+  const bool up = un_c > R(0);
+  r.e += un_c * (up ? EL : ER);
+  r.x += un_c * (up ? FxL : FxR);
+  r.y += un_c * (up ? FyL : FyR);
   return r;
 }
 
 // ---------------------------------------------------------------- K2
-// Block: 64 x 4 lanes (x fastest, coalesced rows); each lane walks BK bins of
-// one cell so the cell's static data is loaded once per BK bins.
+// LDS-tiled advection + emission/absorption.  A block owns a tile of
+// kTX x kTY cells and walks a run of bins.  Per bin: (1) the tile plus two
+// ghost layers of (E, f) and the alpha_F ring are staged in LDS (f = F/E is
+// formed once per cell), (2) every x- and y-face flux of the tile is computed
+// exactly once into LDS, (3) each lane updates its cells (two per lane),
+// applies the causality clamp and the implicit source, and writes E**, F**.
+// Blocks are mapped so that the tiles one XCD runs are contiguous in space
+// (halo rows shared between neighbouring tiles then hit the same L2).
+constexpr int kTX = 64, kTY = 8;
+constexpr int kPX = kTX + 4, kPY = kTY + 4;   // padded tile, halo 2
+constexpr int kRX = kTX + 2, kRY = kTY + 2;   // opacity ring, halo 1
+constexpr int kNXF = kTY * (kTX + 1);         // x-faces of a tile
+constexpr int kNYF = (kTY + 1) * kTX;         // y-faces of a tile
+
+template <typename R>
+struct AdvShared {
+  R E[kPY][kPX], fx[kPY][kPX], fy[kPY][kPX];  // staged state: E and f = F/E
+  R aF[kRY][kRX];                              // alpha_F of the ring, this bin
+  R fle[kNXF + kNYF], flx[kNXF + kNYF], fly[kNXF + kNYF];  // face fluxes
+  R un[kNXF + kNYF];                           // face-normal velocity / c
+  R xidl[kTX + 3], xhp[kTX + 2], xhm[kTX + 2]; // columns x0-1 .. (geometry)
+  R yidl[kTY + 3], yhp[kTY + 2], yhm[kTY + 2]; // rows y0-1 ..
+};
+
+// Logical block index: XCD x (hardware round-robin b mod 8) gets a
+// contiguous range of logical blocks.
+__device__ __forceinline__ unsigned xcd_logical_block() {
+  const unsigned B = gridDim.x, b = blockIdx.x;
+  const unsigned x = b & 7u, slot = b >> 3, q = B >> 3, r = B & 7u;
+  return x * q + (x < r ? x : r) + slot;
+}
+
+// Source cell of a tile entry (ii, jj) with ghost rules; returns false when
+// the entry lies outside the `depth` ghost layers or in a domain corner.
+__device__ __forceinline__ bool ghost_source(int ii, int jj, int nx, int ny, const int* bc,
+                                             int depth, int& si, int& sj, int& sgx, int& sgy,
+                                             bool& vac) {
+  si = ii; sj = jj; sgx = 1; sgy = 1; vac = false;
+  const bool ox = ii < 0 || ii >= nx, oy = jj < 0 || jj >= ny;
+  if (ox && oy) return false;
+  if (ox) {
+    if (ii < -depth || ii >= nx + depth) return false;
+    const int side = ii < 0 ? 0 : 1;
+    if (bc[side] != kReflect) { vac = true; return true; }
+    si = ii < 0 ? -1 - ii : 2 * nx - 1 - ii;
+    sgx = -1;
+  } else if (oy) {
+    if (jj < -depth || jj >= ny + depth) return false;
+    const int side = jj < 0 ? 2 : 3;
+    if (bc[side] != kReflect) { vac = true; return true; }
+    sj = jj < 0 ? -1 - jj : 2 * ny - 1 - jj;
+    sgy = -1;
+  }
+  return true;
+}
+
+constexpr int kRingPerLane = (kRX * kRY + 255) / 256;   // 3
+
 template <typename R, int BK>
 __global__ __launch_bounds__(256) void k_advect_source(GridArgs<R> a) {
-  const int i = blockIdx.x * 64 + threadIdx.x;
-  const int j = blockIdx.y * 4 + threadIdx.y;
-  const int k0 = blockIdx.z * BK;
-  if (i >= a.nx || j >= a.ny) return;
-  const int nx = a.nx;
-  const size_t nc = (size_t)nx * a.ny;
-  const size_t c = (size_t)j * nx + i;
+  __shared__ AdvShared<R> S;
+  const int nx = a.nx, ny = a.ny, nb = a.nb;
+  const size_t nc = (size_t)nx * ny;
+  const int nbx = (nx + kTX - 1) / kTX, nby = (ny + kTY - 1) / kTY;
+  const unsigned L = xcd_logical_block();
+  const int bx = (int)(L % (unsigned)nbx);
+  const unsigned t1 = L / (unsigned)nbx;
+  const int by = (int)(t1 % (unsigned)nby);
+  const int bz = (int)(t1 / (unsigned)nby);
+  const int x0 = bx * kTX, y0 = by * kTY, k0 = bz * BK;
+  const int kend = min(k0 + BK, nb);
+  const int tid = threadIdx.x;
   const R inv_c = R(1.0 / kC);
+  const bool interior = x0 >= 2 && x0 + kTX + 2 <= nx && y0 >= 2 && y0 + kTY + 2 <= ny;
 
-  // static data of the cell and its four face neighbours
-  const int clsC = a.cls[c];
-  const R alC = a.alpha[c], acFC = a.acF[c], acabsC = a.acabs[c], pdaC = a.pda[c];
-  const R emC = a.em[c];
-  const NbrOpacity<R> oW = nbr_opacity(a, i - 1, j), oE = nbr_opacity(a, i + 1, j);
-  const NbrOpacity<R> oS = nbr_opacity(a, i, j - 1), oN = nbr_opacity(a, i, j + 1);
-  const R gxx = a.grad[c], gyy = a.grad[nc + c], gxy = a.grad[2 * nc + c],
-          gpp = a.grad[3 * nc + c];
-  const R uW = a.ufx[(size_t)j * (nx + 1) + i] * inv_c;
-  const R uE = a.ufx[(size_t)j * (nx + 1) + i + 1] * inv_c;
-  const R uS = a.ufy[c] * inv_c;
-  const R uN = a.ufy[c + nx] * inv_c;
-  // geometry (x: column index + 2; y: row index + 2)
-  const R xi_m = a.xidl[i + 1], xi_c = a.xidl[i + 2], xi_p = a.xidl[i + 3], xi_pp = a.xidl[i + 4];
-  const R xhp_W = a.xhp[i + 1], xhm_C = a.xhm[i + 2], xhp_C = a.xhp[i + 2], xhm_E = a.xhm[i + 3];
-  const R yi_m = a.yidl[j + 1], yi_c = a.yidl[j + 2], yi_p = a.yidl[j + 3], yi_pp = a.yidl[j + 4];
-  const R yhp_S = a.yhp[j + 1], yhm_C = a.yhm[j + 2], yhp_C = a.yhp[j + 2], yhm_N = a.yhm[j + 3];
-  const R cxm = a.cxm[i], cxp = a.cxp[i], chp = a.chp[i], cy = a.cy[j];
+  // ---- once per block: ring opacities (registers), geometry and face
+  //      velocities (LDS)
+  R ral[kRingPerLane], racF[kRingPerLane];
+  int rcls[kRingPerLane];
+#pragma unroll
+  for (int m = 0; m < kRingPerLane; ++m) {
+    const int e = tid + 256 * m;
+    ral[m] = R(0); racF[m] = R(0); rcls[m] = 0;
+    if (e < kRX * kRY) {
+      const int ri = e % kRX, rj = e / kRX;
+      int si, sj, sgx, sgy;
+      bool vac;
+      if (ghost_source(x0 + ri - 1, y0 + rj - 1, nx, ny, a.bc, 1, si, sj, sgx, sgy, vac) && !vac) {
+        const size_t c = (size_t)sj * nx + si;
+        ral[m] = a.alpha[c]; racF[m] = a.acF[c]; rcls[m] = a.cls[c];
+      }
+    }
+  }
+  for (int e = tid; e < kTX + 3; e += 256) {
+    const int gi = x0 - 1 + e;                       // column index, >= -1
+    S.xidl[e] = gi <= nx + 1 ? a.xidl[gi + 2] : R(0);
+    if (e < kTX + 2) {
+      S.xhp[e] = gi <= nx ? a.xhp[gi + 2] : R(0);
+      S.xhm[e] = gi <= nx ? a.xhm[gi + 2] : R(0);
+    }
+  }
+  for (int e = tid; e < kTY + 3; e += 256) {
+    const int gj = y0 - 1 + e;
+    S.yidl[e] = gj <= ny + 1 ? a.yidl[gj + 2] : R(0);
+    if (e < kTY + 2) {
+      S.yhp[e] = gj <= ny ? a.yhp[gj + 2] : R(0);
+      S.yhm[e] = gj <= ny ? a.yhm[gj + 2] : R(0);
+    }
+  }
+  for (int f = tid; f < kNXF + kNYF; f += 256) {
+    R u = R(0);
+    if (f < kNXF) {
+      const int gi = x0 + f % (kTX + 1), gj = y0 + f / (kTX + 1);
+      if (gi <= nx && gj < ny) u = a.ufx[(size_t)gj * (nx + 1) + gi] * inv_c;
+    } else {
+      const int g = f - kNXF;
+      const int gi = x0 + g % kTX, gj = y0 + g / kTX;
+      if (gi < nx && gj <= ny) u = a.ufy[(size_t)gj * nx + gi] * inv_c;
+    }
+    S.un[f] = u;
+  }
+
+  // ---- per-lane cells: (tx, ty) and (tx, ty + 4)
+  const int tx = tid & 63, ty = tid >> 6;
+  bool own[2];
+  size_t cidx[2];
+  int ccls[2];
+  R acabs[2], pda[2], em[2], gxx[2], gyy[2], gxy[2], gpp[2], cy[2];
+  const int gi = x0 + tx;
+  const bool colok = gi < nx;
+  const R cxm = colok ? a.cxm[gi] : R(0), cxp = colok ? a.cxp[gi] : R(0);
+  const R chp = colok ? a.chp[gi] : R(0);
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const int gj = y0 + ty + 4 * m;
+    own[m] = colok && gj < ny;
+    cidx[m] = own[m] ? (size_t)gj * nx + gi : 0;
+    const size_t c = cidx[m];
+    ccls[m] = own[m] ? a.cls[c] : 0;
+    acabs[m] = own[m] ? a.acabs[c] : R(0);
+    pda[m] = own[m] ? a.pda[c] : R(0);
+    em[m] = own[m] ? a.em[c] : R(0);
+    gxx[m] = own[m] ? a.grad[c] : R(0);
+    gyy[m] = own[m] ? a.grad[nc + c] : R(0);
+    gxy[m] = own[m] ? a.grad[2 * nc + c] : R(0);
+    gpp[m] = own[m] ? a.grad[3 * nc + c] : R(0);
+    cy[m] = own[m] ? a.cy[gj] : R(0);
+  }
   const R ctdt = a.ctdt, ctdt_c = a.ctdt_c;
-  const bool moving = (gxx != R(0)) || (gyy != R(0)) || (gxy != R(0)) || (gpp != R(0));
 
-  const int kend = min(k0 + BK, a.nb);
   for (int k = k0; k < kend; ++k) {
     const size_t koff = (size_t)k * nc;
-    const R* hb = a.hbar;
-    const int nb = a.nb;
-    // opacities of this bin
-    const R hC = hb[(size_t)clsC * nb + k];
-    const R aFC = alC * hC + acFC;
-    const R aFW = oW.alpha * hb[(size_t)oW.cls * nb + k] + oW.acF;
-    const R aFE = oE.alpha * hb[(size_t)oE.cls * nb + k] + oE.acF;
-    const R aFS = oS.alpha * hb[(size_t)oS.cls * nb + k] + oS.acF;
-    const R aFN = oN.alpha * hb[(size_t)oN.cls * nb + k] + oN.acF;
-    // stencil: centre, and two cells each way along x and y
-    R eC, xC, yC;
-    const R EC = a.E[koff + c], FXC = a.Fx[koff + c], FYC = a.Fy[koff + c];
-    eC = EC;
-    reduced_flux(EC, FXC, FYC, xC, yC);
-    R eWW, xWW, yWW, eW, xW, yW, eE, xE, yE, eEE, xEE, yEE;
-    load_ef(a, koff, i - 2, j, eWW, xWW, yWW);
-    load_ef(a, koff, i - 1, j, eW, xW, yW);
-    load_ef(a, koff, i + 1, j, eE, xE, yE);
-    load_ef(a, koff, i + 2, j, eEE, xEE, yEE);
-    R eSS, xSS, ySS, eS, xS, yS, eN, xN, yN, eNN, xNN, yNN;
-    load_ef(a, koff, i, j - 2, eSS, xSS, ySS);
-    load_ef(a, koff, i, j - 1, eS, xS, yS);
-    load_ef(a, koff, i, j + 1, eN, xN, yN);
-    load_ef(a, koff, i, j + 2, eNN, xNN, yNN);
-    // four face fluxes
-    Flux3<R> fW = face_flux<R, 0>(eWW, xWW, yWW, eW, xW, yW, eC, xC, yC, eE, xE, yE,
-                                  xi_m, xi_c, xi_p, xhp_W, xhm_C, aFW, aFC, uW);
-    Flux3<R> fE = face_flux<R, 0>(eW, xW, yW, eC, xC, yC, eE, xE, yE, eEE, xEE, yEE,
-                                  xi_c, xi_p, xi_pp, xhp_C, xhm_E, aFC, aFE, uE);
-    Flux3<R> fS = face_flux<R, 1>(eSS, xSS, ySS, eS, xS, yS, eC, xC, yC, eN, xN, yN,
-                                  yi_m, yi_c, yi_p, yhp_S, yhm_C, aFS, aFC, uS);
-    Flux3<R> fN = face_flux<R, 1>(eS, xS, yS, eC, xC, yC, eN, xN, yN, eNN, xNN, yNN,
-                                  yi_c, yi_p, yi_pp, yhp_C, yhm_N, aFC, aFN, uN);
-    // conservative update, work term and hoop pressure
-    Eddington<R> D = closure_state(EC, FXC, FYC);
-    R Es = EC - (cxp * fE.e - cxm * fW.e + cy * (fN.e - fS.e));
-    R Xs = FXC - (cxp * fE.x - cxm * fW.x + cy * (fN.x - fS.x));
-    R Ys = FYC - (cxp * fE.y - cxm * fW.y + cy * (fN.y - fS.y));
-    if (moving) Es -= ctdt_c * (D.xx * gxx + D.yy * gyy + D.xy * gxy + D.pp * gpp) * EC;
-    Xs += chp * D.pp * EC;
-    // causality: E >= 0, |F| <= E
-    if (Es <= R(0)) { Es = R(0); Xs = R(0); Ys = R(0); }
-    else {
-      R n2 = Xs * Xs + Ys * Ys;
-      if (n2 > Es * Es) { R s = Es / sqrt(n2); Xs *= s; Ys *= s; }
+    const R* hb = a.hbar + k;
+    // (1) stage E and f of the padded tile, and alpha_F of the ring
+    if (interior) {
+      for (int e = tid; e < kPX * kPY; e += 256) {
+        const int pi = e % kPX, pj = e / kPX;
+        const size_t q = koff + (size_t)(y0 + pj - 2) * nx + (x0 + pi - 2);
+        const R ev = a.E[q];
+        R fxv, fyv;
+        reduced_flux(ev, a.Fx[q], a.Fy[q], fxv, fyv);
+        S.E[pj][pi] = ev; S.fx[pj][pi] = fxv; S.fy[pj][pi] = fyv;
+      }
+    } else {
+      for (int e = tid; e < kPX * kPY; e += 256) {
+        const int pi = e % kPX, pj = e / kPX;
+        int si, sj, sgx, sgy;
+        bool vac;
+        R ev = R(0), fxv = R(0), fyv = R(0);
+        if (ghost_source(x0 + pi - 2, y0 + pj - 2, nx, ny, a.bc, 2, si, sj, sgx, sgy, vac) &&
+            !vac) {
+          const size_t q = koff + (size_t)sj * nx + si;
+          ev = a.E[q];
+          reduced_flux(ev, a.Fx[q], a.Fy[q], fxv, fyv);
+          fxv *= R(sgx);
+          fyv *= R(sgy);
+        }
+        S.E[pj][pi] = ev; S.fx[pj][pi] = fxv; S.fy[pj][pi] = fyv;
+      }
     }
-    // implicit emission / absorption / destruction
-    const R src = emC * a.phi[(size_t)clsC * nb + k];
-    const R kE = acabsC + pdaC * hC;
-    a.Eo[koff + c] = (Es + ctdt * src) / (R(1) + ctdt * kE);
-    const R dF = R(1) / (R(1) + ctdt * aFC);
-    a.Fxo[koff + c] = Xs * dF;
-    a.Fyo[koff + c] = Ys * dF;
+#pragma unroll
+    for (int m = 0; m < kRingPerLane; ++m) {
+      const int e = tid + 256 * m;
+      if (e < kRX * kRY) (&S.aF[0][0])[e] = ral[m] * hb[(size_t)rcls[m] * nb] + racF[m];
+    }
+    __syncthreads();
+    // (2) every face of the tile once: x-faces [0, kNXF), then y-faces
+    for (int f = tid; f < kNXF + kNYF; f += 256) {
+      Flux3<R> r;
+      if (f < kNXF) {
+        const int fr = f / (kTX + 1), fc = f % (kTX + 1);
+        const int pj = fr + 2, pl = fc + 1;
+        r = face_flux<R, 0>(
+            S.E[pj][pl - 1], S.fx[pj][pl - 1], S.fy[pj][pl - 1],
+            S.E[pj][pl], S.fx[pj][pl], S.fy[pj][pl],
+            S.E[pj][pl + 1], S.fx[pj][pl + 1], S.fy[pj][pl + 1],
+            S.E[pj][pl + 2], S.fx[pj][pl + 2], S.fy[pj][pl + 2],
+            S.xidl[fc], S.xidl[fc + 1], S.xidl[fc + 2], S.xhp[fc], S.xhm[fc + 1],
+            S.aF[fr + 1][fc], S.aF[fr + 1][fc + 1], S.un[f]);
+      } else {
+        const int g = f - kNXF;
+        const int fr = g / kTX, fc = g % kTX;
+        const int pi = fc + 2, pl = fr + 1;
+        r = face_flux<R, 1>(
+            S.E[pl - 1][pi], S.fx[pl - 1][pi], S.fy[pl - 1][pi],
+            S.E[pl][pi], S.fx[pl][pi], S.fy[pl][pi],
+            S.E[pl + 1][pi], S.fx[pl + 1][pi], S.fy[pl + 1][pi],
+            S.E[pl + 2][pi], S.fx[pl + 2][pi], S.fy[pl + 2][pi],
+            S.yidl[fr], S.yidl[fr + 1], S.yidl[fr + 2], S.yhp[fr], S.yhm[fr + 1],
+            S.aF[fr][fc + 1], S.aF[fr + 1][fc + 1], S.un[f]);
+      }
+      S.fle[f] = r.e; S.flx[f] = r.x; S.fly[f] = r.y;
+    }
+    __syncthreads();
+    // (3) update, causality clamp, implicit source
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      if (!own[m]) continue;
+      const int lj = ty + 4 * m, pj = lj + 2, pi = tx + 2;
+      const R EC = S.E[pj][pi], fxc = S.fx[pj][pi], fyc = S.fy[pj][pi];
+      const int w = lj * (kTX + 1) + tx;             // west face; east = w + 1
+      const int so = kNXF + lj * kTX + tx;           // south face; north = so + kTX
+      R Es = EC - (cxp * S.fle[w + 1] - cxm * S.fle[w] + cy[m] * (S.fle[so + kTX] - S.fle[so]));
+      R Xs = fxc * EC - (cxp * S.flx[w + 1] - cxm * S.flx[w] + cy[m] * (S.flx[so + kTX] - S.flx[so]));
+      R Ys = fyc * EC - (cxp * S.fly[w + 1] - cxm * S.fly[w] + cy[m] * (S.fly[so + kTX] - S.fly[so]));
+      const R n2 = fxc * fxc + fyc * fyc;
+      const R sc = n2 > R(1) ? frsq(n2) : R(1);
+      const Eddington<R> D = closure_f(fxc * sc, fyc * sc);
+      Es -= ctdt_c * (D.xx * gxx[m] + D.yy * gyy[m] + D.xy * gxy[m] + D.pp * gpp[m]) * EC;
+      Xs += chp * D.pp * EC;
+      // causality: E >= 0 and |F| <= E
+      const R q2 = Xs * Xs + Ys * Ys;
+      const bool pos = Es > R(0);
+      const R cl = (pos && q2 > Es * Es) ? Es * frsq(q2) : R(1);
+      Xs = pos ? Xs * cl : R(0);
+      Ys = pos ? Ys * cl : R(0);
+      Es = pos ? Es : R(0);
+      const int cc = ccls[m];
+      const R hC = hb[(size_t)cc * nb];
+      const R aFC = S.aF[lj + 1][tx + 1];
+      const R src = em[m] * a.phi[(size_t)cc * nb + k];
+      const R kE = acabs[m] + pda[m] * hC;
+      const size_t q = koff + cidx[m];
+      a.Eo[q] = (Es + ctdt * src) * frcp(R(1) + ctdt * kE);
+      const R dF = frcp(R(1) + ctdt * aFC);
+      a.Fxo[q] = Xs * dF;
+      a.Fyo[q] = Ys * dF;
+    }
+    __syncthreads();
   }
 }
 
@@ -413,13 +574,13 @@ __global__ void k_force_out(const double* __restrict__ force, size_t nc, int e2,
 }
 
 // ------------------------------------------------------------ launchers
-constexpr int kBK = 8;
+constexpr int kBK = 28;   // bins per advection block (7 runs for 194 bins)
 
 template <typename R>
 hipError_t launch_advect(const GridArgs<R>& a, hipStream_t s) {
-  dim3 blk(64, 4, 1);
-  dim3 grd((a.nx + 63) / 64, (a.ny + 3) / 4, (a.nb + kBK - 1) / kBK);
-  hipLaunchKernelGGL((k_advect_source<R, kBK>), grd, blk, 0, s, a);
+  const unsigned nbx = (a.nx + kTX - 1) / kTX, nby = (a.ny + kTY - 1) / kTY;
+  const unsigned nbz = (a.nb + kBK - 1) / kBK;
+  hipLaunchKernelGGL((k_advect_source<R, kBK>), dim3(nbx * nby * nbz), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
