@@ -54,7 +54,7 @@ def measured_traffic(kernel, prec):
     return rec.get("bytes_per_launch") if rec else None
 
 
-def run_path(p, prec, steps, warmup, fp64_tau=0.0):
+def run_path(p, prec, steps, warmup, fp64_tau=float("inf")):
     import torch
     from paper_2606_02711_amd import m1
     log(f"[bench] init {prec} fp64_tau={fp64_tau}")
@@ -105,7 +105,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--fp64-tau", type=float, default=0.0,
+    ap.add_argument("--fp64-tau", type=float, default=float("inf"),
                     help="FP32 path: cells above this line-centre depth use a double frequency step")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -58,14 +58,14 @@ typedef enum {
 typedef enum { M1_CART2D = 0, M1_CYL_RZ = 1 } m1_geom;
 typedef enum { M1_BC_VACUUM = 0, M1_BC_REFLECT = 1 } m1_bc;
 /* State storage and arithmetic.  M1_FP64: everything in double.  M1_FP32:
- * state, opacities and transport arithmetic in float; the frequency step
- * (coefficients and subtraction-free elimination) in double for cells whose
- * line-centre optical depth exceeds fp64_tau (default 0: every cell), else in
- * float; force sums and residual norms in double.  A float frequency step
- * drifts by about one float ulp per step (its matrix barely changes from step
- * to step, so the rounding does not average out), which exceeds 1e-5 after a
- * few hundred steps; double arithmetic there keeps the error at the level of
- * the float storage. */
+ * state, opacities and transport arithmetic in float; in the frequency step
+ * the exponential-scheme coefficients are computed in float, or in double in
+ * cells whose line-centre optical depth exceeds fp64_tau, and the
+ * (subtraction-free) elimination always runs in double; force sums and
+ * residual norms are double.  The elimination needs double: its matrix barely
+ * changes from step to step, so float rounding there accumulates linearly
+ * (about one float ulp per step); with double elimination the error stays at
+ * the level of the float storage. */
 typedef enum { M1_FP64 = 0, M1_FP32 = 1 } m1_prec;
 
 typedef struct {
@@ -83,8 +83,9 @@ typedef struct {
   int32_t doppler;         /* 0/1: Doppler term of the frequency step */
   int32_t prec;            /* m1_prec */
   double fp64_tau;         /* FP32 only: line-centre cell optical depth above
-                              which a cell's frequency step runs in double
-                              (0: all cells; +inf: none) */
+                              which a cell's frequency-step coefficients are
+                              computed in double (+inf: none, the default;
+                              0: all cells) */
 } m1_config;
 
 /* Per-cell physical inputs, FP64, [ny][nx].  Host pointers when on_device is
@@ -105,7 +106,7 @@ typedef struct {
 typedef struct m1_handle m1_handle;
 
 /* Fills *cfg with the paper's defaults (T_min 30 K, q 1.1, half-width 1e5,
- * CFL 0.4, recoil and Doppler on, FP64, fp64_tau 0, vacuum boundaries). */
+ * CFL 0.4, recoil and Doppler on, FP64, fp64_tau +inf, vacuum boundaries). */
 int32_t m1_default_config(m1_config *cfg);
 
 /* Number of frequency bins of cfg's grid (194 with the defaults; Section 2.1). */

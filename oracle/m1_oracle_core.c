@@ -67,7 +67,7 @@ static double levermore_chi(double f) {
 
 static void eddington_tensor(double E, double Fx, double Fy,
                              double *Dxx, double *Dyy, double *Dxy, double *Dpp) {
-  double nF = sqrt(Fx * Fx + Fy * Fy);
+  double nF = hypot(Fx, Fy);      /* |F| without underflow of the squares */
   double f = (E > 0.0) ? nF / E : 0.0;
   if (f > 1.0) f = 1.0;
   double chi = levermore_chi(f);
@@ -391,7 +391,7 @@ static void advect_source_bin(const OracleProblem *P, const Geometry *G,
       /* causality: E >= 0 and |F| <= E at the cell centre */
       if (Es <= 0.0) { Es = 0.0; Xs = 0.0; Ys = 0.0; }
       else {
-        double nF = sqrt(Xs * Xs + Ys * Ys);
+        double nF = hypot(Xs, Ys);
         if (nF > Es) { Xs *= Es / nF; Ys *= Es / nF; }
       }
       /* implicit emission / absorption / destruction (BDF1, one substep) */

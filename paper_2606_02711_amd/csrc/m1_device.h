@@ -35,6 +35,7 @@ struct GridArgs {
   const double *dD2h;     // [ncls] 0.5 dnu_D^2
   const double *hkT;      // [ncls] h / (k_B T)
   const double *dnu;      // [nb] bin widths
+  const double *inv_dnu;  // [nb] 1 / bin widths
   const double *two_nu;   // [nb] 2 / nu_k
   const double *nu_c;     // [nb] nu_k / c
   // geometry per column (index i + 2, i in [-2, nx+1]) and per row
@@ -111,6 +112,23 @@ __device__ __forceinline__ Eddington<R> closure_state(R E, R Fx, R Fy) {
   const R n2 = fx * fx + fy * fy;
   const R sc = n2 > R(1) ? frsq(n2) : R(1);
   return closure_f(fx * sc, fy * sc);
+}
+
+// Scale s in (0, 1] with |s F| <= E for E > 0 (the causality condition
+// |H|/J <= 1).  The squares of tiny components underflow in float below
+// ~1e-19 (and in double below ~1e-154), which would hide a violation, so
+// small E is checked in double (float) or after scaling by 2^400 (double).
+template <typename R>
+__device__ __forceinline__ R causal_scale(R E, R X, R Y) {
+  const R tiny = sizeof(R) == 4 ? R(1e-18) : R(1e-150);
+  if (E >= tiny) {
+    const R q2 = X * X + Y * Y;
+    return q2 > E * E ? E * frsq(q2) : R(1);
+  }
+  const double sc = sizeof(R) == 4 ? 1.0 : 0x1p400;
+  const double e = (double)E * sc, x = (double)X * sc, y = (double)Y * sc;
+  const double q2 = x * x + y * y;
+  return q2 > e * e ? (R)(e / sqrt(q2)) : R(1);
 }
 
 template <typename R>

@@ -97,7 +97,7 @@ struct Layout {
   size_t zs, wsc, force;
   size_t cls, island, alpha, acF, acabs, pda, em, grad, ufx, ufy;
   size_t hbar, phi, dD2h, hkT;
-  size_t dnu, two_nu, nu_c, edges;
+  size_t dnu, inv_dnu, two_nu, nu_c, edges;
   size_t geo, xe, ye, nodes;
   size_t partial, result;
   size_t total;
@@ -130,6 +130,7 @@ Layout make_layout(int nx, int ny, int nb, int64_t ncls, size_t rs) {
   L.dD2h = take((size_t)ncls * sizeof(double));
   L.hkT = take((size_t)ncls * sizeof(double));
   L.dnu = take(nb * sizeof(double));
+  L.inv_dnu = take(nb * sizeof(double));
   L.two_nu = take(nb * sizeof(double));
   L.nu_c = take(nb * sizeof(double));
   L.edges = take((nb + 1) * sizeof(double));
@@ -226,6 +227,7 @@ void fill_args(m1_handle* h, GridArgs<R>* a) {
     g.dD2h = (const double*)(w + L.dD2h);
     g.hkT = (const double*)(w + L.hkT);
     g.dnu = (const double*)(w + L.dnu);
+    g.inv_dnu = (const double*)(w + L.inv_dnu);
     g.two_nu = (const double*)(w + L.two_nu);
     g.nu_c = (const double*)(w + L.nu_c);
     const R* geo = (const R*)(w + L.geo);
@@ -390,8 +392,13 @@ int init_typed(m1_handle* h, const m1_fields* f, const std::vector<std::vector<d
   h->e2 = e2;
 
   // per-bin constants, classes, Dawson nodes, geometry
-  std::vector<double> two_nu(nb), nu_c(nb);
-  for (int k = 0; k < nb; ++k) { two_nu[k] = 2.0 / g.nuc[k]; nu_c[k] = g.nuc[k] / kC; }
+  std::vector<double> two_nu(nb), nu_c(nb), inv_dnu(nb);
+  for (int k = 0; k < nb; ++k) {
+    two_nu[k] = 2.0 / g.nuc[k];
+    nu_c[k] = g.nuc[k] / kC;
+    inv_dnu[k] = 1.0 / g.dnu[k];
+  }
+  HIPCHK(hipMemcpyAsync(w + L.inv_dnu, inv_dnu.data(), nb * sizeof(double), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(w + L.dnu, g.dnu.data(), nb * sizeof(double), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(w + L.two_nu, two_nu.data(), nb * sizeof(double), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(w + L.nu_c, nu_c.data(), nb * sizeof(double), hipMemcpyHostToDevice, s));
@@ -475,7 +482,7 @@ int32_t m1_default_config(m1_config* c) {
   c->recoil = 1;
   c->doppler = 1;
   c->prec = M1_FP64;
-  c->fp64_tau = 0.0;
+  c->fp64_tau = INFINITY;
   return M1_OK;
 }
 

@@ -351,9 +351,8 @@ __global__ __launch_bounds__(256) void k_advect_source(GridArgs<R> a) {
       Es -= ctdt_c * (D.xx * gxx[m] + D.yy * gyy[m] + D.xy * gxy[m] + D.pp * gpp[m]) * EC;
       Xs += chp * D.pp * EC;
       // causality: E >= 0 and |F| <= E
-      const R q2 = Xs * Xs + Ys * Ys;
       const bool pos = Es > R(0);
-      const R cl = (pos && q2 > Es * Es) ? Es * frsq(q2) : R(1);
+      const R cl = pos ? causal_scale(Es, Xs, Ys) : R(1);
       Xs = pos ? Xs * cl : R(0);
       Ys = pos ? Ys * cl : R(0);
       Es = pos ? Es : R(0);
@@ -373,39 +372,41 @@ __global__ __launch_bounds__(256) void k_advect_source(GridArgs<R> a) {
 }
 
 // ---------------------------------------------------------------- K3
-// e^{-m} (e^z - 1)/z for m >= max(z, 0) without overflow.
+// E1(z) = (e^z - 1)/z by its Taylor series, for |z| < 1/2.
 template <typename T>
-__device__ __forceinline__ T shifted_E1(T z, T m) {
-  const T lim = sizeof(T) == 8 ? T(700) : T(80);
-  if (m < lim) return exp(-m) * (z == T(0) ? T(1) : expm1(z) / z);
-  if (z == T(0)) return exp(-m);
-  return (exp(z - m) - exp(-m)) / z;
+__device__ __forceinline__ T e1_series(T z) {
+  constexpr int n = sizeof(T) == 8 ? 16 : 9;     // last term < 2e-18 / 2e-9
+  T r = T(1);
+  for (int j = n; j >= 1; --j) r = T(1) + z * r / T(j + 1);
+  return r;
 }
 
-// Exponential-scheme interface between bins l < r: frequency flux
-// F = gr J_r - gl J_l with gl = e^{-Pl}/den, gr = e^{Pr}/den,
-// den = (dl/Kl)(1 - e^{-Pl})/Pl + (dr/Kr)(e^{Pr} - 1)/Pr, Pl = Cl dl/Kl,
-// Pr = Cr dr/Kr, all scaled by e^{-m}, m = max(-Pl, Pr, 0).  Without line
-// opacity (K = 0) the scheme's upwind limit.
+// Exponential-scheme interface between bins l < r (frequency flux
+// F = gr J_r - gl J_l):  gl = e^{A}/den, gr = e^{B}/den with A = -P_l =
+// -Cl ql, B = P_r = Cr qr, den = ql E1(A) + qr E1(B), ql = dl/Kl, qr = dr/Kr,
+// E1(z) = (e^z - 1)/z.  Numerator and denominator are scaled by e^{-m},
+// m = max(A, B, 0) (an exact rewrite), so every exponential is <= 1 and
+// e^{-m} E1(z) <= 2: nothing overflows at any Peclet number.  E1 is taken
+// from its series for |z| < 1/2, else from (e^{z-m} - e^{-m})/z.
 template <typename T>
-__device__ __forceinline__ void interface_rates(T Kl, T Cl, T dl, T Kr, T Cr, T dr,
-                                                T& gl, T& gr) {
-  if (Kl == T(0) || Kr == T(0)) {
-    gl = Cl < T(0) ? -Cl : T(0);
-    gr = Cr > T(0) ? Cr : T(0);
-    return;
-  }
-  T ql = dl / Kl, qr = dr / Kr;
-  T A = -Cl * ql, B = Cr * qr;
+__device__ __forceinline__ void interface_rates(T ql, T Cl, T qr, T Cr, T& gl, T& gr) {
+  // No contraction here: A - m must be exactly 0 on the dominant side.  A
+  // fused multiply-subtract of -Cl*ql - m would leave the rounding error of
+  // A (large when |A| ~ 1e10) in the exponent.
+#pragma clang fp contract(off)
+  const T A = -Cl * ql, B = Cr * qr;
   T m = A > B ? A : B;
-  if (m < T(0)) m = T(0);
-  T den = ql * shifted_E1(A, m) + qr * shifted_E1(B, m);
-  T iden = T(1) / den;
-  gl = exp(A - m) * iden;
-  gr = exp(B - m) * iden;
+  m = m > T(0) ? m : T(0);
+  const T eAm = exp(A - m), eBm = exp(B - m), em = exp(-m);
+  const T sA = fabs(A) < T(0.5) ? em * e1_series(A) : (eAm - em) / A;
+  const T sB = fabs(B) < T(0.5) ? em * e1_series(B) : (eBm - em) / B;
+  const T iden = T(1) / (ql * sA + qr * sB);
+  gl = eAm * iden;
+  gr = eBm * iden;
 }
 
-// Frequency step and force of one cell.  R: storage type, T: arithmetic type.
+// Frequency step and force of one cell.  R: storage type; T: arithmetic of
+// the exponential-scheme coefficients.  The elimination always runs in double.
 //
 // Photon-number variables y_k = dnu_k E_k.  The BDF1 system is
 //   (1 + a_k + b_k) y_k - b_{k+1} y_{k+1} - a_{k-1} y_{k-1} = y_k^{old},
@@ -422,85 +423,84 @@ __device__ void freq_cell(const GridArgs<R>& a, size_t c) {
   const int nb = a.nb;
   const int cl = a.cls[c];
   const T al = (T)a.alpha[c];
-  const T acF = (T)a.acF[c];
+  const double acF = (double)a.acF[c];
   const T gxx = (T)a.grad[c], gyy = (T)a.grad[nc + c], gxy = (T)a.grad[2 * nc + c],
           gpp = (T)a.grad[3 * nc + c];
-  const T dd = (T)a.dD2h[cl] * al;
+  const T dd = (T)a.dD2h[cl] * al;           // 0.5 dnu_D^2 alpha
   const T hkT = (T)a.hkT[cl];
-  const T ctdt = (T)a.ctdt;
+  const double ctdt = (double)a.ctdt;
   const R* hb = a.hbar + (size_t)cl * nb;
   const bool use_recoil = a.recoil != 0;
   const bool use_doppler = a.doppler != 0 &&
       ((gxx != T(0)) || (gyy != T(0)) || (gxy != T(0)) || (gpp != T(0)));
 
   double fx = 0.0, fy = 0.0, gx = 0.0, gy = 0.0;
-  auto coeffs = [&](int k, T& K, T& C) {
-    const size_t q = (size_t)k * nc + c;
-    const R e = a.Eo[q], X = a.Fxo[q], Y = a.Fyo[q];
-    const T h = (T)hb[k];
-    K = dd * h;
-    C = T(0);
-    if (use_recoil) C += K * (hkT - (T)a.two_nu[k]);
+  // coefficients of bin k: q = (dnu_k/2)/K_k and C_k (Appendix A)
+  auto coeffs = [&](int k, T& q, T& C) {
+    const size_t idx = (size_t)k * nc + c;
+    const R e = a.Eo[idx], X = a.Fxo[idx], Y = a.Fyo[idx];
+    const R h = hb[k];
+    const T K = dd * (T)h;
+    T Cv = T(0);
+    if (use_recoil) Cv += K * (hkT - (T)a.two_nu[k]);
     if (use_doppler) {
-      Eddington<T> D = closure_state<T>((T)e, (T)X, (T)Y);
-      C += (T)a.nu_c[k] * (D.xx * gxx + D.yy * gyy + D.xy * gxy + D.pp * gpp);
+      const Eddington<T> D = closure_state<T>((T)e, (T)X, (T)Y);
+      Cv += (T)a.nu_c[k] * (D.xx * gxx + D.yy * gyy + D.xy * gxy + D.pp * gpp);
     }
+    C = Cv;
+    q = K > T(0) ? T(0.5 * a.dnu[k]) / K : T(0);     // 0 flags "no line opacity"
     // force density: sum_k dnu_k alpha_F,k F**_k (and the line part)
     const double dn = a.dnu[k];
     const double aH = (double)al * (double)h;
-    const double aF = aH + (double)acF;
+    const double aF = aH + acF;
     fx += dn * aF * (double)X;
     fy += dn * aF * (double)Y;
     gx += dn * aH * (double)X;
     gy += dn * aH * (double)Y;
   };
 
-  T Kc, Cc;
-  coeffs(0, Kc, Cc);
-  T s_prev = T(1), p_prev = T(1), d_prev = T(0), a_prev = T(0);
-  T b_k = T(0);             // rate of bin k toward k-1 (zero at the lower end)
+  T qc, Cc;
+  coeffs(0, qc, Cc);
+  double s_prev = 1.0, ip_prev = 1.0, d_prev = 0.0, a_prev = 0.0;
+  double b_k = 0.0;                // rate of bin k toward k-1 (zero at the lower end)
   for (int k = 0; k < nb; ++k) {
-    T a_k = T(0), b_next = T(0);
-    const T dnk = (T)a.dnu[k];
+    double a_k = 0.0, b_next = 0.0;
     if (k + 1 < nb) {
-      T Kn, Cn;
-      coeffs(k + 1, Kn, Cn);
-      const T dnn = (T)a.dnu[k + 1];
+      T qn, Cn;
+      coeffs(k + 1, qn, Cn);
       T gl, gr;
-      interface_rates<T>(Kc, Cc, T(0.5) * dnk, Kn, Cn, T(0.5) * dnn, gl, gr);
-      a_k = ctdt * gl / dnk;
-      b_next = ctdt * gr / dnn;
-      Kc = Kn;
+      if (qc > T(0) && qn > T(0)) {
+        interface_rates<T>(qc, Cc, qn, Cn, gl, gr);
+      } else {
+        gl = Cc < T(0) ? -Cc : T(0);       // K -> 0: first-order upwind
+        gr = Cn > T(0) ? Cn : T(0);
+      }
+      a_k = ctdt * (double)gl * a.inv_dnu[k];
+      b_next = ctdt * (double)gr * a.inv_dnu[k + 1];
+      qc = qn;
       Cc = Cn;
     }
-    const size_t q = (size_t)k * nc + c;
-    const T y = dnk * (T)a.Eo[q];
-    T s, d;
-    if (k == 0) { s = T(1); d = y; }
-    else {
-      const T r = T(1) / p_prev;
-      s = T(1) + b_k * s_prev * r;
-      d = y + a_prev * d_prev * r;
-    }
-    const T p = s + a_k;
-    const T ip = T(1) / p;
-    a.zs[q] = (R)(d * ip);
-    a.ws[q] = (R)(b_next * ip);
-    s_prev = s; p_prev = p; d_prev = d; a_prev = a_k; b_k = b_next;
+    const size_t idx = (size_t)k * nc + c;
+    const double y = a.dnu[k] * (double)a.Eo[idx];
+    const double s = (k == 0) ? 1.0 : 1.0 + b_k * s_prev * ip_prev;
+    const double d = (k == 0) ? y : y + a_prev * d_prev * ip_prev;
+    const double p = s + a_k;
+    const double ip = 1.0 / p;
+    a.zs[idx] = (R)(d * ip);
+    a.ws[idx] = (R)(b_next * ip);
+    s_prev = s; ip_prev = ip; d_prev = d; a_prev = a_k; b_k = b_next;
   }
-  // back substitution and F rescale (F^{n+1} = F** E^{n+1}/E**)
-  T y = T(0);
+  // back substitution and F rescale (F^{n+1} = (F**/E**) E^{n+1})
+  double y = 0.0;
   for (int k = nb - 1; k >= 0; --k) {
-    const size_t q = (size_t)k * nc + c;
-    y = (T)a.zs[q] + (T)a.ws[q] * y;
-    const T En = y / (T)a.dnu[k];
-    const T Eo = (T)a.Eo[q];
-    // F^{n+1} = (F**/E**) E^{n+1}, with |F**/E**| <= 1
-    T fxo, fyo;
-    reduced_flux<T>(Eo, (T)a.Fxo[q], (T)a.Fyo[q], fxo, fyo);
-    a.Eo[q] = (R)En;
-    a.Fxo[q] = (R)(fxo * En);
-    a.Fyo[q] = (R)(fyo * En);
+    const size_t idx = (size_t)k * nc + c;
+    y = (double)a.zs[idx] + (double)a.ws[idx] * y;
+    const R En = (R)(y * a.inv_dnu[k]);
+    R fxo, fyo;
+    reduced_flux<R>(a.Eo[idx], a.Fxo[idx], a.Fyo[idx], fxo, fyo);
+    a.Eo[idx] = En;
+    a.Fxo[idx] = fxo * En;
+    a.Fyo[idx] = fyo * En;
   }
   a.force[c] = fx;
   a.force[nc + c] = fy;

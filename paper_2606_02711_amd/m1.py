@@ -17,7 +17,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libm1lya.so")
+LIB_PATH = os.environ.get("M1LYA_LIB", os.path.join(HERE, "libm1lya.so"))
 
 M1_OK, M1_EINVAL, M1_ENOMEM, M1_EDEVICE, M1_ENOTCONV, M1_ESTATE, M1_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 M1_CART2D, M1_CYL_RZ = 0, 1
@@ -103,7 +103,7 @@ def check(code):
 BC = {"vacuum": M1_BC_VACUUM, "reflect": M1_BC_REFLECT}
 
 
-def make_config(p, prec="fp64", fp64_tau=0.0):
+def make_config(p, prec="fp64", fp64_tau=float("inf")):
     c = m1_config()
     check(lib().m1_default_config(ctypes.byref(c)))
     c.geom = M1_CYL_RZ if p["geom"] == "cyl" else M1_CART2D
@@ -153,7 +153,7 @@ class M1Grid:
 
     p: problem dict (see inputs.py); prec: "fp64" or "fp32"."""
 
-    def __init__(self, p, prec="fp64", fp64_tau=0.0, stream=None, workspace=None):
+    def __init__(self, p, prec="fp64", fp64_tau=float("inf"), stream=None, workspace=None):
         torch = _torch()
         self.p = p
         self.prec = prec

@@ -40,6 +40,7 @@ def compare(p, steps, prec, tolE, tolF, oracle=None):
     assert errs["E"] <= tolE and errs["Fx"] <= tolE and errs["Fy"] <= tolE, errs
     assert errs["force"] <= tolF, errs
     assert np.all(np.isfinite(E)) and E.min() >= 0
+    assert np.all(np.isfinite(Fx)) and np.all(np.isfinite(Fy)) and np.all(np.isfinite(f))
     return g, errs
 
 
