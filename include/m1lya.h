@@ -166,10 +166,30 @@ int32_t m1_set_state(m1_handle *h, const double *d_E, const double *d_Fx,
 int32_t m1_get_info(const m1_handle *h, double *dt, int32_t *n_nu, int32_t *prec,
                     int64_t *ncell, int32_t *scale_exp2);
 
-/* Advances n handles (same precision, same stream) by nsteps steps with one
- * batched launch per kernel and step; bitwise identical to stepping each
- * handle alone.  Enqueued on the first handle's stream. */
-int32_t m1_step_batched(m1_handle *const *hs, int32_t n, int32_t nsteps);
+/* ---- batches: many grids advanced by one persistent launch per kernel and
+ * step (the spec batching addition; no counterpart in the paper).
+ * A batch groups n handles of the same precision on the same stream.  Its
+ * descriptor tables live in a caller workspace of m1_batch_workspace_bytes
+ * bytes (256-byte aligned); the library allocates no device memory.  Every
+ * grid's result is bitwise identical to stepping it alone.
+ *
+ * m1_batch_step: the first steps of a new batch time each tile variant
+ * (bins per advection block) on real steps, which give identical results
+ * for every variant, and keep the fastest; afterwards pairs of steps are
+ * replayed from a captured HIP graph when use_graph is set and the stream
+ * is not the null stream.  Stepping a member handle on its own between
+ * batch steps is allowed (the batch re-reads the ping-pong parities). */
+typedef struct m1_batch m1_batch;
+int32_t m1_batch_workspace_bytes(m1_handle *const *hs, int32_t n, size_t *bytes);
+int32_t m1_batch_init(m1_handle *const *hs, int32_t n, void *d_ws, size_t ws_bytes,
+                      int32_t use_graph, m1_batch **out);
+int32_t m1_batch_step(m1_batch *b, int32_t nsteps);
+/* Chosen variant (bins per advection block, or 0 while tuning) and the
+ * measured advection-kernel time of each variant [ms per step]. */
+int32_t m1_batch_info(const m1_batch *b, int32_t *bins_per_block, double *ms_per_variant,
+                      int32_t n_variants);
+/* Waits for the stream, then releases the host object (not the workspace). */
+int32_t m1_batch_free(m1_batch *b);
 
 int32_t m1_sync(m1_handle *h);         /* waits for the stream; surfaces faults */
 int32_t m1_free(m1_handle *h);         /* frees the host handle, not the workspace */

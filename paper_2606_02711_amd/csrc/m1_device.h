@@ -73,9 +73,11 @@ template <typename R>
 __device__ __forceinline__ Eddington<R> closure_f(R fx, R fy) {
   R f2 = fx * fx + fy * fy;
   f2 = f2 > R(1) ? R(1) : f2;
-  R s = fsqrt(R(4) - R(3) * f2);          // in [1, 2]
-  R iso = (R(1) - f2) * frcp(R(1) + s);
-  R g = R(3) * frcp(R(2) + s);
+  const R s = fsqrt(R(4) - R(3) * f2);    // in [1, 2]
+  // one reciprocal for both 1/(1+s) and 1/(2+s)
+  const R r = frcp((R(1) + s) * (R(2) + s));
+  const R iso = (R(1) - f2) * (R(2) + s) * r;
+  const R g = R(3) * (R(1) + s) * r;
   Eddington<R> d;
   d.xx = iso + g * fx * fx;
   d.yy = iso + g * fy * fy;
@@ -123,7 +125,9 @@ __device__ __forceinline__ R causal_scale(R E, R X, R Y) {
   const R tiny = sizeof(R) == 4 ? R(1e-18) : R(1e-150);
   if (E >= tiny) {
     const R q2 = X * X + Y * Y;
-    return q2 > E * E ? E * frsq(q2) : R(1);
+    R sc = R(1);
+    if (q2 > E * E) sc = E * frsq(q2);      // rare: branch, not select
+    return sc;
   }
   const double sc = sizeof(R) == 4 ? 1.0 : 0x1p400;
   const double e = (double)E * sc, x = (double)X * sc, y = (double)Y * sc;

@@ -655,19 +655,260 @@ int32_t m1_step_profiled(m1_handle* h, int32_t nsteps, double* ms) {
   return st;
 }
 
-int32_t m1_step_batched(m1_handle* const* hs, int32_t n, int32_t nsteps) {
-  if (!hs || n <= 0 || nsteps < 0) return fail(M1_EINVAL, "bad arguments");
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+struct m1_batch {
+  std::vector<m1_handle*> hs;
+  int n = 0;
+  int prec = 0;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t args_off = 0, par_off = 0, offa_off = 0, offf_off = 0;
+  std::vector<int> par;                 // base parity per grid
+  int sp = 0;                           // steps taken mod 2
+  int blocks_adv[kNumBatchVariants] = {0, 0, 0, 0};
+  int blocks_freq = 0;
+  int variant = -1;                     // chosen tile variant (-1: tuning)
+  int trial_variant = 0, trial_step = 0;
+  double trial_ms[kNumBatchVariants] = {0, 0, 0, 0};
+  bool use_graph = false;
+  hipGraphExec_t exec = nullptr;
+  int graph_sp = -1;                    // parity at which the graph starts
+};
+
+namespace {
+constexpr int kTrialSteps = 2;          // timed steps per variant while tuning
+
+size_t batch_layout(m1_handle* const* hs, int n, size_t* args_off, size_t* par_off,
+                    size_t* offa_off, size_t* offf_off) {
+  size_t rs = hs[0]->cfg.prec == M1_FP32 ? sizeof(GridArgs<float>) : sizeof(GridArgs<double>);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+  *args_off = take(2 * (size_t)n * rs);
+  *par_off = take((size_t)n * sizeof(int));
+  *offa_off = take((size_t)kNumBatchVariants * (n + 1) * sizeof(int));
+  *offf_off = take((size_t)(n + 1) * sizeof(int));
+  return off;
+}
+
+int check_members(m1_handle* const* hs, int n) {
+  if (!hs || n <= 0) return fail(M1_EINVAL, "empty batch");
   for (int q = 0; q < n; ++q) {
     if (!hs[q]) return fail(M1_EINVAL, "handle %d is NULL", q);
     if (hs[q]->broken) return fail(M1_ESTATE, "handle %d had a device error", q);
-    if (hs[q]->cfg.prec != hs[0]->cfg.prec) return fail(M1_EINVAL, "mixed precisions");
+    if (hs[q]->cfg.prec != hs[0]->cfg.prec) return fail(M1_EINVAL, "mixed precisions in a batch");
+    if (hs[q]->stream != hs[0]->stream) return fail(M1_EINVAL, "batch members must share a stream");
+    for (int r = 0; r < q; ++r)
+      if (hs[r] == hs[q]) return fail(M1_EINVAL, "handle %d appears twice", q);
   }
-  hipStream_t s = hs[0]->stream;
-  for (int t = 0; t < nsteps; ++t)
+  return M1_OK;
+}
+
+template <typename R>
+int upload_args(m1_batch* b) {
+  std::vector<GridArgs<R>> args(2 * (size_t)b->n);
+  for (int q = 0; q < b->n; ++q) {
+    const GridArgs<R>* src = (b->prec == M1_FP32) ? (const GridArgs<R>*)b->hs[q]->af
+                                                  : (const GridArgs<R>*)b->hs[q]->ad;
+    args[q] = src[0];
+    args[b->n + q] = src[1];
+  }
+  HIPCHK(hipMemcpyAsync(b->ws + b->args_off, args.data(), args.size() * sizeof(GridArgs<R>),
+                        hipMemcpyHostToDevice, b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  return M1_OK;
+}
+
+int sync_parity(m1_batch* b) {
+  bool same = true;
+  for (int q = 0; q < b->n; ++q)
+    if ((b->par[q] ^ b->sp) != b->hs[q]->cur) same = false;
+  if (same) return M1_OK;
+  for (int q = 0; q < b->n; ++q) b->par[q] = b->hs[q]->cur ^ b->sp;
+  HIPCHK(hipMemcpyAsync(b->ws + b->par_off, b->par.data(), b->n * sizeof(int),
+                        hipMemcpyHostToDevice, b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; b->graph_sp = -1; }
+  return M1_OK;
+}
+
+template <typename R>
+hipError_t batch_launch_step(m1_batch* b, int variant) {
+  const GridArgs<R>* args = (const GridArgs<R>*)(b->ws + b->args_off);
+  const int* par = (const int*)(b->ws + b->par_off);
+  const int* offa = (const int*)(b->ws + b->offa_off) + (size_t)variant * (b->n + 1);
+  const int* offf = (const int*)(b->ws + b->offf_off);
+  hipError_t e = launch_advect_batched<R>(variant, args, par, b->n, b->sp, offa,
+                                          b->blocks_adv[variant], b->stream);
+  if (e != hipSuccess) return e;
+  return launch_freq_batched<R>(args, par, b->n, b->sp, offf, b->blocks_freq, b->stream);
+}
+
+hipError_t batch_one_step(m1_batch* b, int variant) {
+  hipError_t e = b->prec == M1_FP32 ? batch_launch_step<float>(b, variant)
+                                    : batch_launch_step<double>(b, variant);
+  if (e != hipSuccess) return e;
+  b->sp ^= 1;
+  for (auto* h : b->hs) { h->cur ^= 1; h->steps += 1; h->t += h->dt; }
+  return hipSuccess;
+}
+}  // namespace
+
+extern "C" {
+
+int32_t m1_batch_workspace_bytes(m1_handle* const* hs, int32_t n, size_t* bytes) {
+  if (!bytes) return fail(M1_EINVAL, "bytes is NULL");
+  int st = check_members(hs, n);
+  if (st) return st;
+  size_t a, p, oa, of;
+  *bytes = batch_layout(hs, n, &a, &p, &oa, &of);
+  return M1_OK;
+}
+
+int32_t m1_batch_init(m1_handle* const* hs, int32_t n, void* d_ws, size_t ws_bytes,
+                      int32_t use_graph, m1_batch** out) {
+  if (!out) return fail(M1_EINVAL, "out is NULL");
+  *out = nullptr;
+  int st = check_members(hs, n);
+  if (st) return st;
+  if (!d_ws || (((uintptr_t)d_ws) & 255)) return fail(M1_EINVAL, "workspace NULL or not 256-byte aligned");
+  m1_batch* b = new m1_batch();
+  b->hs.assign(hs, hs + n);
+  b->n = n;
+  b->prec = hs[0]->cfg.prec;
+  b->stream = hs[0]->stream;
+  b->ws = (char*)d_ws;
+  size_t need = batch_layout(hs, n, &b->args_off, &b->par_off, &b->offa_off, &b->offf_off);
+  if (ws_bytes < need) { delete b; return fail(M1_ENOMEM, "batch workspace %zu < %zu", ws_bytes, need); }
+  b->use_graph = use_graph != 0 && b->stream != nullptr;
+  // work lists: prefix sums of work items per grid, per tile variant
+  std::vector<int> offa((size_t)kNumBatchVariants * (n + 1)), offf(n + 1, 0);
+  int64_t tot[kNumBatchVariants] = {0, 0, 0, 0};
+  for (int v = 0; v < kNumBatchVariants; ++v) {
+    offa[(size_t)v * (n + 1)] = 0;
     for (int q = 0; q < n; ++q) {
-      int st = enqueue_step(hs[q], s);
-      if (st) return st;
+      tot[v] += advect_blocks(hs[q]->cfg.nx, hs[q]->cfg.ny, hs[q]->nb, kBatchBK[v]);
+      if (tot[v] > INT32_MAX / 2) { delete b; return fail(M1_EUNSUPPORTED, "batch too large"); }
+      offa[(size_t)v * (n + 1) + q + 1] = (int)tot[v];
     }
+  }
+  int64_t totf = 0;
+  for (int q = 0; q < n; ++q) {
+    totf += freq_blocks(hs[q]->cfg.nx, hs[q]->cfg.ny);
+    offf[q + 1] = (int)totf;
+  }
+  int dev = 0, ncu = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+    ncu = 256;
+  for (int v = 0; v < kNumBatchVariants; ++v) {
+    int occ = b->prec == M1_FP32 ? batched_occupancy<float>(v) : batched_occupancy<double>(v);
+    b->blocks_adv[v] = (int)std::min<int64_t>(tot[v], (int64_t)ncu * occ);
+  }
+  int occf = b->prec == M1_FP32 ? freq_batched_occupancy<float>() : freq_batched_occupancy<double>();
+  b->blocks_freq = (int)std::min<int64_t>(totf, (int64_t)ncu * occf);
+  b->par.resize(n);
+  for (int q = 0; q < n; ++q) b->par[q] = hs[q]->cur;
+  b->sp = 0;
+  hipError_t e = hipMemcpyAsync(b->ws + b->offa_off, offa.data(), offa.size() * sizeof(int),
+                                hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->ws + b->offf_off, offf.data(), offf.size() * sizeof(int),
+                       hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->ws + b->par_off, b->par.data(), n * sizeof(int), hipMemcpyHostToDevice,
+                       b->stream);
+  if (e != hipSuccess) { delete b; return fail(M1_EDEVICE, "batch upload: %s", hipGetErrorString(e)); }
+  st = b->prec == M1_FP32 ? upload_args<float>(b) : upload_args<double>(b);
+  if (st) { delete b; return st; }
+  *out = b;
+  return M1_OK;
+}
+
+int32_t m1_batch_step(m1_batch* b, int32_t nsteps) {
+  if (!b) return fail(M1_EINVAL, "batch is NULL");
+  if (nsteps < 0) return fail(M1_EINVAL, "nsteps < 0");
+  for (auto* h : b->hs)
+    if (h->broken) return fail(M1_ESTATE, "a batch member had a device error");
+  int st = sync_parity(b);
+  if (st) return st;
+  int left = nsteps;
+  // autotuning on real steps: time each variant's steps with events
+  while (left > 0 && b->variant < 0) {
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, b->stream));
+    hipError_t e = batch_one_step(b, b->trial_variant);
+    if (e != hipSuccess) { b->hs[0]->broken = true; return fail(M1_EDEVICE, "batch step: %s", hipGetErrorString(e)); }
+    HIPCHK(hipEventRecord(e1, b->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (b->trial_step > 0) b->trial_ms[b->trial_variant] += ms;   // first step warms up
+    --left;
+    if (++b->trial_step == kTrialSteps + 1) {
+      b->trial_ms[b->trial_variant] /= kTrialSteps;
+      b->trial_step = 0;
+      if (++b->trial_variant == kNumBatchVariants) {
+        int best = 0;
+        for (int v = 1; v < kNumBatchVariants; ++v)
+          if (b->trial_ms[v] < b->trial_ms[best]) best = v;
+        b->variant = best;
+      }
+    }
+  }
+  while (left > 0) {
+    if (b->use_graph && left >= 2) {
+      if (!b->exec || b->graph_sp != b->sp) {
+        if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        int sp0 = b->sp;
+        hipError_t e1 = b->prec == M1_FP32 ? batch_launch_step<float>(b, b->variant)
+                                           : batch_launch_step<double>(b, b->variant);
+        b->sp ^= 1;
+        hipError_t e2 = e1 == hipSuccess ? (b->prec == M1_FP32 ? batch_launch_step<float>(b, b->variant)
+                                                               : batch_launch_step<double>(b, b->variant))
+                                         : e1;
+        b->sp = sp0;
+        hipError_t ec = hipStreamEndCapture(b->stream, &g);
+        if (e2 != hipSuccess || ec != hipSuccess) {
+          if (g) (void)hipGraphDestroy(g);
+          return fail(M1_EDEVICE, "graph capture failed: %s", hipGetErrorString(e2 != hipSuccess ? e2 : ec));
+        }
+        hipError_t ei = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) { b->exec = nullptr; return fail(M1_EDEVICE, "graph instantiate: %s", hipGetErrorString(ei)); }
+        b->graph_sp = b->sp;
+      }
+      HIPCHK(hipGraphLaunch(b->exec, b->stream));
+      for (int r = 0; r < 2; ++r)
+        for (auto* h : b->hs) { h->cur ^= 1; h->steps += 1; h->t += h->dt; }
+      left -= 2;
+    } else {
+      hipError_t e = batch_one_step(b, b->variant);
+      if (e != hipSuccess) { b->hs[0]->broken = true; return fail(M1_EDEVICE, "batch step: %s", hipGetErrorString(e)); }
+      --left;
+    }
+  }
+  return M1_OK;
+}
+
+int32_t m1_batch_info(const m1_batch* b, int32_t* bins_per_block, double* ms, int32_t nv) {
+  if (!b) return fail(M1_EINVAL, "batch is NULL");
+  if (bins_per_block) *bins_per_block = b->variant >= 0 ? kBatchBK[b->variant] : 0;
+  for (int v = 0; ms && v < nv && v < kNumBatchVariants; ++v) ms[v] = b->trial_ms[v];
+  return M1_OK;
+}
+
+int32_t m1_batch_free(m1_batch* b) {
+  if (b) (void)hipStreamSynchronize(b->stream);   // launches in flight read the workspace
+  if (b && b->exec) (void)hipGraphExecDestroy(b->exec);
+  delete b;
   return M1_OK;
 }
 

@@ -16,6 +16,23 @@ template <typename R>
 hipError_t launch_advect(const GridArgs<R>& a, hipStream_t s);
 template <typename R>
 hipError_t launch_freq(const GridArgs<R>& a, hipStream_t s);
+// ---- batched persistent launches (one launch per kernel and step for a
+//      set of grids); variant selects the bins-per-block run length
+constexpr int kNumBatchVariants = 4;
+extern const int kBatchBK[kNumBatchVariants];
+int advect_blocks(int nx, int ny, int nb, int bk);
+int freq_blocks(int nx, int ny);
+template <typename R>
+hipError_t launch_advect_batched(int variant, const GridArgs<R>* args, const int* par, int n,
+                                 int sp, const int* off, int nblocks, hipStream_t s);
+template <typename R>
+hipError_t launch_freq_batched(const GridArgs<R>* args, const int* par, int n, int sp,
+                               const int* off, int nblocks, hipStream_t s);
+template <typename R>
+int batched_occupancy(int variant);
+template <typename R>
+int freq_batched_occupancy();
+
 template <typename R>
 hipError_t launch_residual(const R* E0, const R* E1, size_t n, double* partial, int nblk,
                            double* out, hipStream_t s);

@@ -94,8 +94,8 @@ __device__ __forceinline__ Flux3<R> face_flux(R eLL, R xLL, R yLL, R eL, R xL, R
   R fyR = yR + minmod(dY, (yRR - yR) * iRR) * hR;
   // causality at the interface: |f| > 1 is scaled back to 1
   const R nL = fxL * fxL + fyL * fyL, nR = fxR * fxR + fyR * fyR;
-  const R sL = nL > R(1) ? frsq(nL) : R(1), sR = nR > R(1) ? frsq(nR) : R(1);
-  fxL *= sL; fyL *= sL; fxR *= sR; fyR *= sR;
+  if (nL > R(1)) { const R sL = frsq(nL); fxL *= sL; fyL *= sL; }   // rare
+  if (nR > R(1)) { const R sR = frsq(nR); fxR *= sR; fyR *= sR; }
   Eddington<R> DL = closure_f(fxL, fyL), DR = closure_f(fxR, fyR);
   R FxL = fxL * EL, FyL = fyL * EL, FxR = fxR * ER, FyR = fyR * ER;
   R PxL, PyL, PxR, PyR;       // row n of the pressure tensor, P = D E
@@ -178,13 +178,13 @@ __device__ __forceinline__ bool ghost_source(int ii, int jj, int nx, int ny, con
 
 constexpr int kRingPerLane = (kRX * kRY + 255) / 256;   // 3
 
+// One tile x run of bins (logical block L of grid a).
 template <typename R, int BK>
-__global__ __launch_bounds__(256) void k_advect_source(GridArgs<R> a) {
-  __shared__ AdvShared<R> S;
+__device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigned L,
+                                             AdvShared<R>& S) {
   const int nx = a.nx, ny = a.ny, nb = a.nb;
   const size_t nc = (size_t)nx * ny;
   const int nbx = (nx + kTX - 1) / kTX, nby = (ny + kTY - 1) / kTY;
-  const unsigned L = xcd_logical_block();
   const int bx = (int)(L % (unsigned)nbx);
   const unsigned t1 = L / (unsigned)nbx;
   const int by = (int)(t1 % (unsigned)nby);
@@ -193,7 +193,6 @@ __global__ __launch_bounds__(256) void k_advect_source(GridArgs<R> a) {
   const int kend = min(k0 + BK, nb);
   const int tid = threadIdx.x;
   const R inv_c = R(1.0 / kC);
-  const bool interior = x0 >= 2 && x0 + kTX + 2 <= nx && y0 >= 2 && y0 + kTY + 2 <= ny;
 
   // ---- once per block: ring opacities (registers), geometry and face
   //      velocities (LDS)
@@ -270,30 +269,60 @@ __global__ __launch_bounds__(256) void k_advect_source(GridArgs<R> a) {
   }
   const R ctdt = a.ctdt, ctdt_c = a.ctdt_c;
 
+  // staging entries of this lane (fixed for all bins): source offset within a
+  // bin, or -1 for a vacuum / unused entry, and the mirror signs of f
+  // (hoisted only for double: in float the registers cost an occupancy step)
+  constexpr bool kHoist = sizeof(R) == 8;
+  constexpr int kStage = kHoist ? (kPX * kPY + 255) / 256 : 1;
+  int soff[kStage];
+  R ssx[kStage], ssy[kStage];
+#pragma unroll
+  for (int m = 0; m < kStage; ++m) {
+    const int e = tid + 256 * m;
+    soff[m] = -1; ssx[m] = R(1); ssy[m] = R(1);
+    if (e < kPX * kPY) {
+      const int pi = e % kPX, pj = e / kPX;
+      int si, sj, sgx, sgy;
+      bool vac;
+      if (ghost_source(x0 + pi - 2, y0 + pj - 2, nx, ny, a.bc, 2, si, sj, sgx, sgy, vac) && !vac) {
+        soff[m] = sj * nx + si;
+        ssx[m] = R(sgx); ssy[m] = R(sgy);
+      }
+    }
+  }
+
   for (int k = k0; k < kend; ++k) {
     const size_t koff = (size_t)k * nc;
     const R* hb = a.hbar + k;
+    const R* Ek = a.E + koff;
+    const R* Xk = a.Fx + koff;
+    const R* Yk = a.Fy + koff;
     // (1) stage E and f of the padded tile, and alpha_F of the ring
-    if (interior) {
-      for (int e = tid; e < kPX * kPY; e += 256) {
-        const int pi = e % kPX, pj = e / kPX;
-        const size_t q = koff + (size_t)(y0 + pj - 2) * nx + (x0 + pi - 2);
-        const R ev = a.E[q];
-        R fxv, fyv;
-        reduced_flux(ev, a.Fx[q], a.Fy[q], fxv, fyv);
-        S.E[pj][pi] = ev; S.fx[pj][pi] = fxv; S.fy[pj][pi] = fyv;
+    if constexpr (kHoist) {
+#pragma unroll
+    for (int m = 0; m < kStage; ++m) {
+      const int e = tid + 256 * m;
+      if (e < kPX * kPY) {
+        R ev = R(0), fxv = R(0), fyv = R(0);
+        if (soff[m] >= 0) {
+          ev = Ek[soff[m]];
+          reduced_flux(ev, Xk[soff[m]], Yk[soff[m]], fxv, fyv);
+          fxv *= ssx[m];
+          fyv *= ssy[m];
+        }
+        (&S.E[0][0])[e] = ev; (&S.fx[0][0])[e] = fxv; (&S.fy[0][0])[e] = fyv;
       }
+    }
     } else {
       for (int e = tid; e < kPX * kPY; e += 256) {
         const int pi = e % kPX, pj = e / kPX;
         int si, sj, sgx, sgy;
         bool vac;
         R ev = R(0), fxv = R(0), fyv = R(0);
-        if (ghost_source(x0 + pi - 2, y0 + pj - 2, nx, ny, a.bc, 2, si, sj, sgx, sgy, vac) &&
-            !vac) {
-          const size_t q = koff + (size_t)sj * nx + si;
-          ev = a.E[q];
-          reduced_flux(ev, a.Fx[q], a.Fy[q], fxv, fyv);
+        if (ghost_source(x0 + pi - 2, y0 + pj - 2, nx, ny, a.bc, 2, si, sj, sgx, sgy, vac) && !vac) {
+          const int q = sj * nx + si;
+          ev = Ek[q];
+          reduced_flux(ev, Xk[q], Yk[q], fxv, fyv);
           fxv *= R(sgx);
           fyv *= R(sgy);
         }
@@ -368,6 +397,33 @@ __global__ __launch_bounds__(256) void k_advect_source(GridArgs<R> a) {
       a.Fyo[q] = Ys * dF;
     }
     __syncthreads();
+  }
+}
+
+template <typename R, int BK>
+__global__ __launch_bounds__(256) void k_advect_source(GridArgs<R> a) {
+  __shared__ AdvShared<R> S;
+  advect_block<R, BK>(a, xcd_logical_block(), S);
+}
+
+// Batched, persistent advection: blocks walk the work items (grid, tile x
+// run of bins) of every grid of a batch in a fixed order.  off[g] is the
+// first work item of grid g (off[n] = total); args holds both ping-pong
+// directions, [2][n]; grid g uses direction par[g] ^ sp.
+template <typename R, int BK>
+__global__ __launch_bounds__(256) void k_advect_batched(const GridArgs<R>* __restrict__ args,
+                                                        const int* __restrict__ par, int n,
+                                                        int sp, const int* __restrict__ off) {
+  __shared__ AdvShared<R> S;
+  const int total = off[n];
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (off[mid] <= w) lo = mid; else hi = mid;
+    }
+    const GridArgs<R>& a = args[((par[lo] ^ sp) & 1) * n + lo];
+    advect_block<R, BK>(a, (unsigned)(w - off[lo]), S);
   }
 }
 
@@ -509,11 +565,34 @@ __device__ void freq_cell(const GridArgs<R>& a, size_t c) {
 }
 
 template <typename R>
+__device__ __forceinline__ void freq_dispatch(const GridArgs<R>& a, size_t c) {
+  if (sizeof(R) == 8 || a.island[c]) freq_cell<R, double>(a, c);
+  else freq_cell<R, float>(a, c);
+}
+
+template <typename R>
 __global__ __launch_bounds__(256) void k_freq(GridArgs<R> a) {
   const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= (size_t)a.nx * a.ny) return;
-  if (sizeof(R) == 8 || a.island[c]) freq_cell<R, double>(a, c);
-  else freq_cell<R, float>(a, c);
+  freq_dispatch(a, c);
+}
+
+// Batched, persistent frequency step: work item = 256 cells of one grid.
+template <typename R>
+__global__ __launch_bounds__(256) void k_freq_batched(const GridArgs<R>* __restrict__ args,
+                                                      const int* __restrict__ par, int n, int sp,
+                                                      const int* __restrict__ off) {
+  const int total = off[n];
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (off[mid] <= w) lo = mid; else hi = mid;
+    }
+    const GridArgs<R>& a = args[((par[lo] ^ sp) & 1) * n + lo];
+    const size_t c = (size_t)(w - off[lo]) * 256 + threadIdx.x;
+    if (c < (size_t)a.nx * a.ny) freq_dispatch(a, c);
+  }
 }
 
 // ---------------------------------------------------------------- K4
@@ -591,6 +670,53 @@ hipError_t launch_freq(const GridArgs<R>& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+int advect_blocks(int nx, int ny, int nb, int bk) {
+  return ((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY) * ((nb + bk - 1) / bk);
+}
+int freq_blocks(int nx, int ny) { return (int)(((size_t)nx * ny + 255) / 256); }
+
+const int kBatchBK[kNumBatchVariants] = {7, 14, 28, 49};
+
+template <typename R>
+hipError_t launch_advect_batched(int variant, const GridArgs<R>* args, const int* par, int n,
+                                 int sp, const int* off, int nblocks, hipStream_t s) {
+  dim3 g(nblocks), b(256);
+  switch (variant) {
+    case 0: hipLaunchKernelGGL((k_advect_batched<R, 7>), g, b, 0, s, args, par, n, sp, off); break;
+    case 1: hipLaunchKernelGGL((k_advect_batched<R, 14>), g, b, 0, s, args, par, n, sp, off); break;
+    case 2: hipLaunchKernelGGL((k_advect_batched<R, 28>), g, b, 0, s, args, par, n, sp, off); break;
+    default: hipLaunchKernelGGL((k_advect_batched<R, 49>), g, b, 0, s, args, par, n, sp, off); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_freq_batched(const GridArgs<R>* args, const int* par, int n, int sp,
+                               const int* off, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL((k_freq_batched<R>), dim3(nblocks), dim3(256), 0, s, args, par, n, sp, off);
+  return hipGetLastError();
+}
+
+template <typename R>
+int batched_occupancy(int variant) {
+  int nb = 0;
+  hipError_t e;
+  switch (variant) {
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_advect_batched<R, 7>, 256, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_advect_batched<R, 14>, 256, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_advect_batched<R, 28>, 256, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_advect_batched<R, 49>, 256, 0); break;
+  }
+  return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
+template <typename R>
+int freq_batched_occupancy() {
+  int nb = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_freq_batched<R>, 256, 0);
+  return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
 template <typename R>
 hipError_t launch_step(const GridArgs<R>& a, hipStream_t s) {
   hipError_t e = launch_advect(a, s);
@@ -621,6 +747,14 @@ hipError_t launch_force_out(const double* force, size_t nc, int e2, double* fx, 
 }
 
 template hipError_t launch_step<float>(const GridArgs<float>&, hipStream_t);
+template hipError_t launch_advect_batched<float>(int, const GridArgs<float>*, const int*, int, int, const int*, int, hipStream_t);
+template hipError_t launch_advect_batched<double>(int, const GridArgs<double>*, const int*, int, int, const int*, int, hipStream_t);
+template hipError_t launch_freq_batched<float>(const GridArgs<float>*, const int*, int, int, const int*, int, hipStream_t);
+template hipError_t launch_freq_batched<double>(const GridArgs<double>*, const int*, int, int, const int*, int, hipStream_t);
+template int batched_occupancy<float>(int);
+template int batched_occupancy<double>(int);
+template int freq_batched_occupancy<float>();
+template int freq_batched_occupancy<double>();
 template hipError_t launch_advect<float>(const GridArgs<float>&, hipStream_t);
 template hipError_t launch_advect<double>(const GridArgs<double>&, hipStream_t);
 template hipError_t launch_freq<float>(const GridArgs<float>&, hipStream_t);

@@ -6,8 +6,9 @@ without a built library, or using it without a GPU, raises: there is no CPU
 fallback.
 
 Names follow include/m1lya.h: m1_init, m1_step, m1_force, m1_solve_steady,
-m1_residual, m1_get_state, m1_set_state, m1_step_batched, ...  The class
-`M1Grid` wraps one handle for a problem dict built by `inputs`.
+m1_residual, m1_get_state, m1_set_state, m1_batch_*, ...  The class
+`M1Grid` wraps one handle for a problem dict built by `inputs`; `M1Batch`
+wraps a batch of handles advanced together.
 """
 from __future__ import annotations
 
@@ -72,7 +73,11 @@ def lib():
         "m1_get_state": (I32, [VP, VP, VP, VP]),
         "m1_set_state": (I32, [VP, VP, VP, VP]),
         "m1_get_info": (I32, [VP, P(D), P(I32), P(I32), P(I64), P(I32)]),
-        "m1_step_batched": (I32, [P(VP), I32, I32]),
+        "m1_batch_workspace_bytes": (I32, [P(VP), I32, P(ctypes.c_size_t)]),
+        "m1_batch_init": (I32, [P(VP), I32, VP, ctypes.c_size_t, I32, P(VP)]),
+        "m1_batch_step": (I32, [VP, I32]),
+        "m1_batch_info": (I32, [VP, P(I32), P(D), I32]),
+        "m1_batch_free": (I32, [VP]),
         "m1_step_profiled": (I32, [VP, I32, P(D)]),
         "m1_sync": (I32, [VP]),
         "m1_free": (I32, [VP]),
@@ -90,7 +95,8 @@ def exported_symbols():
     return ["m1_default_config", "m1_num_bins", "m1_workspace_bytes",
             "m1_count_temperature_classes", "m1_init", "m1_step", "m1_force",
             "m1_solve_steady", "m1_residual", "m1_get_state", "m1_set_state", "m1_get_info",
-            "m1_step_batched", "m1_step_profiled", "m1_sync", "m1_free", "m1_last_error"]
+            "m1_batch_workspace_bytes", "m1_batch_init", "m1_batch_step", "m1_batch_info",
+            "m1_batch_free", "m1_step_profiled", "m1_sync", "m1_free", "m1_last_error"]
 
 
 def check(code):
@@ -234,7 +240,9 @@ class M1Grid:
         torch = _torch()
         conv = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda").contiguous()
         self._set = (conv(E), conv(Fx), conv(Fy))
+        torch.cuda.current_stream().synchronize()     # inputs written on torch's stream
         check(lib().m1_set_state(self.h, *[t.data_ptr() for t in self._set]))
+        self.sync()
 
     def force(self, out=None):
         torch = _torch()
@@ -242,10 +250,12 @@ class M1Grid:
             out = torch.empty((4, self.ny, self.nx), dtype=torch.float64, device="cuda")
         check(lib().m1_force(self.h, out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(),
                              out[3].data_ptr()))
+        self.sync()                                   # written on the handle's stream
         return out
 
     def free(self):
         if getattr(self, "h", None) is not None and self.h.value:
+            lib().m1_sync(self.h)                     # work in flight uses the workspace
             lib().m1_free(self.h)
             self.h = ctypes.c_void_p()
 
@@ -256,6 +266,53 @@ class M1Grid:
             pass
 
 
-def step_batched(grids, nsteps):
-    arr = (ctypes.c_void_p * len(grids))(*[g.h.value for g in grids])
-    check(lib().m1_step_batched(arr, len(grids), int(nsteps)))
+class M1Batch:
+    """Grids of one precision on one stream, advanced together by persistent
+    launches (results bitwise identical to stepping each grid alone)."""
+
+    def __init__(self, grids, use_graph=True):
+        torch = _torch()
+        self.grids = list(grids)
+        n = len(self.grids)
+        self._arr = (ctypes.c_void_p * n)(*[g.h.value for g in self.grids])
+        b = ctypes.c_size_t()
+        check(lib().m1_batch_workspace_bytes(self._arr, n, ctypes.byref(b)))
+        self.ws = torch.empty(b.value + 256, dtype=torch.uint8, device="cuda")
+        ptr = (self.ws.data_ptr() + 255) & ~255
+        h = ctypes.c_void_p()
+        check(lib().m1_batch_init(self._arr, n, ptr, b.value, int(bool(use_graph)),
+                                  ctypes.byref(h)))
+        self.h = h
+
+    def step(self, n=1):
+        check(lib().m1_batch_step(self.h, int(n)))
+        for g in self.grids:
+            g.t += n * g.dt
+        return self
+
+    def info(self):
+        """(bins per advection block chosen, or 0 while tuning; ms per variant)."""
+        bk = ctypes.c_int32()
+        ms = (ctypes.c_double * 4)()
+        check(lib().m1_batch_info(self.h, ctypes.byref(bk), ms, 4))
+        return bk.value, list(ms)
+
+    def free(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().m1_batch_free(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def step_batched(grids, nsteps, use_graph=True):
+    """Advances the grids together by nsteps steps (one-off batch)."""
+    b = M1Batch(grids, use_graph=use_graph)
+    b.step(nsteps)
+    for g in grids:
+        g.sync()
+    b.free()

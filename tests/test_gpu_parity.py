@@ -109,21 +109,69 @@ def test_linearity_bitwise_gpu():
     assert np.array_equal(f2, f1 * 2.0 ** 37)
 
 
-def test_batched_equals_alone_bitwise():
-    from paper_2606_02711_amd import m1
-    ps = [inputs.random_small(g, n, n + 3, s, half_width=1e3)
-          for g, n, s in (("cart", 9, 1), ("cyl", 17, 2), ("cart", 33, 3))]
-    alone = []
+def _alone(ps, steps, prec):
+    out = []
     for p in ps:
-        _, E, Fx, Fy, f = run_gpu(p, 6, "fp32")
-        alone.append((E, Fx, Fy, f))
-    print("[gpu] batched", flush=True)
-    gs = [m1.M1Grid(p, prec="fp32") for p in ps]
-    m1.step_batched(gs, 6)
-    for g, (E, Fx, Fy, f) in zip(gs, alone):
+        _, E, Fx, Fy, f = run_gpu(p, steps, prec)
+        out.append((E, Fx, Fy, f))
+    return out
+
+
+def _assert_same(gs, ref):
+    for g, (E, Fx, Fy, f) in zip(gs, ref):
         Eb, Fxb, Fyb = [t.double().cpu().numpy() for t in g.state()]
         assert np.array_equal(Eb, E) and np.array_equal(Fxb, Fx) and np.array_equal(Fyb, Fy)
         assert np.array_equal(g.force().cpu().numpy(), f)
+
+
+def _mixed_problems():
+    return [inputs.random_small(g, n, n + 3, s, half_width=1e3)
+            for g, n, s in (("cart", 9, 1), ("cyl", 17, 2), ("cart", 33, 3), ("cyl", 70, 4))]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batched_equals_alone_bitwise(prec):
+    """One batch of differently sized grids: the tuning steps (every tile
+    variant), then graph replays of step pairs and a single odd step."""
+    from paper_2606_02711_amd import m1
+    ps = _mixed_problems()
+    steps = 4 * 3 + 7
+    ref = _alone(ps, steps, prec)
+    print(f"[gpu] batched {prec}", flush=True)
+    import torch
+    s = torch.cuda.Stream()              # a non-null stream: step pairs replay a graph
+    gs = [m1.M1Grid(p, prec=prec, stream=s) for p in ps]
+    b = m1.M1Batch(gs, use_graph=True)
+    b.step(12)
+    bk, ms = b.info()
+    assert bk in (7, 14, 28, 49) and all(t > 0 for t in ms)
+    b.step(7)
+    _assert_same(gs, ref)
+
+
+def test_batched_with_solo_steps_between():
+    """A member stepped on its own between batch steps keeps its parity."""
+    from paper_2606_02711_amd import m1
+    ps = _mixed_problems()[:3]
+    print("[gpu] batched + solo", flush=True)
+    import torch
+    s = torch.cuda.Stream()
+    gs = [m1.M1Grid(p, prec="fp32", stream=s) for p in ps]
+    b = m1.M1Batch(gs, use_graph=True)
+    b.step(3)
+    gs[1].step(1)
+    b.step(5)
+    gs[0].step(1)
+    gs[2].step(1)
+    b.step(1)
+    gs[1].step(1)
+    # steps taken: grid 0 3+5+1+1, grid 1 3+1+5+1+1, grid 2 3+5+1+1
+    for g, n in zip(gs, (10, 11, 10)):
+        assert g.t == pytest.approx(n * g.dt, rel=1e-12)
+    ref = _alone(ps, 10, "fp32")
+    _assert_same([gs[0], gs[2]], [ref[0], ref[2]])
+    ref1 = _alone([ps[1]], 11, "fp32")
+    _assert_same([gs[1]], ref1)
 
 
 def test_solve_steady_matches_oracle():
