@@ -82,6 +82,50 @@ def run_path(p, prec, steps, warmup, fp64_tau=float("inf")):
     return res
 
 
+def run_batch(ps, steps, warmup):
+    """64 uneven grids: FP32 in one persistent batch, against per-grid loops
+    (FP32 and FP64) that launch each grid's kernels one after another."""
+    import torch
+    from paper_2606_02711_amd import m1
+    cell_bins = 0
+    out = {}
+    stream = torch.cuda.Stream()
+    for mode in ("fp32_batched", "fp32_loop", "fp64_loop"):
+        prec = mode.split("_")[0]
+        log(f"[bench] batch workload: {mode}, {len(ps)} grids")
+        gs = [m1.M1Grid(p, prec=prec, stream=stream) for p in ps]
+        cell_bins = sum(g.ncell * g.nb for g in gs)
+        b = m1.M1Batch(gs, use_graph=True) if mode == "fp32_batched" else None
+        tune = 4 * 3                           # steps the batch spends choosing its tiles
+        for _ in range(max(warmup, tune if b else 0)):
+            if b:
+                b.step(1)
+            else:
+                for g in gs:
+                    g.step(1)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        if b:
+            b.step(steps)
+        else:
+            for _ in range(steps):
+                for g in gs:
+                    g.step(1)
+        stream.synchronize()
+        wall = time.perf_counter() - t0
+        out[mode] = cell_bins * steps / wall
+        if b:
+            out["tile_bins"], ms = b.info()
+            out["tuning_ms_per_step"] = ms
+            b.free()
+        for g in gs:
+            g.free()
+        del gs
+        torch.cuda.empty_cache()
+    out["cell_bins_per_step"] = cell_bins
+    return out
+
+
 def cpu_baseline(p, steps=2):
     from oracle import m1_oracle
     log(f"[bench] oracle sample: {steps} steps of the full workload on the host")
@@ -103,6 +147,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=500,
+                    help="steps of the 64-grid batch workload (0 skips it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--fp64-tau", type=float, default=float("inf"),
@@ -162,6 +208,16 @@ def main():
         out["fp64_ms_per_step"] = 1e3 * r64["wall"] / args.steps
         out["fp64_kernel_ms_per_step"] = {"advect_source": r64["ms_advect"] / args.steps,
                                           "freq_step": r64["ms_freq"] / args.steps}
+    if args.batch_steps > 0:
+        rb = run_batch(inputs.config3(), args.batch_steps, args.warmup)
+        out["batch_64_grids"] = {
+            "workload": "64 uniform clouds, sides log-uniform 64..512, half Cartesian, half "
+                        "cylindrical, log N_HI 19..23, T 100..1e4 K, dust 0..0.01 solar",
+            "steps": args.batch_steps, "cell_bins_per_step": rb["cell_bins_per_step"],
+            "fp32_batched": rb["fp32_batched"], "fp32_loop": rb["fp32_loop"],
+            "fp64_loop": rb["fp64_loop"], "unit": "cell-bin updates/s",
+            "batched_vs_fp64_loop": rb["fp32_batched"] / rb["fp64_loop"],
+            "tile_bins": rb["tile_bins"], "tuning_ms_per_step": rb["tuning_ms_per_step"]}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)
