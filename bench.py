@@ -149,6 +149,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=500,
                     help="steps of the 64-grid batch workload (0 skips it)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the 64-grid batch workload (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--fp64-tau", type=float, default=float("inf"),
@@ -172,6 +174,10 @@ def main():
         torch.cuda.synchronize()
         log("[bench] copy calibration: 3 copies of 1 GiB")
         del src, dst
+    if args.batch_only:
+        rb = run_batch(inputs.config3(), args.batch_steps, args.warmup)
+        print(json.dumps({"batch_64_grids": rb}), flush=True)
+        return
     p = inputs.config2()
     r32 = run_path(p, "fp32", args.steps, args.warmup, args.fp64_tau)
     r64 = None if args.no_fp64 else run_path(p, "fp64", args.steps, args.warmup)
