@@ -167,7 +167,7 @@ int32_t m1_get_info(const m1_handle *h, double *dt, int32_t *n_nu, int32_t *prec
                     int64_t *ncell, int32_t *scale_exp2);
 
 /* ---- batches: many grids advanced by one persistent launch per kernel and
- * step (the spec batching addition; no counterpart in the paper).
+ * step (a throughput addition with no counterpart in the paper).
  * A batch groups n handles of the same precision on the same stream.  Its
  * descriptor tables live in a caller workspace of m1_batch_workspace_bytes
  * bytes (256-byte aligned); the library allocates no device memory.  Every
@@ -190,6 +190,89 @@ int32_t m1_batch_info(const m1_batch *b, int32_t *bins_per_block, double *ms_per
                       int32_t n_variants);
 /* Waits for the stream, then releases the host object (not the workspace). */
 int32_t m1_batch_free(m1_batch *b);
+/* Fixes the tile variant (bins per advection block: 7, 14, 28 or 49) and
+ * ends tuning; results do not depend on it. */
+int32_t m1_batch_set_tile(m1_batch *b, int32_t bins_per_block);
+/* Upper bound of m1_batch_workspace_bytes for any n handles of precision prec. */
+int32_t m1_batch_workspace_bound(int32_t n, int32_t prec, size_t *bytes);
+
+/* ---- serving: a continuous-batching engine for steady-state solves (a
+ * serving addition with no counterpart in the paper).
+ *
+ * The engine owns nothing on the device but what the caller hands it: one
+ * arena of arena_bytes (256-byte aligned) that is its HBM budget.  A request
+ * is admitted when a free block of exactly m1_workspace_bytes(cfg, classes)
+ * bytes exists in the arena (first fit) and fewer than max_resident
+ * requests are resident; queued requests are taken in arrival order, and a
+ * smaller one may pass a head that does not fit at most max_bypass times
+ * before admission waits for the head.  At admission the engine calls
+ * fields_cb(user, id, &fields) for the request's inputs and runs m1_init;
+ * the arrays must stay valid until the m1_server_run call that admits the
+ * request returns.  A callback status other than M1_OK fails the request.
+ *
+ * m1_server_run performs rounds.  In a round every resident request takes
+ * min(check_every, max_steps - steps) steps (in batched mode all requests
+ * whose share is check_every advance together in one persistent batch;
+ * otherwise one request at a time, in order) and then its residual is
+ * computed; a request whose residual is below rel_tol, or that reached
+ * max_steps, is finished.  This is the schedule of m1_solve_steady, so each
+ * result is bitwise identical to solving the request alone.  A finished
+ * request keeps its arena block (for m1_server_handle, then m1_get_state /
+ * m1_force) until m1_server_release.  The engine is single threaded. */
+typedef struct m1_server m1_server;
+
+typedef struct {
+  int32_t prec;            /* m1_prec of every request (m1_config.prec is overridden) */
+  int32_t batched;         /* 1: residents advance in one batch per round; 0: one at a time */
+  int32_t max_resident;    /* >= 1 */
+  int32_t check_every;     /* steps per round and between residual checks, >= 1 */
+  int32_t use_graph;       /* batched mode: replay step pairs from a HIP graph */
+  int32_t max_bypass;      /* >= 0 */
+} m1_server_config;
+
+typedef int32_t (*m1_fields_cb)(void *user, int64_t id, m1_fields *out);
+
+/* Request states reported by m1_server_poll. */
+typedef enum {
+  M1_REQ_QUEUED = 0, M1_REQ_RESIDENT = 1, M1_REQ_CONVERGED = 2, M1_REQ_NOT_CONVERGED = 3,
+  M1_REQ_REJECTED = 4, M1_REQ_FAILED = 5
+} m1_req_state;
+
+typedef struct {
+  int64_t id;
+  int32_t state;           /* m1_req_state */
+  int32_t error;           /* m1_status of a failed init or step, else M1_OK */
+  int64_t steps;
+  double residual;
+  int64_t admit_round, finish_round;
+  size_t ws_bytes;
+} m1_request_info;
+
+int32_t m1_server_create(const m1_server_config *cfg, void *d_arena, size_t arena_bytes,
+                         void *stream, m1_fields_cb cb, void *user, m1_server **out);
+/* Queues a request.  cfg is copied; n_temp_classes as for m1_workspace_bytes.
+ * A request that cannot fit an empty arena is recorded as rejected (it is
+ * reported by the next m1_server_poll) and *id still receives its id. */
+int32_t m1_server_submit(m1_server *s, const m1_config *cfg, int64_t n_temp_classes,
+                         double rel_tol, int64_t max_steps, int64_t *id);
+/* Runs up to `rounds` rounds (admission, steps, residual checks; blocking)
+ * and returns early when nothing is resident or queued.  *n_busy (may be
+ * NULL) receives the number of queued plus resident requests afterwards. */
+int32_t m1_server_run(m1_server *s, int32_t rounds, int32_t *n_busy);
+/* Moves up to cap records of requests that finished (or were rejected or
+ * failed) since the last poll into out; *n receives the count. */
+int32_t m1_server_poll(m1_server *s, m1_request_info *out, int32_t cap, int32_t *n);
+/* Handle of a resident or finished request (owned by the engine). */
+int32_t m1_server_handle(m1_server *s, int64_t id, m1_handle **h);
+/* Frees a finished request's arena block and handle. */
+int32_t m1_server_release(m1_server *s, int64_t id);
+/* Counters: queued, resident, finished and not released, rounds run; arena
+ * bytes in use and the largest free block. */
+int32_t m1_server_stats(const m1_server *s, int64_t *queued, int64_t *resident,
+                        int64_t *finished, int64_t *rounds, size_t *arena_used,
+                        size_t *largest_free);
+/* Waits for the stream and releases every request and the engine. */
+int32_t m1_server_free(m1_server *s);
 
 int32_t m1_sync(m1_handle *h);         /* waits for the stream; surfaces faults */
 int32_t m1_free(m1_handle *h);         /* frees the host handle, not the workspace */

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libm1lya.so")
-SOURCES = ["m1_host.hip", "m1_step_kernels.hip", "m1_setup_kernels.hip"]
+SOURCES = ["m1_host.hip", "m1_step_kernels.hip", "m1_setup_kernels.hip", "m1_serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -463,6 +463,13 @@ size_t init_temp_need(size_t nc, int nb, int64_t ncls, int nx, int ny, bool host
 }  // namespace
 
 // =========================================================================
+namespace m1 {
+int record_error(int code, const char* msg) {
+  g_err = msg;
+  return code;
+}
+}  // namespace m1
+
 extern "C" {
 
 const char* m1_last_error(void) { return g_err.c_str(); }
@@ -902,6 +909,25 @@ int32_t m1_batch_info(const m1_batch* b, int32_t* bins_per_block, double* ms, in
   if (!b) return fail(M1_EINVAL, "batch is NULL");
   if (bins_per_block) *bins_per_block = b->variant >= 0 ? kBatchBK[b->variant] : 0;
   for (int v = 0; ms && v < nv && v < kNumBatchVariants; ++v) ms[v] = b->trial_ms[v];
+  return M1_OK;
+}
+
+int32_t m1_batch_set_tile(m1_batch* b, int32_t bins_per_block) {
+  if (!b) return fail(M1_EINVAL, "batch is NULL");
+  for (int v = 0; v < kNumBatchVariants; ++v)
+    if (kBatchBK[v] == bins_per_block) {
+      b->variant = v;
+      return M1_OK;
+    }
+  return fail(M1_EINVAL, "no tile variant with %d bins per block", bins_per_block);
+}
+
+int32_t m1_batch_workspace_bound(int32_t n, int32_t prec, size_t* bytes) {
+  if (!bytes || n <= 0 || (prec != M1_FP32 && prec != M1_FP64)) return fail(M1_EINVAL, "bad arguments");
+  size_t rs = prec == M1_FP32 ? sizeof(GridArgs<float>) : sizeof(GridArgs<double>);
+  *bytes = align_up(2 * (size_t)n * rs) + align_up((size_t)n * sizeof(int)) +
+           align_up((size_t)kNumBatchVariants * (n + 1) * sizeof(int)) +
+           align_up((size_t)(n + 1) * sizeof(int));
   return M1_OK;
 }
 

@@ -193,10 +193,11 @@ def config2(nx=512, ny=1024, steps=1000):
     return p
 
 
-def uniform_cloud(geom, n, log10_NHI, T, dust_solar, L_box=PC, steps=500):
+def uniform_cloud(geom, n, log10_NHI, T, dust_solar, L_box=PC, steps=500, fields=True):
     """Uniform neutral cloud with a Gaussian sigma = 2 cells central source.
     Cartesian: [-L/2, L/2]^2, all vacuum.  Cylindrical: R, z in [0, L/2] with
-    the axis and the z = 0 midplane reflecting."""
+    the axis and the z = 0 midplane reflecting.  fields=False returns the
+    grid description only (empty "fields")."""
     half = 0.5 * L_box
     if geom == "cart":
         p = base_problem("cart", n, n, -half, half, -half, half,
@@ -204,6 +205,8 @@ def uniform_cloud(geom, n, log10_NHI, T, dust_solar, L_box=PC, steps=500):
     else:
         p = base_problem("cyl", n, n, 0.0, half, 0.0, half,
                          ("reflect", "vacuum", "reflect", "vacuum"), steps=steps)
+    if not fields:
+        return p
     n_HI = 10.0 ** log10_NHI / half
     f = uniform_fields(p, n_HI, T, dust_solar=dust_solar, p_d=0.0)
     dx = (p["x1"] - p["x0"]) / n

@@ -48,6 +48,23 @@ class m1_fields(ctypes.Structure):
                [("on_device", ctypes.c_int32)]
 
 
+class m1_server_config(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("batched", ctypes.c_int32),
+                ("max_resident", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("max_bypass", ctypes.c_int32)]
+
+
+class m1_request_info(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("state", ctypes.c_int32), ("error", ctypes.c_int32),
+                ("steps", ctypes.c_int64), ("residual", ctypes.c_double),
+                ("admit_round", ctypes.c_int64), ("finish_round", ctypes.c_int64),
+                ("ws_bytes", ctypes.c_size_t)]
+
+
+FIELDS_CB = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                             ctypes.POINTER(m1_fields))
+REQ_STATES = ("queued", "resident", "converged", "not_converged", "rejected", "failed")
+
 _lib = None
 
 
@@ -78,6 +95,18 @@ def lib():
         "m1_batch_step": (I32, [VP, I32]),
         "m1_batch_info": (I32, [VP, P(I32), P(D), I32]),
         "m1_batch_free": (I32, [VP]),
+        "m1_batch_set_tile": (I32, [VP, I32]),
+        "m1_batch_workspace_bound": (I32, [I32, I32, P(ctypes.c_size_t)]),
+        "m1_server_create": (I32, [P(m1_server_config), VP, ctypes.c_size_t, VP, FIELDS_CB, VP,
+                                   P(VP)]),
+        "m1_server_submit": (I32, [VP, P(m1_config), I64, D, I64, P(I64)]),
+        "m1_server_run": (I32, [VP, I32, P(I32)]),
+        "m1_server_poll": (I32, [VP, P(m1_request_info), I32, P(I32)]),
+        "m1_server_handle": (I32, [VP, I64, P(VP)]),
+        "m1_server_release": (I32, [VP, I64]),
+        "m1_server_stats": (I32, [VP, P(I64), P(I64), P(I64), P(I64), P(ctypes.c_size_t),
+                                  P(ctypes.c_size_t)]),
+        "m1_server_free": (I32, [VP]),
         "m1_step_profiled": (I32, [VP, I32, P(D)]),
         "m1_sync": (I32, [VP]),
         "m1_free": (I32, [VP]),
@@ -96,7 +125,10 @@ def exported_symbols():
             "m1_count_temperature_classes", "m1_init", "m1_step", "m1_force",
             "m1_solve_steady", "m1_residual", "m1_get_state", "m1_set_state", "m1_get_info",
             "m1_batch_workspace_bytes", "m1_batch_init", "m1_batch_step", "m1_batch_info",
-            "m1_batch_free", "m1_step_profiled", "m1_sync", "m1_free", "m1_last_error"]
+            "m1_batch_free", "m1_batch_set_tile", "m1_batch_workspace_bound",
+            "m1_server_create", "m1_server_submit", "m1_server_run", "m1_server_poll",
+            "m1_server_handle", "m1_server_release", "m1_server_stats", "m1_server_free",
+            "m1_step_profiled", "m1_sync", "m1_free", "m1_last_error"]
 
 
 def check(code):
@@ -316,3 +348,126 @@ def step_batched(grids, nsteps, use_graph=True):
     for g in grids:
         g.sync()
     b.free()
+
+
+class M1Server:
+    """Continuous-batching engine for steady-state solves (m1_server_*).
+
+    Requests are problem dicts, or zero-argument callables returning one
+    (called at submission for the configuration and again at admission for
+    the fields, so a long queue holds no field arrays)."""
+
+    def __init__(self, arena_bytes, prec="fp32", batched=True, max_resident=64, check_every=16,
+                 use_graph=True, max_bypass=8, stream=None):
+        torch = _torch()
+        self.prec = prec
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device="cuda")
+        ptr = (self.arena.data_ptr() + 255) & ~255
+        c = m1_server_config(M1_FP32 if prec == "fp32" else M1_FP64, int(bool(batched)),
+                             int(max_resident), int(check_every), int(bool(use_graph)),
+                             int(max_bypass))
+        self._cb = FIELDS_CB(self._fields)
+        self._source = {}        # id -> problem dict or factory, until admission
+        self._meta = {}          # id -> (nb, ny, nx)
+        self._keep = {}          # host arrays of requests admitted in the current run call
+        self._cb_error = None
+        h = ctypes.c_void_p()
+        check(lib().m1_server_create(ctypes.byref(c), ptr, int(arena_bytes),
+                                     self.stream.cuda_stream, self._cb, None, ctypes.byref(h)))
+        self.h = h
+
+    def _fields(self, user, rid, out):
+        try:
+            src = self._source.pop(rid)
+            p = src() if callable(src) else src
+            host = [np.ascontiguousarray(p["fields"][n], dtype=np.float64).ravel()
+                    for n in FIELD_ORDER]
+            self._keep[rid] = host
+            fl = out.contents
+            for n, a in zip(FIELD_ORDER, host):
+                setattr(fl, n, a.ctypes.data)
+            fl.on_device = 0
+            return M1_OK
+        except Exception as e:           # reported as a failed request
+            self._cb_error = e
+            return M1_EINVAL
+
+    def submit(self, p, rel_tol=1e-6, max_steps=100000, meta=None, n_classes=None):
+        """meta (a problem dict whose fields may be empty) and n_classes, when
+        given, spare building the fields at submission."""
+        if meta is None or n_classes is None:
+            meta = p() if callable(p) else p
+            n_classes = count_temperature_classes(meta["fields"]["T"])
+        cfg = make_config(meta, self.prec)
+        ncls = int(n_classes)
+        rid = ctypes.c_int64()
+        check(lib().m1_server_submit(self.h, ctypes.byref(cfg), ncls, float(rel_tol),
+                                     int(max_steps), ctypes.byref(rid)))
+        self._source[rid.value] = p
+        self._meta[rid.value] = (num_bins(cfg), cfg.ny, cfg.nx)
+        return rid.value
+
+    def run(self, rounds=1):
+        busy = ctypes.c_int32()
+        try:
+            check(lib().m1_server_run(self.h, int(rounds), ctypes.byref(busy)))
+        finally:
+            self._keep.clear()
+        return busy.value
+
+    def poll(self, cap=1024):
+        arr = (m1_request_info * cap)()
+        n = ctypes.c_int32()
+        check(lib().m1_server_poll(self.h, arr, cap, ctypes.byref(n)))
+        out = []
+        for i in range(n.value):
+            r = arr[i]
+            out.append(dict(id=r.id, state=REQ_STATES[r.state], error=r.error, steps=r.steps,
+                            residual=r.residual, admit_round=r.admit_round,
+                            finish_round=r.finish_round, ws_bytes=r.ws_bytes))
+            self._source.pop(r.id, None)
+        return out
+
+    def _handle(self, rid):
+        h = ctypes.c_void_p()
+        check(lib().m1_server_handle(self.h, int(rid), ctypes.byref(h)))
+        return h
+
+    def state(self, rid):
+        torch = _torch()
+        E = torch.empty(self._meta[rid], dtype=torch.float64, device="cuda")
+        Fx, Fy = torch.empty_like(E), torch.empty_like(E)
+        check(lib().m1_get_state(self._handle(rid), E.data_ptr(), Fx.data_ptr(), Fy.data_ptr()))
+        return E, Fx, Fy
+
+    def force(self, rid):
+        torch = _torch()
+        h = self._handle(rid)
+        _, ny, nx = self._meta[rid]
+        out = torch.empty((4, ny, nx), dtype=torch.float64, device="cuda")
+        check(lib().m1_force(h, out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(),
+                             out[3].data_ptr()))
+        check(lib().m1_sync(h))
+        return out
+
+    def release(self, rid):
+        check(lib().m1_server_release(self.h, int(rid)))
+        self._meta.pop(rid, None)
+
+    def stats(self):
+        v = [ctypes.c_int64() for _ in range(4)] + [ctypes.c_size_t(), ctypes.c_size_t()]
+        check(lib().m1_server_stats(self.h, *[ctypes.byref(x) for x in v]))
+        keys = ("queued", "resident", "finished", "rounds", "arena_used", "largest_free")
+        return {k: x.value for k, x in zip(keys, v)}
+
+    def free(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().m1_server_free(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
