@@ -126,6 +126,27 @@ def run_batch(ps, steps, warmup):
     return out
 
 
+def run_serving(args):
+    """Poisson stream of steady-state solves (uniform clouds, log N_HI 19..23,
+    T 100..1e4 K, dust 0..0.01 solar) through the continuous-batching engine
+    in FP32, and through the FP64 plain path (one request at a time)."""
+    from paper_2606_02711_amd import inputs, serve
+    reqs = inputs.config4_requests(rate=args.serve_rate, duration=args.serve_seconds,
+                                   lo=args.serve_lo, hi=args.serve_hi)
+    out = {"workload": f"Poisson {args.serve_rate} req/s for {args.serve_seconds} s, sides "
+                       f"log-uniform {args.serve_lo}..{args.serve_hi}, rel_tol 1e-6",
+           "requests": len(reqs)}
+    for name, prec, batched, slots in (("fp32_batched", "fp32", True, args.serve_slots),
+                                       ("fp64_plain", "fp64", False, 1)):
+        log(f"[bench] serving {name}: {len(reqs)} requests")
+        r = serve.run_stream(reqs, prec=prec, batched=batched, arena_bytes=args.serve_arena_gb << 30,
+                             max_resident=slots, check_every=32, rel_tol=1e-6,
+                             max_steps=args.serve_max_steps, duration=args.serve_seconds,
+                             drain=args.serve_drain, log=log)
+        out[name] = r
+    return out
+
+
 def cpu_baseline(p, steps=2):
     from oracle import m1_oracle
     log(f"[bench] oracle sample: {steps} steps of the full workload on the host")
@@ -149,6 +170,17 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=500,
                     help="steps of the 64-grid batch workload (0 skips it)")
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
+                    help="length of the request stream (0 skips the serving workload)")
+    ap.add_argument("--serve-rate", type=float, default=0.5, help="requests per second")
+    ap.add_argument("--serve-lo", type=int, default=64)
+    ap.add_argument("--serve-hi", type=int, default=128)
+    ap.add_argument("--serve-slots", type=int, default=32, help="resident requests at most")
+    ap.add_argument("--serve-arena-gb", type=int, default=64)
+    ap.add_argument("--serve-max-steps", type=int, default=200000)
+    ap.add_argument("--serve-drain", type=float, default=30.0,
+                    help="seconds after the stream ends before the backlog is counted")
+    ap.add_argument("--serve-only", action="store_true")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the 64-grid batch workload (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -174,6 +206,9 @@ def main():
         torch.cuda.synchronize()
         log("[bench] copy calibration: 3 copies of 1 GiB")
         del src, dst
+    if args.serve_only:
+        print(json.dumps({"serving": run_serving(args)}), flush=True)
+        return
     if args.batch_only:
         rb = run_batch(inputs.config3(), args.batch_steps, args.warmup)
         print(json.dumps({"batch_64_grids": rb}), flush=True)
@@ -224,6 +259,8 @@ def main():
             "fp64_loop": rb["fp64_loop"], "unit": "cell-bin updates/s",
             "batched_vs_fp64_loop": rb["fp32_batched"] / rb["fp64_loop"],
             "tile_bins": rb["tile_bins"], "tuning_ms_per_step": rb["tuning_ms_per_step"]}
+    if args.serve_seconds > 0:
+        out["serving"] = run_serving(args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)

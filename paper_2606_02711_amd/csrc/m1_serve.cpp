@@ -215,13 +215,12 @@ void admit(m1_server* s) {
 }
 
 int advance(m1_server* s) {
-  std::vector<Request*> together, alone;
+  std::vector<Request*> together;
   std::vector<int32_t> share(s->resident.size());
   for (size_t q = 0; q < s->resident.size(); ++q) {
     Request* r = s->resident[q];
     share[q] = (int32_t)std::min<int64_t>(s->c.check_every, r->max_steps - r->steps);
     if (s->c.batched && share[q] == s->c.check_every) together.push_back(r);
-    else alone.push_back(r);
   }
   if (!together.empty()) {
     std::vector<m1_handle*> hs;
@@ -389,7 +388,9 @@ int32_t m1_server_stats(const m1_server* s, int64_t* queued, int64_t* resident, 
 int32_t m1_server_free(m1_server* s) {
   if (!s) return M1_OK;
   drop_batch(s);
-  (void)hipStreamSynchronize(s->stream);
+  bool any = false;                        // nothing was enqueued without a handle
+  for (auto& kv : s->all) any = any || kv.second->h;
+  if (any) (void)hipStreamSynchronize(s->stream);
   for (auto& kv : s->all) {
     if (kv.second->h) m1_free(kv.second->h);
     delete kv.second;

@@ -102,3 +102,53 @@ def test_temperature_classes():
     assert m1.count_temperature_classes(p["fields"]["T"]) == 2
     r = inputs.random_small("cart", 8, 8, seed=1)
     assert m1.count_temperature_classes(r["fields"]["T"]) == 64
+
+
+def test_server_bookkeeping_without_device_work():
+    """Engine set-up, submission, rejection and polling run on the host only
+    (no request is admitted, so no device call is made)."""
+    import ctypes
+    from paper_2606_02711_amd import inputs
+    L = m1.lib()
+    c = m1.m1_server_config(m1.M1_FP32, 1, 4, 16, 0, 2)
+    fake_arena = 1 << 40                     # never dereferenced: nothing is admitted
+    cb = m1.FIELDS_CB(lambda u, i, f: m1.M1_EINVAL)
+    h = ctypes.c_void_p()
+    small = inputs.uniform_cloud("cart", 8, 19.0, 1e4, 0.0, fields=False)
+    big = inputs.uniform_cloud("cyl", 64, 19.0, 1e4, 0.0, fields=False)
+    ws_small = m1.workspace_bytes(m1.make_config(small, "fp32"), 1)
+    ws_big = m1.workspace_bytes(m1.make_config(big, "fp32"), 1)
+    assert ws_big > 4 * ws_small
+    arena = 2 * ws_small + (1 << 16)
+    # bad arguments are refused before anything is created
+    assert L.m1_server_create(None, fake_arena, arena, None, cb, None, ctypes.byref(h)) == m1.M1_EINVAL
+    assert L.m1_server_create(ctypes.byref(c), fake_arena + 8, arena, None, cb, None,
+                              ctypes.byref(h)) == m1.M1_EINVAL
+    assert L.m1_server_create(ctypes.byref(c), fake_arena, 1024, None, cb, None,
+                              ctypes.byref(h)) == m1.M1_ENOMEM
+    m1.check(L.m1_server_create(ctypes.byref(c), fake_arena, arena, None, cb, None, ctypes.byref(h)))
+    ids = []
+    for p in (small, big, small):
+        rid = ctypes.c_int64()
+        cfg = m1.make_config(p, "fp64")              # precision is the engine's
+        m1.check(L.m1_server_submit(h, ctypes.byref(cfg), 1, 1e-6, 100, ctypes.byref(rid)))
+        ids.append(rid.value)
+    assert ids == [0, 1, 2]
+    recs = (m1.m1_request_info * 8)()
+    n = ctypes.c_int32()
+    m1.check(L.m1_server_poll(h, recs, 8, ctypes.byref(n)))
+    assert n.value == 1 and recs[0].id == 1 and m1.REQ_STATES[recs[0].state] == "rejected"
+    assert recs[0].ws_bytes == ws_big and recs[0].error == m1.M1_ENOMEM
+    q, r, f, rounds = (ctypes.c_int64() for _ in range(4))
+    used, largest = ctypes.c_size_t(), ctypes.c_size_t()
+    m1.check(L.m1_server_stats(h, *(ctypes.byref(x) for x in (q, r, f, rounds, used, largest))))
+    assert (q.value, r.value, f.value, rounds.value) == (2, 0, 1, 0)
+    assert largest.value >= 2 * ws_small
+    # queued requests cannot be released; rejected ones can; bad arguments are refused
+    assert L.m1_server_release(h, 0) == m1.M1_ESTATE
+    m1.check(L.m1_server_release(h, 1))
+    assert L.m1_server_release(h, 1) == m1.M1_EINVAL
+    rid = ctypes.c_int64()
+    cfg = m1.make_config(small, "fp32")
+    assert L.m1_server_submit(h, ctypes.byref(cfg), 1, 0.0, 100, ctypes.byref(rid)) == m1.M1_EINVAL
+    m1.check(L.m1_server_free(h))
