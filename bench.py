@@ -126,6 +126,47 @@ def run_batch(ps, steps, warmup):
     return out
 
 
+def run_large(steps, warmup):
+    """4096 x 8192 cylindrical cloud in FP32, the force density copied out
+    (to device arrays) after every step."""
+    import torch
+    from paper_2606_02711_amd import inputs, m1
+    log("[bench] large grid: building inputs")
+    p = inputs.config5()
+    g = m1.M1Grid(p, prec="fp32")
+    del p
+    force = torch.empty((4, g.ny, g.nx), dtype=torch.float64, device="cuda")
+    fp = [force[q].data_ptr() for q in range(4)]
+    L = m1.lib()
+    for _ in range(warmup):
+        g.step(1)
+        m1.check(L.m1_force(g.h, *fp))
+    g.sync()
+    log(f"[bench] large grid: timing {steps} steps")
+    t0 = time.perf_counter()
+    ms = [0.0, 0.0]
+    for _ in range(steps):
+        a, b = g.step_profiled(1)
+        ms[0] += a
+        ms[1] += b
+        m1.check(L.m1_force(g.h, *fp))
+    g.sync()
+    wall = time.perf_counter() - t0
+    cb = g.ncell * g.nb
+    out = {"workload": "cylindrical 4096x8192 (R,z) turbulent log-normal cloud (sigma_ln 1.5), "
+                       "HII region, velocities up to 50 km/s, dust 0.01 solar, p_d 1e-7, 16 ring "
+                       "sources; FP32; force density output every step",
+           "steps": steps, "cell_bins": cb, "value": cb * steps / wall, "unit": "cell-bin updates/s",
+           "ms_per_step": 1e3 * wall / steps,
+           "kernel_ms_per_step": {"advect_source": ms[0] / steps, "freq_step": ms[1] / steps},
+           "algorithmic_GBps": 24.0 * cb * steps / wall / 1e9,
+           "hbm_frac_algorithmic": 24.0 * cb * steps / wall / 1e9 / HBM_PEAK_GBS}
+    g.free()
+    del g, force
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_serving(args):
     """Poisson stream of steady-state solves (uniform clouds, log N_HI 19..23,
     T 100..1e4 K, dust 0..0.01 solar) through the continuous-batching engine
@@ -170,6 +211,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=500,
                     help="steps of the 64-grid batch workload (0 skips it)")
+    ap.add_argument("--large-steps", type=int, default=20,
+                    help="timed steps of the 4096 x 8192 grid (0 skips it)")
     ap.add_argument("--serve-seconds", type=float, default=30.0,
                     help="length of the request stream (0 skips the serving workload)")
     ap.add_argument("--serve-rate", type=float, default=0.5, help="requests per second")
@@ -259,6 +302,8 @@ def main():
             "fp64_loop": rb["fp64_loop"], "unit": "cell-bin updates/s",
             "batched_vs_fp64_loop": rb["fp32_batched"] / rb["fp64_loop"],
             "tile_bins": rb["tile_bins"], "tuning_ms_per_step": rb["tuning_ms_per_step"]}
+    if args.large_steps > 0:
+        out["large_grid"] = run_large(args.large_steps, 2)
     if args.serve_seconds > 0:
         out["serving"] = run_serving(args)
     if not args.no_cpu:

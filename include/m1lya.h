@@ -162,6 +162,13 @@ int32_t m1_get_state(m1_handle *h, double *d_E, double *d_Fx, double *d_Fy);
 int32_t m1_set_state(m1_handle *h, const double *d_E, const double *d_Fx,
                      const double *d_Fy);
 
+/* Copy of the window i in [i0, i1), j in [j0, j1) of the state of every bin
+ * into caller device arrays of doubles [N_nu][j1 - j0][i1 - i0] (physical
+ * units; NULL outputs are skipped).  For grids whose full FP64 copy would not
+ * fit beside the workspace.  Blocking. */
+int32_t m1_get_state_region(m1_handle *h, int32_t i0, int32_t i1, int32_t j0, int32_t j1,
+                            double *d_E, double *d_Fx, double *d_Fy);
+
 /* Scalars of a handle: dt [s], N_nu, precision, cells, internal scale 2^e. */
 int32_t m1_get_info(const m1_handle *h, double *dt, int32_t *n_nu, int32_t *prec,
                     int64_t *ncell, int32_t *scale_exp2);

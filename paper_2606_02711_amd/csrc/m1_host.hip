@@ -1006,6 +1006,26 @@ int32_t m1_get_state(m1_handle* h, double* d_E, double* d_Fx, double* d_Fy) {
   return m1_sync(h);
 }
 
+int32_t m1_get_state_region(m1_handle* h, int32_t i0, int32_t i1, int32_t j0, int32_t j1,
+                            double* d_E, double* d_Fx, double* d_Fy) {
+  if (!h) return fail(M1_EINVAL, "handle is NULL");
+  if (i0 < 0 || j0 < 0 || i1 > h->cfg.nx || j1 > h->cfg.ny || i0 >= i1 || j0 >= j1)
+    return fail(M1_EINVAL, "region [%d,%d) x [%d,%d) outside the %d x %d grid or empty", i0, i1,
+                j0, j1, h->cfg.nx, h->cfg.ny);
+  double* dst[3] = {d_E, d_Fx, d_Fy};
+  for (int q = 0; q < 3; ++q) {
+    if (!dst[q]) continue;
+    const char* src = h->ws + h->L.state[h->cur][q];
+    hipError_t e = h->cfg.prec == M1_FP32
+        ? launch_region_copy<float>((const float*)src, dst[q], h->cfg.nx, h->cfg.ny, h->nb, i0, j0,
+                                    i1 - i0, j1 - j0, -h->e2, h->stream)
+        : launch_region_copy<double>((const double*)src, dst[q], h->cfg.nx, h->cfg.ny, h->nb, i0,
+                                     j0, i1 - i0, j1 - j0, -h->e2, h->stream);
+    if (e != hipSuccess) return fail(M1_EDEVICE, "copy launch: %s", hipGetErrorString(e));
+  }
+  return m1_sync(h);
+}
+
 int32_t m1_set_state(m1_handle* h, const double* d_E, const double* d_Fx, const double* d_Fy) {
   if (!h || !d_E || !d_Fx || !d_Fy) return fail(M1_EINVAL, "bad arguments");
   size_t n = (size_t)h->nb * h->nc;

@@ -39,6 +39,9 @@ hipError_t launch_residual(const R* E0, const R* E1, size_t n, double* partial, 
 // dst = src * 2^e2 with a type conversion (state <-> FP64 physical units)
 template <typename S, typename D>
 hipError_t launch_scale_copy(const S* src, D* dst, size_t n, int e2, hipStream_t s);
+template <typename S>
+hipError_t launch_region_copy(const S* src, double* dst, int nx, int ny, int nb, int i0, int j0,
+                              int w, int h, int e2, hipStream_t s);
 hipError_t launch_force_out(const double* force, size_t nc, int e2, double* fx, double* fy,
                             double* gx, double* gy, hipStream_t s);
 

@@ -641,6 +641,19 @@ __global__ void k_scale_copy(const S* __restrict__ src, D* __restrict__ dst, siz
     dst[q] = (D)ldexp((double)src[q], e2);
 }
 
+// dst[k][jj][ii] = 2^e2 src[k][j0 + jj][i0 + ii] for a w x h window of every bin.
+template <typename S>
+__global__ void k_region_copy(const S* __restrict__ src, double* __restrict__ dst, int nx, int ny,
+                              int nb, int i0, int j0, int w, int h, int e2) {
+  const size_t per = (size_t)w * h, n = per * nb;
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += (size_t)gridDim.x * blockDim.x) {
+    const size_t k = q / per, r = q % per;
+    const int jj = (int)(r / w), ii = (int)(r % w);
+    dst[q] = ldexp((double)src[(k * ny + j0 + jj) * nx + i0 + ii], e2);
+  }
+}
+
 __global__ void k_force_out(const double* __restrict__ force, size_t nc, int e2,
                             double* fx, double* fy, double* gx, double* gy) {
   for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < nc;
@@ -738,6 +751,20 @@ hipError_t launch_scale_copy(const S* src, D* dst, size_t n, int e2, hipStream_t
   hipLaunchKernelGGL((k_scale_copy<S, D>), dim3(g ? g : 1), dim3(256), 0, s, src, dst, n, e2);
   return hipGetLastError();
 }
+
+template <typename S>
+hipError_t launch_region_copy(const S* src, double* dst, int nx, int ny, int nb, int i0, int j0,
+                              int w, int h, int e2, hipStream_t s) {
+  const size_t n = (size_t)w * h * nb;
+  unsigned g = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL((k_region_copy<S>), dim3(g ? g : 1), dim3(256), 0, s, src, dst, nx, ny, nb,
+                     i0, j0, w, h, e2);
+  return hipGetLastError();
+}
+template hipError_t launch_region_copy<float>(const float*, double*, int, int, int, int, int, int,
+                                              int, int, hipStream_t);
+template hipError_t launch_region_copy<double>(const double*, double*, int, int, int, int, int, int,
+                                               int, int, hipStream_t);
 
 hipError_t launch_force_out(const double* force, size_t nc, int e2, double* fx, double* fy,
                             double* gx, double* gy, hipStream_t s) {

@@ -89,6 +89,7 @@ def lib():
         "m1_residual": (I32, [VP, P(D)]),
         "m1_get_state": (I32, [VP, VP, VP, VP]),
         "m1_set_state": (I32, [VP, VP, VP, VP]),
+        "m1_get_state_region": (I32, [VP, I32, I32, I32, I32, VP, VP, VP]),
         "m1_get_info": (I32, [VP, P(D), P(I32), P(I32), P(I64), P(I32)]),
         "m1_batch_workspace_bytes": (I32, [P(VP), I32, P(ctypes.c_size_t)]),
         "m1_batch_init": (I32, [P(VP), I32, VP, ctypes.c_size_t, I32, P(VP)]),
@@ -123,7 +124,7 @@ def lib():
 def exported_symbols():
     return ["m1_default_config", "m1_num_bins", "m1_workspace_bytes",
             "m1_count_temperature_classes", "m1_init", "m1_step", "m1_force",
-            "m1_solve_steady", "m1_residual", "m1_get_state", "m1_set_state", "m1_get_info",
+            "m1_solve_steady", "m1_residual", "m1_get_state", "m1_set_state", "m1_get_state_region", "m1_get_info",
             "m1_batch_workspace_bytes", "m1_batch_init", "m1_batch_step", "m1_batch_info",
             "m1_batch_free", "m1_batch_set_tile", "m1_batch_workspace_bound",
             "m1_server_create", "m1_server_submit", "m1_server_run", "m1_server_poll",
@@ -266,6 +267,16 @@ class M1Grid:
         Fx = torch.empty_like(E)
         Fy = torch.empty_like(E)
         check(lib().m1_get_state(self.h, E.data_ptr(), Fx.data_ptr(), Fy.data_ptr()))
+        return E, Fx, Fy
+
+    def state_region(self, i0, i1, j0, j1):
+        """E, Fx, Fy of cells i0 <= i < i1, j0 <= j < j1, all bins (float64)."""
+        torch = _torch()
+        E = torch.empty((self.nb, j1 - j0, i1 - i0), dtype=torch.float64, device="cuda")
+        Fx = torch.empty_like(E)
+        Fy = torch.empty_like(E)
+        check(lib().m1_get_state_region(self.h, int(i0), int(i1), int(j0), int(j1), E.data_ptr(),
+                                        Fx.data_ptr(), Fy.data_ptr()))
         return E, Fx, Fy
 
     def set_state(self, E, Fx, Fy):
