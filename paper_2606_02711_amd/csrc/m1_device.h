@@ -19,6 +19,7 @@ struct GridArgs {
   int nx, ny, nb, geom;
   int bc[4];
   int recoil, doppler;
+  int islands;            // FP32 storage with a finite fp64_tau: island cells may exist
   R ctdt;                 // c_tilde * dt
   R ctdt_c;               // c_tilde * dt / c (work term)
   // ping-pong state: in (E, Fx, Fy) -> out

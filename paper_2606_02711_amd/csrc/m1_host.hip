@@ -203,6 +203,7 @@ void fill_args(m1_handle* h, GridArgs<R>* a) {
     g.nx = nx; g.ny = ny; g.nb = h->nb; g.geom = c.geom;
     for (int s = 0; s < 4; ++s) g.bc[s] = c.bc[s];
     g.recoil = c.recoil; g.doppler = c.doppler;
+    g.islands = (c.prec == M1_FP32 && c.fp64_tau < INFINITY) ? 1 : 0;
     g.ctdt = (R)(c.c_tilde * h->dt);
     g.ctdt_c = (R)(c.c_tilde * h->dt / kC);
     int in = dir, out = dir ^ 1;
@@ -676,6 +677,7 @@ struct m1_batch {
   int sp = 0;                           // steps taken mod 2
   int blocks_adv[kNumBatchVariants] = {0, 0, 0, 0};
   int blocks_freq = 0;
+  int islands = 0;                      // some member may have island cells
   int variant = -1;                     // chosen tile variant (-1: tuning)
   int trial_variant = 0, trial_step = 0;
   double trial_ms[kNumBatchVariants] = {0, 0, 0, 0};
@@ -749,7 +751,8 @@ hipError_t batch_launch_step(m1_batch* b, int variant) {
   hipError_t e = launch_advect_batched<R>(variant, args, par, b->n, b->sp, offa,
                                           b->blocks_adv[variant], b->stream);
   if (e != hipSuccess) return e;
-  return launch_freq_batched<R>(args, par, b->n, b->sp, offf, b->blocks_freq, b->stream);
+  return launch_freq_batched<R>(args, par, b->n, b->sp, offf, b->blocks_freq, b->islands,
+                                b->stream);
 }
 
 hipError_t batch_one_step(m1_batch* b, int variant) {
@@ -789,6 +792,8 @@ int32_t m1_batch_init(m1_handle* const* hs, int32_t n, void* d_ws, size_t ws_byt
   size_t need = batch_layout(hs, n, &b->args_off, &b->par_off, &b->offa_off, &b->offf_off);
   if (ws_bytes < need) { delete b; return fail(M1_ENOMEM, "batch workspace %zu < %zu", ws_bytes, need); }
   b->use_graph = use_graph != 0 && b->stream != nullptr;
+  for (int q = 0; q < n; ++q)
+    if (hs[q]->cfg.prec == M1_FP32 && hs[q]->cfg.fp64_tau < INFINITY) b->islands = 1;
   // work lists: prefix sums of work items per grid, per tile variant
   std::vector<int> offa((size_t)kNumBatchVariants * (n + 1)), offf(n + 1, 0);
   int64_t tot[kNumBatchVariants] = {0, 0, 0, 0};

@@ -27,7 +27,7 @@ hipError_t launch_advect_batched(int variant, const GridArgs<R>* args, const int
                                  int sp, const int* off, int nblocks, hipStream_t s);
 template <typename R>
 hipError_t launch_freq_batched(const GridArgs<R>* args, const int* par, int n, int sp,
-                               const int* off, int nblocks, hipStream_t s);
+                               const int* off, int nblocks, int islands, hipStream_t s);
 template <typename R>
 int batched_occupancy(int variant);
 template <typename R>

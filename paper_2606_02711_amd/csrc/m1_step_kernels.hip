@@ -433,8 +433,23 @@ template <typename T>
 __device__ __forceinline__ T e1_series(T z) {
   constexpr int n = sizeof(T) == 8 ? 16 : 9;     // last term < 2e-18 / 2e-9
   T r = T(1);
-  for (int j = n; j >= 1; --j) r = T(1) + z * r / T(j + 1);
+#pragma unroll
+  for (int j = n; j >= 1; --j) r = T(1) + z * r * (T(1) / T(j + 1));   // 1/(j+1) folds
   return r;
+}
+
+// e^x.  Float: the hardware's 2^t with t = x log2(e) carried to about 2^-40
+// (head product, its rounding error by FMA, and the tail of log2(e)), so the
+// result keeps about 1 ulp; x = 0 gives exactly 1.  Arguments below -150
+// give 0.  Double: the library exp.
+__device__ __forceinline__ double fexp(double x) { return exp(x); }
+__device__ __forceinline__ float fexp(float x) {
+  x = x > -150.0f ? x : -150.0f;
+  const float L = 1.44269502162933349609375f;        // log2(e) rounded to float
+  const float Llo = 1.92596298909109e-8f;             // log2(e) - L
+  const float t = x * L;
+  const float err = __builtin_fmaf(x, L, -t) + x * Llo;
+  return __builtin_amdgcn_exp2f(t) * (1.0f + err * 0.693147180559945309f);
 }
 
 // Exponential-scheme interface between bins l < r (frequency flux
@@ -453,12 +468,134 @@ __device__ __forceinline__ void interface_rates(T ql, T Cl, T qr, T Cr, T& gl, T
   const T A = -Cl * ql, B = Cr * qr;
   T m = A > B ? A : B;
   m = m > T(0) ? m : T(0);
-  const T eAm = exp(A - m), eBm = exp(B - m), em = exp(-m);
-  const T sA = fabs(A) < T(0.5) ? em * e1_series(A) : (eAm - em) / A;
-  const T sB = fabs(B) < T(0.5) ? em * e1_series(B) : (eBm - em) / B;
-  const T iden = T(1) / (ql * sA + qr * sB);
+  const T eAm = fexp(A - m), eBm = fexp(B - m), em = fexp(-m);
+  // |A|, |B| >= 1/2 on the division branches; den is positive
+  const T sA = fabs(A) < T(0.5) ? em * e1_series(A) : (eAm - em) * frcp(A);
+  const T sB = fabs(B) < T(0.5) ? em * e1_series(B) : (eBm - em) * frcp(B);
+  const T den = ql * sA + qr * sB;
+  const T iden = den >= recip_floor<T>() ? frcp(den) : T(1) / den;
   gl = eAm * iden;
   gr = eBm * iden;
+}
+
+// Coefficients of bin k of one cell (Appendix A): q = (dnu_k/2)/K_k, with
+// K_k = (dnu_D^2/2) alpha <H>_k (q = 0 flags a bin without line opacity), and
+// C_k = K_k R_k + (nu_k/c) D_k : grad u, from the post-source state (e, X, Y).
+template <typename R, typename T>
+struct FreqCell {
+  T dd, hkT, gxx, gyy, gxy, gpp;
+  bool recoil, doppler;
+  __device__ __forceinline__ void coeffs(const GridArgs<R>& a, int k, R h, R e, R X, R Y, T& q,
+                                         T& C) const {
+    const T K = dd * (T)h;
+    T Cv = T(0);
+    if (recoil) Cv += K * (hkT - (T)a.two_nu[k]);
+    if (doppler) {
+      const Eddington<T> D = closure_state<T>((T)e, (T)X, (T)Y);
+      Cv += (T)a.nu_c[k] * (D.xx * gxx + D.yy * gyy + D.xy * gxy + D.pp * gpp);
+    }
+    C = Cv;
+    const T hdnu = (T)(0.5 * a.dnu[k]);
+    q = K >= recip_floor<T>() ? hdnu * frcp(K) : (K > T(0) ? hdnu / K : T(0));
+  }
+};
+
+// Forward elimination over the bins of one cell: writes z_k = d_k/p_k and
+// w_k = b_{k+1}/p_k, accumulates the force.  The state is only read here
+// and the scratch only written.  With double storage the loads of a bin are
+// issued one bin ahead of their use (the latency dominates there); with
+// float storage they are issued just in time, which keeps the register count
+// at full occupancy.
+template <typename R, typename T>
+__device__ __forceinline__ void freq_forward(const GridArgs<R>& a, const FreqCell<R, T>& fc,
+                                             size_t c, size_t nc, const R* __restrict__ Ein,
+                                             const R* __restrict__ Xin,
+                                             const R* __restrict__ Yin, const R* __restrict__ hb,
+                                             R* __restrict__ zs, R* __restrict__ ws, T al,
+                                             double acF, double* f4) {
+  const int nb = a.nb;
+  const double ctdt = (double)a.ctdt;
+  double fx = 0.0, fy = 0.0, gx = 0.0, gy = 0.0;
+  auto force = [&](int k, R h, R X, R Y) {
+    // force density: sum_k dnu_k alpha_F,k F**_k (and the line part)
+    const double dn = a.dnu[k];
+    const double aH = (double)al * (double)h;
+    const double aF = aH + acF;
+    fx += dn * aF * (double)X;
+    fy += dn * aF * (double)Y;
+    gx += dn * aH * (double)X;
+    gy += dn * aH * (double)Y;
+  };
+  constexpr bool kAhead = sizeof(R) == 8;
+  R e0 = Ein[c], x0 = Xin[c], y0 = Yin[c], h0 = hb[0];
+  R e1 = R(0), x1 = R(0), y1 = R(0), h1 = R(0);
+  if (kAhead && nb > 1) { e1 = Ein[nc + c]; x1 = Xin[nc + c]; y1 = Yin[nc + c]; h1 = hb[1]; }
+  T qc, Cc;
+  fc.coeffs(a, 0, h0, e0, x0, y0, qc, Cc);
+  force(0, h0, x0, y0);
+  double s_prev = 1.0, ip_prev = 1.0, d_prev = 0.0, a_prev = 0.0;
+  double b_k = 0.0;                // rate of bin k toward k-1 (zero at the lower end)
+  for (int k = 0; k < nb; ++k) {
+    R e2 = R(0), x2 = R(0), y2 = R(0), h2 = R(0);
+    if constexpr (kAhead) {
+      if (k + 2 < nb) {
+        const size_t i2 = (size_t)(k + 2) * nc + c;
+        e2 = Ein[i2]; x2 = Xin[i2]; y2 = Yin[i2]; h2 = hb[k + 2];
+      }
+    } else if (k + 1 < nb) {
+      const size_t i1 = (size_t)(k + 1) * nc + c;
+      e1 = Ein[i1]; x1 = Xin[i1]; y1 = Yin[i1]; h1 = hb[k + 1];
+    }
+    double a_k = 0.0, b_next = 0.0;
+    if (k + 1 < nb) {
+      T qn, Cn;
+      fc.coeffs(a, k + 1, h1, e1, x1, y1, qn, Cn);
+      force(k + 1, h1, x1, y1);
+      T gl, gr;
+      if (qc > T(0) && qn > T(0)) {
+        interface_rates<T>(qc, Cc, qn, Cn, gl, gr);
+      } else {
+        gl = Cc < T(0) ? -Cc : T(0);       // K -> 0: first-order upwind
+        gr = Cn > T(0) ? Cn : T(0);
+      }
+      a_k = ctdt * (double)gl * a.inv_dnu[k];
+      b_next = ctdt * (double)gr * a.inv_dnu[k + 1];
+      qc = qn;
+      Cc = Cn;
+    }
+    const double y = a.dnu[k] * (double)e0;
+    const double s = (k == 0) ? 1.0 : 1.0 + b_k * s_prev * ip_prev;
+    const double d = (k == 0) ? y : y + a_prev * d_prev * ip_prev;
+    const double p = s + a_k;
+    const double ip = 1.0 / p;
+    const size_t idx = (size_t)k * nc + c;
+    zs[idx] = (R)(d * ip);
+    ws[idx] = (R)(b_next * ip);
+    s_prev = s; ip_prev = ip; d_prev = d; a_prev = a_k; b_k = b_next;
+    e0 = e1;
+    if constexpr (kAhead) { e1 = e2; x1 = x2; y1 = y2; h1 = h2; }
+  }
+  f4[0] = fx; f4[1] = fy; f4[2] = gx; f4[3] = gy;
+}
+
+// Back substitution y_k = z_k + w_k y_{k+1} and the H rescale
+// F^{n+1} = (F**/E**) E^{n+1}, in place over the state.
+template <typename R>
+__device__ __forceinline__ void freq_backward(const GridArgs<R>& a, size_t c, size_t nc,
+                                              R* __restrict__ Eio, R* __restrict__ Xio,
+                                              R* __restrict__ Yio, const R* __restrict__ zs,
+                                              const R* __restrict__ ws) {
+  double y = 0.0;
+  for (int k = a.nb - 1; k >= 0; --k) {
+    const size_t idx = (size_t)k * nc + c;
+    y = (double)zs[idx] + (double)ws[idx] * y;
+    const R En = (R)(y * a.inv_dnu[k]);
+    R fxo, fyo;
+    reduced_flux<R>(Eio[idx], Xio[idx], Yio[idx], fxo, fyo);
+    Eio[idx] = En;
+    Xio[idx] = fxo * En;
+    Yio[idx] = fyo * En;
+  }
 }
 
 // Frequency step and force of one cell.  R: storage type; T: arithmetic of
@@ -476,110 +613,59 @@ __device__ __forceinline__ void interface_rates(T ql, T Cl, T qr, T Cr, T& gl, T
 template <typename R, typename T>
 __device__ void freq_cell(const GridArgs<R>& a, size_t c) {
   const size_t nc = (size_t)a.nx * a.ny;
-  const int nb = a.nb;
   const int cl = a.cls[c];
+  FreqCell<R, T> fc;
   const T al = (T)a.alpha[c];
-  const double acF = (double)a.acF[c];
-  const T gxx = (T)a.grad[c], gyy = (T)a.grad[nc + c], gxy = (T)a.grad[2 * nc + c],
-          gpp = (T)a.grad[3 * nc + c];
-  const T dd = (T)a.dD2h[cl] * al;           // 0.5 dnu_D^2 alpha
-  const T hkT = (T)a.hkT[cl];
-  const double ctdt = (double)a.ctdt;
-  const R* hb = a.hbar + (size_t)cl * nb;
-  const bool use_recoil = a.recoil != 0;
-  const bool use_doppler = a.doppler != 0 &&
-      ((gxx != T(0)) || (gyy != T(0)) || (gxy != T(0)) || (gpp != T(0)));
-
-  double fx = 0.0, fy = 0.0, gx = 0.0, gy = 0.0;
-  // coefficients of bin k: q = (dnu_k/2)/K_k and C_k (Appendix A)
-  auto coeffs = [&](int k, T& q, T& C) {
-    const size_t idx = (size_t)k * nc + c;
-    const R e = a.Eo[idx], X = a.Fxo[idx], Y = a.Fyo[idx];
-    const R h = hb[k];
-    const T K = dd * (T)h;
-    T Cv = T(0);
-    if (use_recoil) Cv += K * (hkT - (T)a.two_nu[k]);
-    if (use_doppler) {
-      const Eddington<T> D = closure_state<T>((T)e, (T)X, (T)Y);
-      Cv += (T)a.nu_c[k] * (D.xx * gxx + D.yy * gyy + D.xy * gxy + D.pp * gpp);
-    }
-    C = Cv;
-    q = K > T(0) ? T(0.5 * a.dnu[k]) / K : T(0);     // 0 flags "no line opacity"
-    // force density: sum_k dnu_k alpha_F,k F**_k (and the line part)
-    const double dn = a.dnu[k];
-    const double aH = (double)al * (double)h;
-    const double aF = aH + acF;
-    fx += dn * aF * (double)X;
-    fy += dn * aF * (double)Y;
-    gx += dn * aH * (double)X;
-    gy += dn * aH * (double)Y;
-  };
-
-  T qc, Cc;
-  coeffs(0, qc, Cc);
-  double s_prev = 1.0, ip_prev = 1.0, d_prev = 0.0, a_prev = 0.0;
-  double b_k = 0.0;                // rate of bin k toward k-1 (zero at the lower end)
-  for (int k = 0; k < nb; ++k) {
-    double a_k = 0.0, b_next = 0.0;
-    if (k + 1 < nb) {
-      T qn, Cn;
-      coeffs(k + 1, qn, Cn);
-      T gl, gr;
-      if (qc > T(0) && qn > T(0)) {
-        interface_rates<T>(qc, Cc, qn, Cn, gl, gr);
-      } else {
-        gl = Cc < T(0) ? -Cc : T(0);       // K -> 0: first-order upwind
-        gr = Cn > T(0) ? Cn : T(0);
-      }
-      a_k = ctdt * (double)gl * a.inv_dnu[k];
-      b_next = ctdt * (double)gr * a.inv_dnu[k + 1];
-      qc = qn;
-      Cc = Cn;
-    }
-    const size_t idx = (size_t)k * nc + c;
-    const double y = a.dnu[k] * (double)a.Eo[idx];
-    const double s = (k == 0) ? 1.0 : 1.0 + b_k * s_prev * ip_prev;
-    const double d = (k == 0) ? y : y + a_prev * d_prev * ip_prev;
-    const double p = s + a_k;
-    const double ip = 1.0 / p;
-    a.zs[idx] = (R)(d * ip);
-    a.ws[idx] = (R)(b_next * ip);
-    s_prev = s; ip_prev = ip; d_prev = d; a_prev = a_k; b_k = b_next;
-  }
-  // back substitution and F rescale (F^{n+1} = (F**/E**) E^{n+1})
-  double y = 0.0;
-  for (int k = nb - 1; k >= 0; --k) {
-    const size_t idx = (size_t)k * nc + c;
-    y = (double)a.zs[idx] + (double)a.ws[idx] * y;
-    const R En = (R)(y * a.inv_dnu[k]);
-    R fxo, fyo;
-    reduced_flux<R>(a.Eo[idx], a.Fxo[idx], a.Fyo[idx], fxo, fyo);
-    a.Eo[idx] = En;
-    a.Fxo[idx] = fxo * En;
-    a.Fyo[idx] = fyo * En;
-  }
-  a.force[c] = fx;
-  a.force[nc + c] = fy;
-  a.force[2 * nc + c] = gx;
-  a.force[3 * nc + c] = gy;
+  fc.gxx = (T)a.grad[c];
+  fc.gyy = (T)a.grad[nc + c];
+  fc.gxy = (T)a.grad[2 * nc + c];
+  fc.gpp = (T)a.grad[3 * nc + c];
+  fc.dd = (T)a.dD2h[cl] * al;           // 0.5 dnu_D^2 alpha
+  fc.hkT = (T)a.hkT[cl];
+  fc.recoil = a.recoil != 0;
+  fc.doppler = a.doppler != 0 &&
+      ((fc.gxx != T(0)) || (fc.gyy != T(0)) || (fc.gxy != T(0)) || (fc.gpp != T(0)));
+  double f4[4];
+  freq_forward<R, T>(a, fc, c, nc, a.Eo, a.Fxo, a.Fyo, a.hbar + (size_t)cl * a.nb, a.zs, a.ws,
+                     al, (double)a.acF[c], f4);
+  freq_backward<R>(a, c, nc, a.Eo, a.Fxo, a.Fyo, a.zs, a.ws);
+  a.force[c] = f4[0];
+  a.force[nc + c] = f4[1];
+  a.force[2 * nc + c] = f4[2];
+  a.force[3 * nc + c] = f4[3];
 }
 
-template <typename R>
+// Pass 0 steps every cell of a double grid and the non-island cells of a
+// float grid (coefficients in float); pass 1 the island cells of a float grid
+// (coefficients in double).  Separate kernels, so the rare double-coefficient
+// code does not set the register budget of the common one.
+template <typename R, int P>
 __device__ __forceinline__ void freq_dispatch(const GridArgs<R>& a, size_t c) {
-  if (sizeof(R) == 8 || a.island[c]) freq_cell<R, double>(a, c);
-  else freq_cell<R, float>(a, c);
+  if constexpr (sizeof(R) == 8) {
+    freq_cell<R, double>(a, c);
+  } else if constexpr (P == 0) {
+    if (!a.island[c]) freq_cell<R, float>(a, c);
+  } else {
+    if (a.island[c]) freq_cell<R, double>(a, c);
+  }
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_freq(GridArgs<R> a) {
+// The float pass fits 64 registers: eight waves per SIMD hide its latency.
+template <typename R, int P>
+constexpr int kFreqWaves = (sizeof(R) == 4 && P == 0) ? 8 : 1;
+
+template <typename R, int P>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFreqWaves<R, P>)))
+void k_freq(GridArgs<R> a) {
   const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= (size_t)a.nx * a.ny) return;
-  freq_dispatch(a, c);
+  freq_dispatch<R, P>(a, c);
 }
 
 // Batched, persistent frequency step: work item = 256 cells of one grid.
-template <typename R>
-__global__ __launch_bounds__(256) void k_freq_batched(const GridArgs<R>* __restrict__ args,
+template <typename R, int P>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFreqWaves<R, P>)))
+void k_freq_batched(const GridArgs<R>* __restrict__ args,
                                                       const int* __restrict__ par, int n, int sp,
                                                       const int* __restrict__ off) {
   const int total = off[n];
@@ -591,7 +677,7 @@ __global__ __launch_bounds__(256) void k_freq_batched(const GridArgs<R>* __restr
     }
     const GridArgs<R>& a = args[((par[lo] ^ sp) & 1) * n + lo];
     const size_t c = (size_t)(w - off[lo]) * 256 + threadIdx.x;
-    if (c < (size_t)a.nx * a.ny) freq_dispatch(a, c);
+    if (c < (size_t)a.nx * a.ny) freq_dispatch<R, P>(a, c);
   }
 }
 
@@ -679,7 +765,9 @@ hipError_t launch_advect(const GridArgs<R>& a, hipStream_t s) {
 template <typename R>
 hipError_t launch_freq(const GridArgs<R>& a, hipStream_t s) {
   size_t nc = (size_t)a.nx * a.ny;
-  hipLaunchKernelGGL((k_freq<R>), dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, a);
+  const dim3 g((unsigned)((nc + 255) / 256));
+  hipLaunchKernelGGL((k_freq<R, 0>), g, dim3(256), 0, s, a);
+  if (sizeof(R) == 4 && a.islands) hipLaunchKernelGGL((k_freq<R, 1>), g, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -705,8 +793,10 @@ hipError_t launch_advect_batched(int variant, const GridArgs<R>* args, const int
 
 template <typename R>
 hipError_t launch_freq_batched(const GridArgs<R>* args, const int* par, int n, int sp,
-                               const int* off, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_freq_batched<R>), dim3(nblocks), dim3(256), 0, s, args, par, n, sp, off);
+                               const int* off, int nblocks, int islands, hipStream_t s) {
+  hipLaunchKernelGGL((k_freq_batched<R, 0>), dim3(nblocks), dim3(256), 0, s, args, par, n, sp, off);
+  if (sizeof(R) == 4 && islands)
+    hipLaunchKernelGGL((k_freq_batched<R, 1>), dim3(nblocks), dim3(256), 0, s, args, par, n, sp, off);
   return hipGetLastError();
 }
 
@@ -726,7 +816,7 @@ int batched_occupancy(int variant) {
 template <typename R>
 int freq_batched_occupancy() {
   int nb = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_freq_batched<R>, 256, 0);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_freq_batched<R, 0>, 256, 0);
   return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
@@ -776,8 +866,8 @@ hipError_t launch_force_out(const double* force, size_t nc, int e2, double* fx, 
 template hipError_t launch_step<float>(const GridArgs<float>&, hipStream_t);
 template hipError_t launch_advect_batched<float>(int, const GridArgs<float>*, const int*, int, int, const int*, int, hipStream_t);
 template hipError_t launch_advect_batched<double>(int, const GridArgs<double>*, const int*, int, int, const int*, int, hipStream_t);
-template hipError_t launch_freq_batched<float>(const GridArgs<float>*, const int*, int, int, const int*, int, hipStream_t);
-template hipError_t launch_freq_batched<double>(const GridArgs<double>*, const int*, int, int, const int*, int, hipStream_t);
+template hipError_t launch_freq_batched<float>(const GridArgs<float>*, const int*, int, int, const int*, int, int, hipStream_t);
+template hipError_t launch_freq_batched<double>(const GridArgs<double>*, const int*, int, int, const int*, int, int, hipStream_t);
 template int batched_occupancy<float>(int);
 template int batched_occupancy<double>(int);
 template int freq_batched_occupancy<float>();

@@ -21,18 +21,19 @@ def rel(a, b):
     return float(np.linalg.norm(a - b)) / nb if nb > 0 else float(np.linalg.norm(a))
 
 
-def run_gpu(p, steps, prec):
+def run_gpu(p, steps, prec, fp64_tau=float("inf")):
     from paper_2606_02711_amd import m1
-    print(f"[gpu] {p['geom']} {p['nx']}x{p['ny']} steps={steps} prec={prec}", flush=True)
-    g = m1.M1Grid(p, prec=prec)
+    print(f"[gpu] {p['geom']} {p['nx']}x{p['ny']} steps={steps} prec={prec} fp64_tau={fp64_tau}",
+          flush=True)
+    g = m1.M1Grid(p, prec=prec, fp64_tau=fp64_tau)
     g.step(steps)
     E, Fx, Fy = [t.double().cpu().numpy() for t in g.state()]
     f = g.force().cpu().numpy()
     return g, E, Fx, Fy, f
 
 
-def compare(p, steps, prec, tolE, tolF, oracle=None):
-    g, E, Fx, Fy, f = run_gpu(p, steps, prec)
+def compare(p, steps, prec, tolE, tolF, oracle=None, fp64_tau=float("inf")):
+    g, E, Fx, Fy, f = run_gpu(p, steps, prec, fp64_tau)
     o = oracle if oracle is not None else M.run(p, steps=steps)
     assert g.dt == pytest.approx(o.dt, rel=1e-14)
     errs = dict(E=rel(E, o.E), Fx=rel(Fx, o.Fx), Fy=rel(Fy, o.Fy), force=rel(f, o.force))
@@ -58,6 +59,16 @@ def test_fp64_parity_random_heterogeneous(geom, nx, ny, seed, hw):
 def test_fp32_parity_random_heterogeneous(geom, nx, ny, seed, hw):
     p = inputs.random_small(geom, nx, ny, seed, half_width=hw, log_nHI=(-4.0, 1.0))
     compare(p, 8, "fp32", 1e-5, 1e-4)
+
+
+@pytest.mark.parametrize("fp64_tau", [0.0, 30.0])
+def test_fp32_island_cells_parity(fp64_tau):
+    """FP32 storage with double frequency-step coefficients in the cells whose
+    line-centre depth reaches fp64_tau (all cells at 0)."""
+    p = inputs.random_small("cyl", 67, 33, 5, half_width=1e5, log_nHI=(-4.0, 1.0))
+    g, errs = compare(p, 8, "fp32", 1e-5, 1e-4, fp64_tau=fp64_tau)
+    _, E0, _, _, _ = run_gpu(p, 8, "fp32")
+    assert not np.array_equal(g.state()[0].cpu().numpy(), E0)   # the island path ran
 
 
 def test_reflecting_box_and_line_off_cells():
@@ -146,6 +157,22 @@ def test_batched_equals_alone_bitwise(prec):
     bk, ms = b.info()
     assert bk in (7, 14, 28, 49) and all(t > 0 for t in ms)
     b.step(7)
+    _assert_same(gs, ref)
+
+
+def test_batched_with_island_cells_equals_alone():
+    from paper_2606_02711_amd import m1
+    import torch
+    ps = _mixed_problems()[:3]
+    taus = (float("inf"), 30.0, 0.0)
+    ref = []
+    for p, t in zip(ps, taus):
+        _, E, Fx, Fy, f = run_gpu(p, 9, "fp32", t)
+        ref.append((E, Fx, Fy, f))
+    print("[gpu] batched islands", flush=True)
+    s = torch.cuda.Stream()
+    gs = [m1.M1Grid(p, prec="fp32", fp64_tau=t, stream=s) for p, t in zip(ps, taus)]
+    m1.M1Batch(gs, use_graph=True).step(9)
     _assert_same(gs, ref)
 
 
