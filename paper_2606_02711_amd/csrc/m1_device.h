@@ -13,6 +13,13 @@ constexpr double kC = 2.99792458e10;        // speed of light [cm/s]
 constexpr int kVacuum = 0;
 constexpr int kReflect = 1;
 
+// Frequency-step scratch of one cell and bin: z_k = d_k/p_k, w_k = b_{k+1}/p_k
+// (stored together so each is one 8- or 16-byte access).
+template <typename R>
+struct __attribute__((aligned(2 * sizeof(R)))) ZW {
+  R z, w;
+};
+
 // Kernel arguments of one grid.  Pointers are into the handle's workspace.
 template <typename R>
 struct GridArgs {
@@ -45,7 +52,7 @@ struct GridArgs {
   const R *yidl, *yhm, *yhp;
   const R *cy;                 // [ny] ctdt / dz_j
   // frequency step
-  R *zs, *ws;             // scratch [nb][ncell]
+  ZW<R> *zw;              // scratch [nb][ncell]
   double *force;          // [4][ncell]
 };
 

@@ -94,7 +94,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
   size_t state[2][3];
-  size_t zs, wsc, force;
+  size_t zw, force;
   size_t cls, island, alpha, acF, acabs, pda, em, grad, ufx, ufy;
   size_t hbar, phi, dD2h, hkT;
   size_t dnu, inv_dnu, two_nu, nu_c, edges;
@@ -112,8 +112,7 @@ Layout make_layout(int nx, int ny, int nb, int64_t ncls, size_t rs) {
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
   for (int b = 0; b < 2; ++b)
     for (int f = 0; f < 3; ++f) L.state[b][f] = take(nbc * rs);
-  L.zs = take(nbc * rs);
-  L.wsc = take(nbc * rs);
+  L.zw = take(2 * nbc * rs);
   L.force = take(4 * nc * sizeof(double));
   L.cls = take(nc * sizeof(int32_t));
   L.island = take(nc);
@@ -242,8 +241,7 @@ void fill_args(m1_handle* h, GridArgs<R>* a) {
     g.yhm = g.yidl + (ny + 4);
     g.yhp = g.yhm + (ny + 4);
     g.cy = g.yhp + (ny + 4);
-    g.zs = (R*)(w + L.zs);
-    g.ws = (R*)(w + L.wsc);
+    g.zw = (ZW<R>*)(w + L.zw);
     g.force = (double*)(w + L.force);
   }
 }

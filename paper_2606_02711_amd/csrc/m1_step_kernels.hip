@@ -391,10 +391,10 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
       const R src = em[m] * a.phi[(size_t)cc * nb + k];
       const R kE = acabs[m] + pda[m] * hC;
       const size_t q = koff + cidx[m];
-      a.Eo[q] = (Es + ctdt * src) * frcp(R(1) + ctdt * kE);
+      __builtin_nontemporal_store((Es + ctdt * src) * frcp(R(1) + ctdt * kE), &a.Eo[q]);
       const R dF = frcp(R(1) + ctdt * aFC);
-      a.Fxo[q] = Xs * dF;
-      a.Fyo[q] = Ys * dF;
+      __builtin_nontemporal_store(Xs * dF, &a.Fxo[q]);
+      __builtin_nontemporal_store(Ys * dF, &a.Fyo[q]);
     }
     __syncthreads();
   }
@@ -511,7 +511,7 @@ __device__ __forceinline__ void freq_forward(const GridArgs<R>& a, const FreqCel
                                              size_t c, size_t nc, const R* __restrict__ Ein,
                                              const R* __restrict__ Xin,
                                              const R* __restrict__ Yin, const R* __restrict__ hb,
-                                             R* __restrict__ zs, R* __restrict__ ws, T al,
+                                             ZW<R>* __restrict__ zw, T al,
                                              double acF, double* f4) {
   const int nb = a.nb;
   const double ctdt = (double)a.ctdt;
@@ -569,8 +569,11 @@ __device__ __forceinline__ void freq_forward(const GridArgs<R>& a, const FreqCel
     const double p = s + a_k;
     const double ip = 1.0 / p;
     const size_t idx = (size_t)k * nc + c;
-    zs[idx] = (R)(d * ip);
-    ws[idx] = (R)(b_next * ip);
+    ZW<R> v;
+    v.z = (R)(d * ip);
+    v.w = (R)(b_next * ip);
+    __builtin_nontemporal_store(v.z, &zw[idx].z);
+    __builtin_nontemporal_store(v.w, &zw[idx].w);
     s_prev = s; ip_prev = ip; d_prev = d; a_prev = a_k; b_k = b_next;
     e0 = e1;
     if constexpr (kAhead) { e1 = e2; x1 = x2; y1 = y2; h1 = h2; }
@@ -583,18 +586,21 @@ __device__ __forceinline__ void freq_forward(const GridArgs<R>& a, const FreqCel
 template <typename R>
 __device__ __forceinline__ void freq_backward(const GridArgs<R>& a, size_t c, size_t nc,
                                               R* __restrict__ Eio, R* __restrict__ Xio,
-                                              R* __restrict__ Yio, const R* __restrict__ zs,
-                                              const R* __restrict__ ws) {
+                                              R* __restrict__ Yio,
+                                              const ZW<R>* __restrict__ zw) {
   double y = 0.0;
   for (int k = a.nb - 1; k >= 0; --k) {
     const size_t idx = (size_t)k * nc + c;
-    y = (double)zs[idx] + (double)ws[idx] * y;
+    ZW<R> v;
+    v.z = __builtin_nontemporal_load(&zw[idx].z);
+    v.w = __builtin_nontemporal_load(&zw[idx].w);
+    y = (double)v.z + (double)v.w * y;
     const R En = (R)(y * a.inv_dnu[k]);
     R fxo, fyo;
     reduced_flux<R>(Eio[idx], Xio[idx], Yio[idx], fxo, fyo);
-    Eio[idx] = En;
-    Xio[idx] = fxo * En;
-    Yio[idx] = fyo * En;
+    __builtin_nontemporal_store(En, &Eio[idx]);
+    __builtin_nontemporal_store(fxo * En, &Xio[idx]);
+    __builtin_nontemporal_store(fyo * En, &Yio[idx]);
   }
 }
 
@@ -626,9 +632,9 @@ __device__ void freq_cell(const GridArgs<R>& a, size_t c) {
   fc.doppler = a.doppler != 0 &&
       ((fc.gxx != T(0)) || (fc.gyy != T(0)) || (fc.gxy != T(0)) || (fc.gpp != T(0)));
   double f4[4];
-  freq_forward<R, T>(a, fc, c, nc, a.Eo, a.Fxo, a.Fyo, a.hbar + (size_t)cl * a.nb, a.zs, a.ws,
+  freq_forward<R, T>(a, fc, c, nc, a.Eo, a.Fxo, a.Fyo, a.hbar + (size_t)cl * a.nb, a.zw,
                      al, (double)a.acF[c], f4);
-  freq_backward<R>(a, c, nc, a.Eo, a.Fxo, a.Fyo, a.zs, a.ws);
+  freq_backward<R>(a, c, nc, a.Eo, a.Fxo, a.Fyo, a.zw);
   a.force[c] = f4[0];
   a.force[nc + c] = f4[1];
   a.force[2 * nc + c] = f4[2];
