@@ -143,11 +143,15 @@ __device__ __forceinline__ R causal_scale(R E, R X, R Y) {
   return q2 > e * e ? (R)(e / sqrt(q2)) : R(1);
 }
 
-template <typename R>
-__device__ __forceinline__ R minmod(R a, R b) {
-  const R m = fabs(a) < fabs(b) ? a : b;
-  const bool same = (a > R(0) && b > R(0)) || (a < R(0) && b < R(0));
-  return same ? m : R(0);
+// MinMod limiter: the argument of smaller magnitude when a and b share a
+// sign, else 0 -- which is exactly the median of (a, b, 0).  Float: one
+// v_med3_f32.  Double: max(min(a,b),0) + min(max(a,b),0), where one of the
+// two terms is always zero, so the sum is exact.
+__device__ __forceinline__ float minmod(float a, float b) {
+  return __builtin_amdgcn_fmed3f(a, b, 0.0f);
+}
+__device__ __forceinline__ double minmod(double a, double b) {
+  return fmax(fmin(a, b), 0.0) + fmin(fmax(a, b), 0.0);
 }
 
 }  // namespace m1
