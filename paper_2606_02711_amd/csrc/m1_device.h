@@ -58,10 +58,13 @@ struct GridArgs {
 
 // ---------------------------------------------------------------------------
 // Levermore closure in cancellation-free form.  With f = |F|/E and
-// s = sqrt(4 - 3 f^2):  (1 - chi)/2 = (1 - f^2)/(1 + s)  and
-// (3 chi - 1)/2 h_i h_j = 3 f_i f_j / (2 + s), so
-//   D = (1 - f^2)/(1 + s) I + 3 f (x) f / (2 + s),
-// which needs no division by |F| and stays exact at F = 0.
+// s = sqrt(4 - 3 f^2):  (1 - chi)/2 = (1 - f^2)/(1 + s) = (s - 1)/3 (since
+// s^2 - 1 = 3 (1 - f^2)) and (3 chi - 1)/2 h_i h_j = 3 f_i f_j / (2 + s), so
+//   D = (s - 1)/3 I + 3 f (x) f / (2 + s),
+// which needs no division by |F|, stays exact at F = 0, and needs a single
+// reciprocal.  s - 1 is formed exactly from the rounded s (s in [1, 2]), so
+// the isotropic part carries an absolute error of the order of the rounding
+// of s, negligible against the free-streaming part as f -> 1.
 template <typename R>
 struct Eddington {
   R xx, yy, xy, pp;
@@ -79,16 +82,15 @@ __device__ __forceinline__ double frsq(double x) { return 1.0 / sqrt(x); }
 
 template <typename R>
 __device__ __forceinline__ Eddington<R> closure_f(R fx, R fy) {
-  R f2 = fx * fx + fy * fy;
+  const R xx2 = fx * fx, yy2 = fy * fy;
+  R f2 = xx2 + yy2;
   f2 = f2 > R(1) ? R(1) : f2;
   const R s = fsqrt(R(4) - R(3) * f2);    // in [1, 2]
-  // one reciprocal for both 1/(1+s) and 1/(2+s)
-  const R r = frcp((R(1) + s) * (R(2) + s));
-  const R iso = (R(1) - f2) * (R(2) + s) * r;
-  const R g = R(3) * (R(1) + s) * r;
+  const R g = R(3) * frcp(R(2) + s);
+  const R iso = (s - R(1)) * R(1.0 / 3.0);
   Eddington<R> d;
-  d.xx = iso + g * fx * fx;
-  d.yy = iso + g * fy * fy;
+  d.xx = iso + g * xx2;
+  d.yy = iso + g * yy2;
   d.xy = g * fx * fy;
   d.pp = iso;
   return d;

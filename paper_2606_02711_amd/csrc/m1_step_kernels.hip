@@ -94,8 +94,10 @@ __device__ __forceinline__ Flux3<R> face_flux(R eLL, R xLL, R yLL, R eL, R xL, R
   R fyR = yR + minmod(dY, (yRR - yR) * iRR) * hR;
   // causality at the interface: |f| > 1 is scaled back to 1
   const R nL = fxL * fxL + fyL * fyL, nR = fxR * fxR + fyR * fyR;
-  if (nL > R(1)) { const R sL = frsq(nL); fxL *= sL; fyL *= sL; }   // rare
-  if (nR > R(1)) { const R sR = frsq(nR); fxR *= sR; fyR *= sR; }
+  if (nL > R(1) || nR > R(1)) [[unlikely]] {    // rare: one branch for both sides
+    const R sL = nL > R(1) ? frsq(nL) : R(1), sR = nR > R(1) ? frsq(nR) : R(1);
+    fxL *= sL; fyL *= sL; fxR *= sR; fyR *= sR;
+  }
   Eddington<R> DL = closure_f(fxL, fyL), DR = closure_f(fxR, fyR);
   R FxL = fxL * EL, FyL = fyL * EL, FxR = fxR * ER, FyR = fyR * ER;
   R PxL, PyL, PxR, PyR;       // row n of the pressure tensor, P = D E
