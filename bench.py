@@ -96,7 +96,7 @@ def run_batch(ps, steps, warmup):
         gs = [m1.M1Grid(p, prec=prec, stream=stream) for p in ps]
         cell_bins = sum(g.ncell * g.nb for g in gs)
         b = m1.M1Batch(gs, use_graph=True) if mode == "fp32_batched" else None
-        tune = 4 * 3                           # steps the batch spends choosing its tiles
+        tune = 5 * 3                           # steps the batch spends choosing its tiles
         for _ in range(max(warmup, tune if b else 0)):
             if b:
                 b.step(1)

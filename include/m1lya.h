@@ -180,9 +180,14 @@ int32_t m1_get_info(const m1_handle *h, double *dt, int32_t *n_nu, int32_t *prec
  * bytes (256-byte aligned); the library allocates no device memory.  Every
  * grid's result is bitwise identical to stepping it alone.
  *
+ * Tile variants: 7, 14, 28 or 49 bins per advection block with the
+ * frequency step in a second kernel, or -1: one fused kernel whose blocks
+ * walk all bins of a 32 x 16 tile and run the frequency step of their cells
+ * (FP32 batches without island cells only).
+ *
  * m1_batch_step: the first steps of a new batch time each tile variant
- * (bins per advection block) on real steps, which give identical results
- * for every variant, and keep the fastest; afterwards pairs of steps are
+ * on real steps, which give identical results for every variant, and keep
+ * the fastest; afterwards pairs of steps are
  * replayed from a captured HIP graph when use_graph is set and the stream
  * is not the null stream.  Stepping a member handle on its own between
  * batch steps is allowed (the batch re-reads the ping-pong parities). */
@@ -191,14 +196,15 @@ int32_t m1_batch_workspace_bytes(m1_handle *const *hs, int32_t n, size_t *bytes)
 int32_t m1_batch_init(m1_handle *const *hs, int32_t n, void *d_ws, size_t ws_bytes,
                       int32_t use_graph, m1_batch **out);
 int32_t m1_batch_step(m1_batch *b, int32_t nsteps);
-/* Chosen variant (bins per advection block, or 0 while tuning) and the
- * measured advection-kernel time of each variant [ms per step]. */
+/* Chosen tile variant (7, 14, 28, 49 or -1; 0 while tuning) and the
+ * measured step time of each of the five variants [ms per step; +inf for a
+ * variant that does not apply]. */
 int32_t m1_batch_info(const m1_batch *b, int32_t *bins_per_block, double *ms_per_variant,
                       int32_t n_variants);
 /* Waits for the stream, then releases the host object (not the workspace). */
 int32_t m1_batch_free(m1_batch *b);
-/* Fixes the tile variant (bins per advection block: 7, 14, 28 or 49) and
- * ends tuning; results do not depend on it. */
+/* Fixes the tile variant (7, 14, 28, 49 or -1) and ends tuning; results do
+ * not depend on it.  -1 on a batch it does not apply to: M1_EUNSUPPORTED. */
 int32_t m1_batch_set_tile(m1_batch *b, int32_t bins_per_block);
 /* Upper bound of m1_batch_workspace_bytes for any n handles of precision prec. */
 int32_t m1_batch_workspace_bound(int32_t n, int32_t prec, size_t *bytes);

@@ -673,12 +673,13 @@ struct m1_batch {
   size_t args_off = 0, par_off = 0, offa_off = 0, offf_off = 0;
   std::vector<int> par;                 // base parity per grid
   int sp = 0;                           // steps taken mod 2
-  int blocks_adv[kNumBatchVariants] = {0, 0, 0, 0};
+  int blocks_adv[kNumBatchVariants] = {};
   int blocks_freq = 0;
   int islands = 0;                      // some member may have island cells
+  bool fused_ok = false;                // the fused variant applies (float, no islands)
   int variant = -1;                     // chosen tile variant (-1: tuning)
   int trial_variant = 0, trial_step = 0;
-  double trial_ms[kNumBatchVariants] = {0, 0, 0, 0};
+  double trial_ms[kNumBatchVariants] = {};
   bool use_graph = false;
   hipGraphExec_t exec = nullptr;
   int graph_sp = -1;                    // parity at which the graph starts
@@ -748,7 +749,7 @@ hipError_t batch_launch_step(m1_batch* b, int variant) {
   const int* offf = (const int*)(b->ws + b->offf_off);
   hipError_t e = launch_advect_batched<R>(variant, args, par, b->n, b->sp, offa,
                                           b->blocks_adv[variant], b->stream);
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || variant == kFusedVariant) return e;   // fused: no separate freq kernel
   return launch_freq_batched<R>(args, par, b->n, b->sp, offf, b->blocks_freq, b->islands,
                                 b->stream);
 }
@@ -792,9 +793,10 @@ int32_t m1_batch_init(m1_handle* const* hs, int32_t n, void* d_ws, size_t ws_byt
   b->use_graph = use_graph != 0 && b->stream != nullptr;
   for (int q = 0; q < n; ++q)
     if (hs[q]->cfg.prec == M1_FP32 && hs[q]->cfg.fp64_tau < INFINITY) b->islands = 1;
+  b->fused_ok = b->prec == M1_FP32 && !b->islands;
   // work lists: prefix sums of work items per grid, per tile variant
   std::vector<int> offa((size_t)kNumBatchVariants * (n + 1)), offf(n + 1, 0);
-  int64_t tot[kNumBatchVariants] = {0, 0, 0, 0};
+  int64_t tot[kNumBatchVariants] = {};
   for (int v = 0; v < kNumBatchVariants; ++v) {
     offa[(size_t)v * (n + 1)] = 0;
     for (int q = 0; q < n; ++q) {
@@ -845,6 +847,19 @@ int32_t m1_batch_step(m1_batch* b, int32_t nsteps) {
   if (st) return st;
   int left = nsteps;
   // autotuning on real steps: time each variant's steps with events
+  auto skip_unusable = [&]() {
+    if (b->variant < 0 && b->trial_variant == kFusedVariant && !b->fused_ok) {
+      b->trial_ms[kFusedVariant] = INFINITY;
+      b->trial_variant = kNumBatchVariants;
+    }
+    if (b->variant < 0 && b->trial_variant == kNumBatchVariants) {
+      int best = 0;
+      for (int v = 1; v < kNumBatchVariants; ++v)
+        if (b->trial_ms[v] < b->trial_ms[best]) best = v;
+      b->variant = best;
+    }
+  };
+  skip_unusable();
   while (left > 0 && b->variant < 0) {
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
@@ -863,12 +878,8 @@ int32_t m1_batch_step(m1_batch* b, int32_t nsteps) {
     if (++b->trial_step == kTrialSteps + 1) {
       b->trial_ms[b->trial_variant] /= kTrialSteps;
       b->trial_step = 0;
-      if (++b->trial_variant == kNumBatchVariants) {
-        int best = 0;
-        for (int v = 1; v < kNumBatchVariants; ++v)
-          if (b->trial_ms[v] < b->trial_ms[best]) best = v;
-        b->variant = best;
-      }
+      ++b->trial_variant;
+      skip_unusable();
     }
   }
   while (left > 0) {
@@ -919,6 +930,8 @@ int32_t m1_batch_set_tile(m1_batch* b, int32_t bins_per_block) {
   if (!b) return fail(M1_EINVAL, "batch is NULL");
   for (int v = 0; v < kNumBatchVariants; ++v)
     if (kBatchBK[v] == bins_per_block) {
+      if (v == kFusedVariant && !b->fused_ok)
+        return fail(M1_EUNSUPPORTED, "the fused kernel needs FP32 grids without island cells");
       b->variant = v;
       return M1_OK;
     }

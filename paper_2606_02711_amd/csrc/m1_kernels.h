@@ -12,13 +12,17 @@ namespace m1 {
 // ---- hot path (m1_step_kernels.hip)
 template <typename R>
 hipError_t launch_step(const GridArgs<R>& a, hipStream_t s);
+// Tiles of a grid (32 x 16 cells each).
+int tile_count(int nx, int ny);
 template <typename R>
 hipError_t launch_advect(const GridArgs<R>& a, hipStream_t s);
 template <typename R>
 hipError_t launch_freq(const GridArgs<R>& a, hipStream_t s);
 // ---- batched persistent launches (one launch per kernel and step for a
-//      set of grids); variant selects the bins-per-block run length
-constexpr int kNumBatchVariants = 4;
+//      set of grids); variant selects the bins-per-block run length, or the
+//      fused kernel (kBatchBK = -1: a block walks all bins of a tile)
+constexpr int kNumBatchVariants = 5;
+constexpr int kFusedVariant = 4;
 extern const int kBatchBK[kNumBatchVariants];
 int advect_blocks(int nx, int ny, int nb, int bk);
 int freq_blocks(int nx, int ny);

@@ -184,19 +184,36 @@ __device__ __forceinline__ bool ghost_source(int ii, int jj, int nx, int ny, con
 
 constexpr int kRingPerLane = (kRX * kRY + 255) / 256;   // 3
 
-// One tile x run of bins (logical block L of grid a).
-template <typename R, int BK>
+// Where the post-source state E**, F** of an owned cell goes: to the output
+// state (the frequency step runs in its own kernel), or into the frequency
+// step of the same block (fused).
+template <typename R>
+struct WriteSink {
+  __device__ __forceinline__ void init(const GridArgs<R>&, const bool*, const size_t*,
+                                       const int*) {}
+  __device__ __forceinline__ void put(const GridArgs<R>& a, int, int, size_t q, R h, R E, R X,
+                                      R Y) {
+    (void)h;
+    __builtin_nontemporal_store(E, &a.Eo[q]);
+    __builtin_nontemporal_store(X, &a.Fxo[q]);
+    __builtin_nontemporal_store(Y, &a.Fyo[q]);
+  }
+  __device__ __forceinline__ void finish(const GridArgs<R>&, const bool*, const size_t*) {}
+};
+
+// One tile x run of bins (logical block L of grid a); BK = 0: all bins.
+template <typename R, int BK, class Sink>
 __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigned L,
-                                             AdvShared<R>& S) {
+                                             AdvShared<R>& S, Sink& sink) {
   const int nx = a.nx, ny = a.ny, nb = a.nb;
   const size_t nc = (size_t)nx * ny;
   const int nbx = (nx + kTX - 1) / kTX, nby = (ny + kTY - 1) / kTY;
   const int bx = (int)(L % (unsigned)nbx);
   const unsigned t1 = L / (unsigned)nbx;
   const int by = (int)(t1 % (unsigned)nby);
-  const int bz = (int)(t1 / (unsigned)nby);
+  const int bz = BK > 0 ? (int)(t1 / (unsigned)nby) : 0;
   const int x0 = bx * kTX, y0 = by * kTY, k0 = bz * BK;
-  const int kend = min(k0 + BK, nb);
+  const int kend = BK > 0 ? min(k0 + BK, nb) : nb;
   const int tid = threadIdx.x;
   const R inv_c = R(1.0 / kC);
 
@@ -274,6 +291,7 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
     cy[m] = own[m] ? a.cy[gj] : R(0);
   }
   const R ctdt = a.ctdt, ctdt_c = a.ctdt_c;
+  sink.init(a, own, cidx, ccls);
 
   // staging entries of this lane (fixed for all bins): source offset within a
   // bin, or -1 for a vacuum / unused entry, and the mirror signs of f
@@ -397,19 +415,19 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
       const R src = em[m] * a.phi[(size_t)cc * nb + k];
       const R kE = acabs[m] + pda[m] * hC;
       const size_t q = koff + cidx[m];
-      __builtin_nontemporal_store((Es + ctdt * src) * frcp(R(1) + ctdt * kE), &a.Eo[q]);
       const R dF = frcp(R(1) + ctdt * aFC);
-      __builtin_nontemporal_store(Xs * dF, &a.Fxo[q]);
-      __builtin_nontemporal_store(Ys * dF, &a.Fyo[q]);
+      sink.put(a, m, k, q, hC, (Es + ctdt * src) * frcp(R(1) + ctdt * kE), Xs * dF, Ys * dF);
     }
     __syncthreads();
   }
+  sink.finish(a, own, cidx);
 }
 
 template <typename R, int BK>
 __global__ __launch_bounds__(256) void k_advect_source(GridArgs<R> a) {
   __shared__ AdvShared<R> S;
-  advect_block<R, BK>(a, xcd_logical_block(), S);
+  WriteSink<R> sink;
+  advect_block<R, BK>(a, xcd_logical_block(), S, sink);
 }
 
 // Batched, persistent advection: blocks walk the work items (grid, tile x
@@ -429,7 +447,8 @@ __global__ __launch_bounds__(256) void k_advect_batched(const GridArgs<R>* __res
       if (off[mid] <= w) lo = mid; else hi = mid;
     }
     const GridArgs<R>& a = args[((par[lo] ^ sp) & 1) * n + lo];
-    advect_block<R, BK>(a, (unsigned)(w - off[lo]), S);
+    WriteSink<R> sink;
+    advect_block<R, BK>(a, (unsigned)(w - off[lo]), S, sink);
   }
 }
 
@@ -506,6 +525,27 @@ struct FreqCell {
   }
 };
 
+// One row of the forward elimination (double).  With r1 = s_{k-1}/p_{k-1} and
+// r2 = a_{k-1} z_{k-1}:  s_k = 1 + b_k r1,  d_k = y_k + r2,  p_k = s_k + a_k,
+// z_k = d_k/p_k,  w_k = b_{k+1}/p_k.
+struct FreqRow {
+  double r1 = 0.0, r2 = 0.0;
+  double b = 0.0;                  // rate of bin k toward k-1 (zero at the lower end)
+  template <typename R>
+  __device__ __forceinline__ void eliminate(int k, double y, double a_k, double b_next,
+                                            ZW<R>* __restrict__ out) {
+    const double s = (k == 0) ? 1.0 : 1.0 + b * r1;
+    const double d = (k == 0) ? y : y + r2;
+    const double ip = 1.0 / (s + a_k);
+    const double z = d * ip;
+    __builtin_nontemporal_store((R)z, &out->z);
+    __builtin_nontemporal_store((R)(b_next * ip), &out->w);
+    r1 = s * ip;
+    r2 = a_k * z;
+    b = b_next;
+  }
+};
+
 // Forward elimination over the bins of one cell: writes z_k = d_k/p_k and
 // w_k = b_{k+1}/p_k, accumulates the force.  The state is only read here
 // and the scratch only written.  With double storage the loads of a bin are
@@ -539,8 +579,7 @@ __device__ __forceinline__ void freq_forward(const GridArgs<R>& a, const FreqCel
   T qc, Cc;
   fc.coeffs(a, 0, h0, e0, x0, y0, qc, Cc);
   force(0, h0, x0, y0);
-  double s_prev = 1.0, ip_prev = 1.0, d_prev = 0.0, a_prev = 0.0;
-  double b_k = 0.0;                // rate of bin k toward k-1 (zero at the lower end)
+  FreqRow row;
   for (int k = 0; k < nb; ++k) {
     R e2 = R(0), x2 = R(0), y2 = R(0), h2 = R(0);
     if constexpr (kAhead) {
@@ -569,18 +608,7 @@ __device__ __forceinline__ void freq_forward(const GridArgs<R>& a, const FreqCel
       qc = qn;
       Cc = Cn;
     }
-    const double y = a.dnu[k] * (double)e0;
-    const double s = (k == 0) ? 1.0 : 1.0 + b_k * s_prev * ip_prev;
-    const double d = (k == 0) ? y : y + a_prev * d_prev * ip_prev;
-    const double p = s + a_k;
-    const double ip = 1.0 / p;
-    const size_t idx = (size_t)k * nc + c;
-    ZW<R> v;
-    v.z = (R)(d * ip);
-    v.w = (R)(b_next * ip);
-    __builtin_nontemporal_store(v.z, &zw[idx].z);
-    __builtin_nontemporal_store(v.w, &zw[idx].w);
-    s_prev = s; ip_prev = ip; d_prev = d; a_prev = a_k; b_k = b_next;
+    row.eliminate<R>(k, a.dnu[k] * (double)e0, a_k, b_next, &zw[(size_t)k * nc + c]);
     e0 = e1;
     if constexpr (kAhead) { e1 = e2; x1 = x2; y1 = y2; h1 = h2; }
   }
@@ -693,6 +721,141 @@ void k_freq_batched(const GridArgs<R>* __restrict__ args,
   }
 }
 
+// ------------------------------------------------------------ fused K2+K3
+// Float storage without island cells: the frequency step runs inside the
+// advection block.  The block walks all bins of its tile; each owned cell's
+// post-source state E**, F** of bin k feeds that cell's forward elimination
+// at once (the rates of interface k-1|k need both bins, so row k-1 is
+// eliminated when bin k arrives), and after the last bin the block
+// back-substitutes its cells.  E** never goes to memory; f** = F**/E** is
+// kept in the output flux arrays until the back substitution replaces it.
+// The arithmetic is that of advect_block + freq_cell<float, float> step for
+// step, so both paths give identical bits.
+struct FusedSink {
+  FreqCell<float, float> fc[2];
+  float al[2], qp[2], Cp[2], ep[2];
+  double acF[2];
+  double f4[2][4];
+  FreqRow row[2];
+
+  __device__ __forceinline__ void init(const GridArgs<float>& a, const bool* own,
+                                       const size_t* cidx, const int* ccls) {
+    const size_t nc = (size_t)a.nx * a.ny;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const size_t c = cidx[m];
+      const int cl = ccls[m];
+      al[m] = own[m] ? a.alpha[c] : 0.0f;
+      acF[m] = own[m] ? (double)a.acF[c] : 0.0;
+      FreqCell<float, float>& f = fc[m];
+      f.gxx = own[m] ? a.grad[c] : 0.0f;
+      f.gyy = own[m] ? a.grad[nc + c] : 0.0f;
+      f.gxy = own[m] ? a.grad[2 * nc + c] : 0.0f;
+      f.gpp = own[m] ? a.grad[3 * nc + c] : 0.0f;
+      f.dd = (float)a.dD2h[cl] * al[m];
+      f.hkT = (float)a.hkT[cl];
+      f.recoil = a.recoil != 0;
+      f.doppler = a.doppler != 0 &&
+          ((f.gxx != 0.0f) || (f.gyy != 0.0f) || (f.gxy != 0.0f) || (f.gpp != 0.0f));
+      qp[m] = Cp[m] = ep[m] = 0.0f;
+      f4[m][0] = f4[m][1] = f4[m][2] = f4[m][3] = 0.0;
+      row[m] = FreqRow();
+    }
+  }
+
+  __device__ __forceinline__ void put(const GridArgs<float>& a, int m, int k, size_t q, float h,
+                                      float E, float X, float Y) {
+    float fxo, fyo;
+    reduced_flux<float>(E, X, Y, fxo, fyo);
+    __builtin_nontemporal_store(fxo, &a.Fxo[q]);
+    __builtin_nontemporal_store(fyo, &a.Fyo[q]);
+    float qk, Ck;
+    fc[m].coeffs(a, k, h, E, X, Y, qk, Ck);
+    const double dn = a.dnu[k];
+    const double aH = (double)al[m] * (double)h;
+    const double aF = aH + acF[m];
+    f4[m][0] += dn * aF * (double)X;
+    f4[m][1] += dn * aF * (double)Y;
+    f4[m][2] += dn * aH * (double)X;
+    f4[m][3] += dn * aH * (double)Y;
+    if (k > 0) {
+      float gl, gr;
+      if (qp[m] > 0.0f && qk > 0.0f) {
+        interface_rates<float>(qp[m], Cp[m], qk, Ck, gl, gr);
+      } else {
+        gl = Cp[m] < 0.0f ? -Cp[m] : 0.0f;      // K -> 0: first-order upwind
+        gr = Ck > 0.0f ? Ck : 0.0f;
+      }
+      const double ctdt = (double)a.ctdt;
+      const double a_k = ctdt * (double)gl * a.inv_dnu[k - 1];
+      const double b_next = ctdt * (double)gr * a.inv_dnu[k];
+      const size_t nc = (size_t)a.nx * a.ny;
+      row[m].eliminate<float>(k - 1, a.dnu[k - 1] * (double)ep[m], a_k, b_next, &a.zw[q - nc]);
+    }
+    qp[m] = qk;
+    Cp[m] = Ck;
+    ep[m] = E;
+  }
+
+  __device__ __forceinline__ void finish(const GridArgs<float>& a, const bool* own,
+                                         const size_t* cidx) {
+    const size_t nc = (size_t)a.nx * a.ny;
+    const int nb = a.nb;
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+      if (own[m])
+        row[m].eliminate<float>(nb - 1, a.dnu[nb - 1] * (double)ep[m], 0.0, 0.0,
+                                &a.zw[(size_t)(nb - 1) * nc + cidx[m]]);
+    double y[2] = {0.0, 0.0};
+    for (int k = nb - 1; k >= 0; --k) {
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        if (!own[m]) continue;
+        const size_t idx = (size_t)k * nc + cidx[m];
+        ZW<float> v;
+        v.z = __builtin_nontemporal_load(&a.zw[idx].z);
+        v.w = __builtin_nontemporal_load(&a.zw[idx].w);
+        y[m] = (double)v.z + (double)v.w * y[m];
+        const float En = (float)(y[m] * a.inv_dnu[k]);
+        const float fxo = __builtin_nontemporal_load(&a.Fxo[idx]);
+        const float fyo = __builtin_nontemporal_load(&a.Fyo[idx]);
+        __builtin_nontemporal_store(En, &a.Eo[idx]);
+        __builtin_nontemporal_store(fxo * En, &a.Fxo[idx]);
+        __builtin_nontemporal_store(fyo * En, &a.Fyo[idx]);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      if (!own[m]) continue;
+      const size_t c = cidx[m];
+      a.force[c] = f4[m][0];
+      a.force[nc + c] = f4[m][1];
+      a.force[2 * nc + c] = f4[m][2];
+      a.force[3 * nc + c] = f4[m][3];
+    }
+  }
+};
+
+// Batched, persistent fused step: work item = one tile (all bins) of a grid.
+// Four waves per SIMD (128 registers).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+void k_step_fused_batched(const GridArgs<float>* __restrict__ args,
+                                                            const int* __restrict__ par, int n,
+                                                            int sp, const int* __restrict__ off) {
+  __shared__ AdvShared<float> S;
+  const int total = off[n];
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (off[mid] <= w) lo = mid; else hi = mid;
+    }
+    const GridArgs<float>& a = args[((par[lo] ^ sp) & 1) * n + lo];
+    FusedSink sink;
+    advect_block<float, 0>(a, (unsigned)(w - off[lo]), S, sink);
+  }
+}
+
 // ---------------------------------------------------------------- K4
 // Block partial sums of (E1 - E0)^2 and E1^2 in FP64, fixed order.
 template <typename R>
@@ -783,12 +946,14 @@ hipError_t launch_freq(const GridArgs<R>& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+int tile_count(int nx, int ny) { return ((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY); }
 int advect_blocks(int nx, int ny, int nb, int bk) {
-  return ((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY) * ((nb + bk - 1) / bk);
+  return tile_count(nx, ny) * (bk > 0 ? (nb + bk - 1) / bk : 1);
 }
+
 int freq_blocks(int nx, int ny) { return (int)(((size_t)nx * ny + 255) / 256); }
 
-const int kBatchBK[kNumBatchVariants] = {7, 14, 28, 49};
+const int kBatchBK[kNumBatchVariants] = {7, 14, 28, 49, -1};
 
 template <typename R>
 hipError_t launch_advect_batched(int variant, const GridArgs<R>* args, const int* par, int n,
@@ -798,7 +963,14 @@ hipError_t launch_advect_batched(int variant, const GridArgs<R>* args, const int
     case 0: hipLaunchKernelGGL((k_advect_batched<R, 7>), g, b, 0, s, args, par, n, sp, off); break;
     case 1: hipLaunchKernelGGL((k_advect_batched<R, 14>), g, b, 0, s, args, par, n, sp, off); break;
     case 2: hipLaunchKernelGGL((k_advect_batched<R, 28>), g, b, 0, s, args, par, n, sp, off); break;
-    default: hipLaunchKernelGGL((k_advect_batched<R, 49>), g, b, 0, s, args, par, n, sp, off); break;
+    case 3: hipLaunchKernelGGL((k_advect_batched<R, 49>), g, b, 0, s, args, par, n, sp, off); break;
+    default:
+      if constexpr (sizeof(R) == 4)
+        hipLaunchKernelGGL(k_step_fused_batched, g, b, 0, s, (const GridArgs<float>*)args, par, n,
+                           sp, off);
+      else
+        return hipErrorInvalidValue;              // fused: float storage only
+      break;
   }
   return hipGetLastError();
 }
@@ -820,7 +992,8 @@ int batched_occupancy(int variant) {
     case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_advect_batched<R, 7>, 256, 0); break;
     case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_advect_batched<R, 14>, 256, 0); break;
     case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_advect_batched<R, 28>, 256, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_advect_batched<R, 49>, 256, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_advect_batched<R, 49>, 256, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_fused_batched, 256, 0); break;
   }
   return e == hipSuccess && nb > 0 ? nb : 1;
 }
@@ -876,6 +1049,7 @@ hipError_t launch_force_out(const double* force, size_t nc, int e2, double* fx, 
 }
 
 template hipError_t launch_step<float>(const GridArgs<float>&, hipStream_t);
+template hipError_t launch_step<double>(const GridArgs<double>&, hipStream_t);
 template hipError_t launch_advect_batched<float>(int, const GridArgs<float>*, const int*, int, int, const int*, int, hipStream_t);
 template hipError_t launch_advect_batched<double>(int, const GridArgs<double>*, const int*, int, int, const int*, int, hipStream_t);
 template hipError_t launch_freq_batched<float>(const GridArgs<float>*, const int*, int, int, const int*, int, int, hipStream_t);
@@ -888,7 +1062,6 @@ template hipError_t launch_advect<float>(const GridArgs<float>&, hipStream_t);
 template hipError_t launch_advect<double>(const GridArgs<double>&, hipStream_t);
 template hipError_t launch_freq<float>(const GridArgs<float>&, hipStream_t);
 template hipError_t launch_freq<double>(const GridArgs<double>&, hipStream_t);
-template hipError_t launch_step<double>(const GridArgs<double>&, hipStream_t);
 template hipError_t launch_residual<float>(const float*, const float*, size_t, double*, int, double*, hipStream_t);
 template hipError_t launch_residual<double>(const double*, const double*, size_t, double*, int, double*, hipStream_t);
 template hipError_t launch_scale_copy<float, double>(const float*, double*, size_t, int, hipStream_t);

@@ -334,11 +334,15 @@ class M1Batch:
         return self
 
     def info(self):
-        """(bins per advection block chosen, or 0 while tuning; ms per variant)."""
+        """(tile variant chosen: 7, 14, 28, 49 bins per block or -1 fused; 0 while
+        tuning; ms per step of each of the five variants)."""
         bk = ctypes.c_int32()
-        ms = (ctypes.c_double * 4)()
-        check(lib().m1_batch_info(self.h, ctypes.byref(bk), ms, 4))
+        ms = (ctypes.c_double * 5)()
+        check(lib().m1_batch_info(self.h, ctypes.byref(bk), ms, 5))
         return bk.value, list(ms)
+
+    def set_tile(self, bins_per_block):
+        check(lib().m1_batch_set_tile(self.h, int(bins_per_block)))
 
     def free(self):
         if getattr(self, "h", None) is not None and self.h.value:

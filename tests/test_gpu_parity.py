@@ -142,22 +142,56 @@ def _mixed_problems():
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_batched_equals_alone_bitwise(prec):
-    """One batch of differently sized grids: the tuning steps (every tile
+    """One batch of differently sized grids: the tuning steps (three per tile
     variant), then graph replays of step pairs and a single odd step."""
     from paper_2606_02711_amd import m1
     ps = _mixed_problems()
-    steps = 4 * 3 + 7
+    steps = 5 * 3 + 7
     ref = _alone(ps, steps, prec)
     print(f"[gpu] batched {prec}", flush=True)
     import torch
     s = torch.cuda.Stream()              # a non-null stream: step pairs replay a graph
     gs = [m1.M1Grid(p, prec=prec, stream=s) for p in ps]
     b = m1.M1Batch(gs, use_graph=True)
-    b.step(12)
+    b.step(15)
     bk, ms = b.info()
-    assert bk in (7, 14, 28, 49) and all(t > 0 for t in ms)
+    assert bk in (7, 14, 28, 49, -1) and all(t > 0 for t in ms)
+    assert (ms[4] == float("inf")) == (prec == "fp64")      # fused: FP32 only
     b.step(7)
     _assert_same(gs, ref)
+
+
+def test_fused_kernel_equals_two_kernel_path_bitwise():
+    """The fused kernel (frequency step inside the advection blocks) against
+    the advection + frequency-step kernels, through batches with a fixed tile
+    variant: identical bits after 11 steps, graph replays included."""
+    from paper_2606_02711_amd import m1
+    import torch
+    ps = _mixed_problems()
+    out = {}
+    for bk in (-1, 28, 7):
+        print(f"[gpu] batch with tile variant {bk}", flush=True)
+        s = torch.cuda.Stream()
+        gs = [m1.M1Grid(p, prec="fp32", stream=s) for p in ps]
+        b = m1.M1Batch(gs, use_graph=True)
+        b.set_tile(bk)
+        b.step(11)
+        b.free()
+        out[bk] = [[t.cpu().numpy() for t in g.state()] + [g.force().cpu().numpy()] for g in gs]
+    for bk in (28, 7):
+        for ga, gb in zip(out[-1], out[bk]):
+            for x, y in zip(ga, gb):
+                assert np.array_equal(x, y), bk
+
+
+def test_fused_variant_refused_with_island_cells():
+    from paper_2606_02711_amd import m1
+    p = _mixed_problems()[0]
+    g = m1.M1Grid(p, prec="fp32", fp64_tau=30.0)
+    b = m1.M1Batch([g], use_graph=False)
+    with pytest.raises(m1.M1Error):
+        b.set_tile(-1)
+    b.free()
 
 
 def test_batched_with_island_cells_equals_alone():
