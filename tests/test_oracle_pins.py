@@ -438,3 +438,270 @@ def test_linearity_in_source_is_bitwise():
     assert np.array_equal(b.E, a.E * 2.0 ** 40)
     assert np.array_equal(b.Fx, a.Fx * 2.0 ** 40)
     assert np.array_equal(b.force, a.force * 2.0 ** 40)
+
+
+def test_thin_point_source_falls_off_as_one_over_r():
+    """Optically thin 2D (slab) point source: in steady free streaming the
+    energy crossing a circle of radius r is the luminosity per unit depth, so
+    2 pi r c |F| = L (the 1/r fall-off of a line source), with f -> 1.  M1 on
+    a Cartesian grid carries direction-dependent ray artefacts of tens of
+    percent cell by cell, so the check is on annulus means."""
+    n, Lb = 64, 1.0e16
+    p = inputs.base_problem("cart", n, n, -Lb / 2, Lb / 2, -Lb / 2, Lb / 2, ("vacuum",) * 4,
+                            c_tilde_frac=1.0)
+    p["half_width"] = 10.0
+    f = inputs.uniform_fields(p, 0.0, 1.0e4)
+    dx = Lb / n
+    f["emis"] = np.zeros((n, n))
+    f["emis"][n // 2, n // 2] = 1.0 / (dx * dx)          # 1 erg/s per cm of depth
+    p["fields"] = f
+    o = M.Oracle(p)
+    o.step(int(1.6 * (Lb / 2) / (inputs.C_LIGHT * o.dt)))
+    dnu = o.s.grid["dnu"]
+    E = np.tensordot(dnu, o.E, axes=1)
+    Fm = np.hypot(np.tensordot(dnu, o.Fx, axes=1), np.tensordot(dnu, o.Fy, axes=1))
+    xc = -Lb / 2 + (np.arange(n) + 0.5) * dx
+    X, Y = np.meshgrid(xc, xc)
+    r = np.hypot(X - xc[n // 2], Y - xc[n // 2])
+    means, radii = [], []
+    for lo, hi in ((10, 14), (14, 18), (18, 22), (22, 26), (26, 30)):
+        m = (r >= lo * dx) & (r < hi * dx)
+        q = 2.0 * np.pi * r[m] * inputs.C_LIGHT * Fm[m]
+        assert q.mean() == pytest.approx(1.0, abs=0.01), (lo, q.mean())
+        assert (Fm[m] / E[m]).min() > 0.95
+        means.append(Fm[m].mean())
+        radii.append(r[m].mean())
+    slope = np.polyfit(np.log(radii), np.log(means), 1)[0]
+    assert slope == pytest.approx(-1.0, abs=0.02)
+
+
+def test_frequency_stage_matches_dense_solve_on_8x8():
+    """Brute force on an 8x8 grid: the oracle's frequency stage (tridiagonal
+    system assembled per cell, Thomas sweep in long double) against the same
+    BDF1 system built here from the definitions K_k = dnu_D^2 alpha <H>_k / 2,
+    C_k = K_k (h/kT - 2/nu_k) (recoil; no velocity) and solved by a dense LU
+    solve, with H rescaled by J_new/J**."""
+    p = inputs.random_small("cart", 8, 8, 77, with_velocity=False, half_width=300.0,
+                            log_nHI=(-3.0, 0.0))
+    o = M.Oracle(p)
+    s = o.s
+    rng = np.random.default_rng(5)
+    shape = (s.nb, s.ny, s.nx)
+    E0 = rng.uniform(0.5, 1.0, shape) * 1e-20
+    ang = rng.uniform(0, 2 * np.pi, shape)
+    fr = rng.uniform(0.0, 0.9, shape)
+    o.set_state(E0, E0 * fr * np.cos(ang), E0 * fr * np.sin(ang))
+    o.step(1)
+    Ess, Xss, Yss = o.post_source_state()
+    dnu = s.grid["dnu"]
+    ct = p["c_tilde"] * o.dt
+    worst = 0.0
+    for c in range(s.nx * s.ny):
+        j, i = divmod(c, s.nx)
+        h = s.hbar[s.cls[c]]
+        K = 0.5 * s.dnuD[c] ** 2 * s.alpha[c] * h
+        C = K * (s.hkT[c] - 2.0 / s.grid["nu_c"])
+        A = np.eye(s.nb)
+        for k in range(s.nb - 1):
+            gl, gr = M.interface_rates(K[k], C[k], 0.5 * dnu[k], K[k + 1], C[k + 1],
+                                       0.5 * dnu[k + 1])
+            # flux through k+1/2: gr J_{k+1} - gl J_k, leaving bin k and entering k+1
+            A[k, k] += ct * gl / dnu[k]
+            A[k, k + 1] -= ct * gr / dnu[k]
+            A[k + 1, k + 1] += ct * gr / dnu[k + 1]
+            A[k + 1, k] -= ct * gl / dnu[k + 1]
+        Jn = np.linalg.solve(A, Ess[:, j, i])
+        worst = max(worst, np.max(np.abs(Jn - o.E[:, j, i]) / np.abs(Jn).max()))
+        ratio = np.where(Ess[:, j, i] > 0, Jn / np.where(Ess[:, j, i] > 0, Ess[:, j, i], 1), 0)
+        assert np.allclose(o.Fx[:, j, i], Xss[:, j, i] * ratio, rtol=1e-10, atol=0)
+        # photons are conserved by the frequency stage
+        assert np.dot(dnu, Jn) == pytest.approx(np.dot(dnu, Ess[:, j, i]), rel=1e-12)
+    assert worst < 1e-11, worst
+
+
+def _brute_force_transport(p, o, E, Fx, Fy):
+    """E**, F** of one step written out cell by cell from Section 2.1 (velocity
+    zero): ghost cells, MinMod slopes on centroid distances, Levermore closure
+    in its chi form, GLF flux blended with the diffusion flux by eps, update,
+    cylindrical hoop term, causality, implicit source."""
+    s = o.s
+    nx, ny, nb = s.nx, s.ny, s.nb
+    cyl = p["geom"] == "cyl"
+    xe = p["x0"] + (p["x1"] - p["x0"]) * np.arange(nx + 1) / nx
+    ye = p["y0"] + (p["y1"] - p["y0"]) * np.arange(ny + 1) / ny
+    if cyl:
+        xb = 2.0 / 3.0 * (xe[1:] ** 3 - xe[:-1] ** 3) / (xe[1:] ** 2 - xe[:-1] ** 2)
+    else:
+        xb = 0.5 * (xe[1:] + xe[:-1])
+    yb = 0.5 * (ye[1:] + ye[:-1])
+    ct = p["c_tilde"] * o.dt
+    bc = p["bc"]
+
+    def chi_D(e, fx, fy):
+        if e <= 0:
+            return 1 / 3, 1 / 3, 0.0, 1 / 3
+        fxr, fyr = fx, fy
+        f = np.hypot(fxr, fyr)
+        chi = (3 + 4 * f * f) / (5 + 2 * np.sqrt(4 - 3 * f * f))
+        if f == 0:
+            return 1 / 3, 1 / 3, 0.0, 1 / 3
+        nxv, nyv = fxr / f, fyr / f
+        a, b = (1 - chi) / 2, (3 * chi - 1) / 2
+        return a + b * nxv * nxv, a + b * nyv * nyv, b * nxv * nyv, a
+
+    def minmod(a, b):
+        return a if (a * b > 0 and abs(a) < abs(b)) else (b if a * b > 0 else 0.0)
+
+    def cell(k, i, j):
+        """(E, fx, fy, alpha_F, centroid) of cell (i, j) with ghosts."""
+        if i < 0 or i >= nx:
+            side = 0 if i < 0 else 1
+            if bc[side] == "vacuum":
+                return 0.0, 0.0, 0.0, 0.0, None
+            ii = -1 - i if i < 0 else 2 * nx - 1 - i
+            e, fx, fy, aF, _ = cell(k, ii, j)
+            return e, -fx, fy, aF, None
+        if j < 0 or j >= ny:
+            side = 2 if j < 0 else 3
+            if bc[side] == "vacuum":
+                return 0.0, 0.0, 0.0, 0.0, None
+            jj = -1 - j if j < 0 else 2 * ny - 1 - j
+            e, fx, fy, aF, _ = cell(k, i, jj)
+            return e, fx, -fy, aF, None
+        c = j * nx + i
+        e = E[k, j, i]
+        fx = Fx[k, j, i] / e if e > 0 else 0.0
+        fy = Fy[k, j, i] / e if e > 0 else 0.0
+        aF = s.alpha[c] * s.hbar[s.cls[c], k] + s.acF[c]
+        return e, fx, fy, aF, None
+
+    def centroid(d, a, b):
+        if d == 0 and cyl:
+            return 2.0 / 3.0 * (b ** 3 - a ** 3) / (b ** 2 - a ** 2)
+        return 0.5 * (a + b)
+
+    def pos(d, i, j, g):
+        """Centroid along d of cell index i (d = 0) or j (d = 1), ghosts too:
+        mirror image at a reflecting edge, the continued cell at a vacuum one."""
+        n, e_, b_, q = (nx, xe, xb, i) if d == 0 else (ny, ye, yb, j)
+        if 0 <= q < n:
+            return b_[q]
+        lo = q < 0
+        side = (0 if lo else 1) + 2 * d
+        if bc[side] == "reflect":
+            m = -1 - q if lo else 2 * n - 1 - q
+            return 2 * e_[0] - b_[m] if lo else 2 * e_[n] - b_[m]
+        w = e_[1] - e_[0] if lo else e_[n] - e_[n - 1]
+        a = e_[0] + q * w if lo else e_[n] + (q - n) * w
+        return centroid(d, a, a + w)
+
+    def face_flux(k, d, i, j):
+        """Flux of (E, F_x, F_y) through the face between cell (i, j) and its
+        neighbour in direction d (0: x, 1: y) on the high side."""
+        step = (1, 0) if d == 0 else (0, 1)
+        cs = [(i + t * step[0], j + t * step[1]) for t in (-1, 0, 1, 2)]
+        vals = []
+        for (a_, b_) in cs:
+            e, fx, fy, aF, g = cell(k, a_, b_)
+            vals.append((e, fx, fy, aF, pos(d, a_, b_, g)))
+        xf = xe[i + 1] if d == 0 else ye[j + 1]
+        (eLL, xLL, yLL, _, cLL), (eL, xL, yL, aL, cL), (eR, xR, yR, aR, cR), (eRR, xRR, yRR, _, cRR) = vals
+        recon = []
+        for q in range(3):
+            qLL, qL, qR, qRR = [v[q] for v in vals]
+            sL = minmod((qL - qLL) / (cL - cLL), (qR - qL) / (cR - cL))
+            sR = minmod((qR - qL) / (cR - cL), (qRR - qR) / (cRR - cR))
+            recon.append((qL + sL * (xf - cL), qR + sR * (xf - cR)))
+        EL, ER = recon[0]
+        fxL, fxR = recon[1]
+        fyL, fyR = recon[2]
+        for side in (0, 1):
+            fx_, fy_ = (fxL, fyL) if side == 0 else (fxR, fyR)
+            nrm = np.hypot(fx_, fy_)
+            if nrm > 1:
+                fx_, fy_ = fx_ / nrm, fy_ / nrm
+            if side == 0:
+                fxL, fyL = fx_, fy_
+            else:
+                fxR, fyR = fx_, fy_
+        DL = chi_D(1.0, fxL, fyL)
+        DR = chi_D(1.0, fxR, fyR)
+        tau = aL * (xf - cL) + aR * (cR - xf)
+        eps = (0.2 + tau) / (0.2 + tau + tau * tau)
+        one_m_eps = tau * tau / (0.2 + tau + tau * tau)       # 1 - eps without cancellation
+        FL = (fxL * EL, fyL * EL)
+        FR = (fxR * ER, fyR * ER)
+        fe = eps * (0.5 * (FL[d] + FR[d]) - 0.5 * (ER - EL))
+        if tau > 0:
+            fe -= one_m_eps * (eR - eL) / (3 * tau)
+        # row d of D E
+        PL = (DL[0] * EL, DL[2] * EL) if d == 0 else (DL[2] * EL, DL[1] * EL)
+        PR = (DR[0] * ER, DR[2] * ER) if d == 0 else (DR[2] * ER, DR[1] * ER)
+        fxx = 0.5 * (PL[0] + PR[0]) - eps * 0.5 * (FR[0] - FL[0])
+        fyy = 0.5 * (PL[1] + PR[1]) - eps * 0.5 * (FR[1] - FL[1])
+        return fe, fxx, fyy
+
+    Es = np.zeros_like(E)
+    Xs = np.zeros_like(E)
+    Ys = np.zeros_like(E)
+    for k in range(nb):
+        for j in range(ny):
+            for i in range(nx):
+                c = j * nx + i
+                dz = ye[j + 1] - ye[j]
+                if cyl:
+                    dV = np.pi * (xe[i + 1] ** 2 - xe[i] ** 2) * dz
+                    Axm, Axp = 2 * np.pi * xe[i] * dz, 2 * np.pi * xe[i + 1] * dz
+                    Ay = np.pi * (xe[i + 1] ** 2 - xe[i] ** 2)
+                else:
+                    dV = (xe[i + 1] - xe[i]) * dz
+                    Axm = Axp = dz
+                    Ay = xe[i + 1] - xe[i]
+                fw = face_flux(k, 0, i - 1, j)
+                fe_ = face_flux(k, 0, i, j)
+                fs = face_flux(k, 1, i, j - 1)
+                fn = face_flux(k, 1, i, j)
+                e, fx, fy, aF, _ = cell(k, i, j)
+                upd = [ct / dV * (Axp * fe_[q] - Axm * fw[q] + Ay * (fn[q] - fs[q])) for q in range(3)]
+                e1 = e - upd[0]
+                x1 = fx * e - upd[1]
+                y1 = fy * e - upd[2]
+                if cyl:
+                    Dpp = chi_D(1.0, fx, fy)[3]
+                    x1 += ct * Dpp * e * (Axp - Axm) / dV
+                if e1 <= 0:
+                    e1 = x1 = y1 = 0.0
+                else:
+                    nF = np.hypot(x1, y1)
+                    if nF > e1:
+                        x1, y1 = x1 * e1 / nF, y1 * e1 / nF
+                h = s.hbar[s.cls[c], k]
+                aH = s.alpha[c] * h
+                kE = s.acabs[c] + s.pd[c] * aH
+                src = s.emis[c] * s.phi[s.cls[c], k] / inputs.C_LIGHT
+                Es[k, j, i] = (e1 + ct * src) / (1 + ct * kE)
+                Xs[k, j, i] = x1 / (1 + ct * (aH + s.acF[c]))
+                Ys[k, j, i] = y1 / (1 + ct * (aH + s.acF[c]))
+    return Es, Xs, Ys
+
+
+@pytest.mark.parametrize("geom,bc", [("cart", ("vacuum",) * 4),
+                                     ("cyl", ("reflect", "vacuum", "reflect", "vacuum")),
+                                     ("cart", ("reflect", "vacuum", "vacuum", "reflect"))])
+def test_transport_stage_matches_brute_force_on_8x8(geom, bc):
+    p = inputs.random_small(geom, 8, 8, 31, with_velocity=False, half_width=30.0,
+                            log_nHI=(-4.0, -1.0), bc=bc)
+    o = M.Oracle(p)
+    s = o.s
+    rng = np.random.default_rng(9)
+    shape = (s.nb, s.ny, s.nx)
+    E0 = rng.uniform(0.1, 1.0, shape)
+    ang = rng.uniform(0, 2 * np.pi, shape)
+    fr = rng.uniform(0.0, 0.99, shape)
+    X0, Y0 = E0 * fr * np.cos(ang), E0 * fr * np.sin(ang)
+    o.set_state(E0, X0, Y0)
+    o.step(1)
+    Ess, Xss, Yss = o.post_source_state()
+    Eb, Xb, Yb = _brute_force_transport(p, o, E0, X0, Y0)
+    for a, b in ((Ess, Eb), (Xss, Xb), (Yss, Yb)):
+        assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b)), np.max(np.abs(a - b))
