@@ -29,9 +29,11 @@ struct GridArgs {
   int islands;            // FP32 storage with a finite fp64_tau: island cells may exist
   R ctdt;                 // c_tilde * dt
   R ctdt_c;               // c_tilde * dt / c (work term)
-  // ping-pong state: in (E, Fx, Fy) -> out
-  const R *E, *Fx, *Fy;
-  R *Eo, *Fxo, *Fyo;
+  // ping-pong state: in -> out.  The state of a cell and bin is E and the
+  // reduced flux f = F/E (0 where E = 0): the frequency step changes E only,
+  // since its rescale F -> F E^{n+1}/E** leaves F/E as it is.
+  const R *E, *fx, *fy;
+  R *Eo, *fxo, *fyo;
   // per cell
   const int32_t *cls;
   const uint8_t *island;
@@ -117,10 +119,9 @@ __device__ __forceinline__ void reduced_flux(R E, R Fx, R Fy, R& fx, R& fy) {
   }
 }
 
+// Closure of a reduced flux, |f| > 1 scaled back to 1 first.
 template <typename R>
-__device__ __forceinline__ Eddington<R> closure_state(R E, R Fx, R Fy) {
-  R fx, fy;
-  reduced_flux(E, Fx, Fy, fx, fy);
+__device__ __forceinline__ Eddington<R> closure_reduced(R fx, R fy) {
   const R n2 = fx * fx + fy * fy;
   const R sc = n2 > R(1) ? frsq(n2) : R(1);
   return closure_f(fx * sc, fy * sc);

@@ -207,11 +207,11 @@ void fill_args(m1_handle* h, GridArgs<R>* a) {
     g.ctdt_c = (R)(c.c_tilde * h->dt / kC);
     int in = dir, out = dir ^ 1;
     g.E = (const R*)(w + L.state[in][0]);
-    g.Fx = (const R*)(w + L.state[in][1]);
-    g.Fy = (const R*)(w + L.state[in][2]);
+    g.fx = (const R*)(w + L.state[in][1]);
+    g.fy = (const R*)(w + L.state[in][2]);
     g.Eo = (R*)(w + L.state[out][0]);
-    g.Fxo = (R*)(w + L.state[out][1]);
-    g.Fyo = (R*)(w + L.state[out][2]);
+    g.fxo = (R*)(w + L.state[out][1]);
+    g.fyo = (R*)(w + L.state[out][2]);
     g.cls = (const int32_t*)(w + L.cls);
     g.island = (const uint8_t*)(w + L.island);
     g.alpha = (const R*)(w + L.alpha);
@@ -1007,19 +1007,32 @@ int32_t m1_solve_steady(m1_handle* h, double rel_tol, int64_t max_steps, int32_t
   return M1_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// Physical state of the window [i0, i1) x [j0, j1) of every bin.
+int state_out(m1_handle* h, int i0, int i1, int j0, int j1, double* d_E, double* d_Fx,
+              double* d_Fy) {
+  const char* E = h->ws + h->L.state[h->cur][0];
+  const char* fx = h->ws + h->L.state[h->cur][1];
+  const char* fy = h->ws + h->L.state[h->cur][2];
+  hipError_t e = h->cfg.prec == M1_FP32
+      ? launch_state_out<float>((const float*)E, (const float*)fx, (const float*)fy, h->cfg.nx,
+                                h->cfg.ny, h->nb, i0, j0, i1 - i0, j1 - j0, -h->e2, d_E, d_Fx,
+                                d_Fy, h->stream)
+      : launch_state_out<double>((const double*)E, (const double*)fx, (const double*)fy,
+                                 h->cfg.nx, h->cfg.ny, h->nb, i0, j0, i1 - i0, j1 - j0, -h->e2,
+                                 d_E, d_Fx, d_Fy, h->stream);
+  if (e != hipSuccess) return fail(M1_EDEVICE, "copy launch: %s", hipGetErrorString(e));
+  return m1_sync(h);
+}
+}  // namespace
+
+extern "C" {
+
 int32_t m1_get_state(m1_handle* h, double* d_E, double* d_Fx, double* d_Fy) {
   if (!h) return fail(M1_EINVAL, "handle is NULL");
-  size_t n = (size_t)h->nb * h->nc;
-  double* dst[3] = {d_E, d_Fx, d_Fy};
-  for (int q = 0; q < 3; ++q) {
-    if (!dst[q]) continue;
-    const char* src = h->ws + h->L.state[h->cur][q];
-    hipError_t e = h->cfg.prec == M1_FP32
-        ? launch_scale_copy<float, double>((const float*)src, dst[q], n, -h->e2, h->stream)
-        : launch_scale_copy<double, double>((const double*)src, dst[q], n, -h->e2, h->stream);
-    if (e != hipSuccess) return fail(M1_EDEVICE, "copy launch: %s", hipGetErrorString(e));
-  }
-  return m1_sync(h);
+  return state_out(h, 0, h->cfg.nx, 0, h->cfg.ny, d_E, d_Fx, d_Fy);
 }
 
 int32_t m1_get_state_region(m1_handle* h, int32_t i0, int32_t i1, int32_t j0, int32_t j1,
@@ -1028,31 +1041,21 @@ int32_t m1_get_state_region(m1_handle* h, int32_t i0, int32_t i1, int32_t j0, in
   if (i0 < 0 || j0 < 0 || i1 > h->cfg.nx || j1 > h->cfg.ny || i0 >= i1 || j0 >= j1)
     return fail(M1_EINVAL, "region [%d,%d) x [%d,%d) outside the %d x %d grid or empty", i0, i1,
                 j0, j1, h->cfg.nx, h->cfg.ny);
-  double* dst[3] = {d_E, d_Fx, d_Fy};
-  for (int q = 0; q < 3; ++q) {
-    if (!dst[q]) continue;
-    const char* src = h->ws + h->L.state[h->cur][q];
-    hipError_t e = h->cfg.prec == M1_FP32
-        ? launch_region_copy<float>((const float*)src, dst[q], h->cfg.nx, h->cfg.ny, h->nb, i0, j0,
-                                    i1 - i0, j1 - j0, -h->e2, h->stream)
-        : launch_region_copy<double>((const double*)src, dst[q], h->cfg.nx, h->cfg.ny, h->nb, i0,
-                                     j0, i1 - i0, j1 - j0, -h->e2, h->stream);
-    if (e != hipSuccess) return fail(M1_EDEVICE, "copy launch: %s", hipGetErrorString(e));
-  }
-  return m1_sync(h);
+  return state_out(h, i0, i1, j0, j1, d_E, d_Fx, d_Fy);
 }
 
 int32_t m1_set_state(m1_handle* h, const double* d_E, const double* d_Fx, const double* d_Fy) {
   if (!h || !d_E || !d_Fx || !d_Fy) return fail(M1_EINVAL, "bad arguments");
   size_t n = (size_t)h->nb * h->nc;
-  const double* src[3] = {d_E, d_Fx, d_Fy};
-  for (int q = 0; q < 3; ++q) {
-    char* dst = h->ws + h->L.state[h->cur][q];
-    hipError_t e = h->cfg.prec == M1_FP32
-        ? launch_scale_copy<double, float>(src[q], (float*)dst, n, h->e2, h->stream)
-        : launch_scale_copy<double, double>(src[q], (double*)dst, n, h->e2, h->stream);
-    if (e != hipSuccess) return fail(M1_EDEVICE, "copy launch: %s", hipGetErrorString(e));
-  }
+  char* E = h->ws + h->L.state[h->cur][0];
+  char* fx = h->ws + h->L.state[h->cur][1];
+  char* fy = h->ws + h->L.state[h->cur][2];
+  hipError_t e = h->cfg.prec == M1_FP32
+      ? launch_state_in<float>(d_E, d_Fx, d_Fy, n, h->e2, (float*)E, (float*)fx, (float*)fy,
+                               h->stream)
+      : launch_state_in<double>(d_E, d_Fx, d_Fy, n, h->e2, (double*)E, (double*)fx, (double*)fy,
+                                h->stream);
+  if (e != hipSuccess) return fail(M1_EDEVICE, "copy launch: %s", hipGetErrorString(e));
   return M1_OK;
 }
 

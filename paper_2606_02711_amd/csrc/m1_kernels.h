@@ -40,12 +40,15 @@ int freq_batched_occupancy();
 template <typename R>
 hipError_t launch_residual(const R* E0, const R* E1, size_t n, double* partial, int nblk,
                            double* out, hipStream_t s);
-// dst = src * 2^e2 with a type conversion (state <-> FP64 physical units)
-template <typename S, typename D>
-hipError_t launch_scale_copy(const S* src, D* dst, size_t n, int e2, hipStream_t s);
+// Physical FP64 state (E, F) of a window of every bin from the internal (E, f)
+// state, and the internal state from a physical one.
 template <typename S>
-hipError_t launch_region_copy(const S* src, double* dst, int nx, int ny, int nb, int i0, int j0,
-                              int w, int h, int e2, hipStream_t s);
+hipError_t launch_state_out(const S* E, const S* fx, const S* fy, int nx, int ny, int nb, int i0,
+                            int j0, int w, int h, int e2, double* dE, double* dFx, double* dFy,
+                            hipStream_t s);
+template <typename D>
+hipError_t launch_state_in(const double* sE, const double* sFx, const double* sFy, size_t n,
+                           int e2, D* E, D* fx, D* fy, hipStream_t s);
 hipError_t launch_force_out(const double* force, size_t nc, int e2, double* fx, double* fy,
                             double* gx, double* gy, hipStream_t s);
 

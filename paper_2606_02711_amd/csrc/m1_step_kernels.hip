@@ -9,66 +9,13 @@
 //   freq_step     : Section 2.3 force density and Appendix A frequency step
 //                   for all bins of one cell per lane: exponential-scheme
 //                   interface rates, subtraction-free elimination of the
-//                   tridiagonal system in photon-number variables, H rescale.
+//                   tridiagonal system in photon-number variables.  The H
+//                   rescale F -> F E^{n+1}/E** keeps f = F/E, which is what
+//                   the state stores, so only E is rewritten.
 //   residual      : deterministic FP64 norms ||E^{n+1} - E^n||, ||E^{n+1}||.
 #include "m1_kernels.h"
 
 namespace m1 {
-
-// ----------------------------------------------------------- state loading
-// Value of (E, f_x, f_y) of cell (ii, jj) of bin offset koff, with ghost
-// cells: vacuum -> E = f = 0; reflecting -> mirror image with the normal
-// component of f negated.  At most one of ii, jj is out of range.
-template <typename R>
-__device__ __forceinline__ void load_ef(const GridArgs<R>& a, size_t koff, int ii, int jj,
-                                        R& e, R& fx, R& fy) {
-  int si = ii, sj = jj;
-  R sx = R(1), sy = R(1);
-  if (ii < 0 || ii >= a.nx) {
-    int side = ii < 0 ? 0 : 1;
-    if (a.bc[side] != kReflect) { e = fx = fy = R(0); return; }
-    si = ii < 0 ? -1 - ii : 2 * a.nx - 1 - ii;
-    sx = R(-1);
-  } else if (jj < 0 || jj >= a.ny) {
-    int side = jj < 0 ? 2 : 3;
-    if (a.bc[side] != kReflect) { e = fx = fy = R(0); return; }
-    sj = jj < 0 ? -1 - jj : 2 * a.ny - 1 - jj;
-    sy = R(-1);
-  }
-  size_t q = koff + (size_t)sj * a.nx + si;
-  e = a.E[q];
-  reduced_flux(e, a.Fx[q], a.Fy[q], fx, fy);
-  fx *= sx;
-  fy *= sy;
-}
-
-// Static opacity data of a neighbour (mirror cell at reflecting boundaries;
-// alpha_F = 0 in vacuum ghosts).
-template <typename R>
-struct NbrOpacity {
-  int cls;
-  R alpha, acF;
-};
-
-template <typename R>
-__device__ __forceinline__ NbrOpacity<R> nbr_opacity(const GridArgs<R>& a, int ii, int jj) {
-  NbrOpacity<R> o;
-  int si = ii, sj = jj;
-  if (ii < 0 || ii >= a.nx) {
-    int side = ii < 0 ? 0 : 1;
-    if (a.bc[side] != kReflect) { o.cls = 0; o.alpha = R(0); o.acF = R(0); return o; }
-    si = ii < 0 ? -1 - ii : 2 * a.nx - 1 - ii;
-  } else if (jj < 0 || jj >= a.ny) {
-    int side = jj < 0 ? 2 : 3;
-    if (a.bc[side] != kReflect) { o.cls = 0; o.alpha = R(0); o.acF = R(0); return o; }
-    sj = jj < 0 ? -1 - jj : 2 * a.ny - 1 - jj;
-  }
-  size_t c = (size_t)sj * a.nx + si;
-  o.cls = a.cls[c];
-  o.alpha = a.alpha[c];
-  o.acF = a.acF[c];
-  return o;
-}
 
 template <typename R>
 struct Flux3 {
@@ -124,10 +71,11 @@ __device__ __forceinline__ Flux3<R> face_flux(R eLL, R xLL, R yLL, R eL, R xL, R
 // ---------------------------------------------------------------- K2
 // LDS-tiled advection + emission/absorption.  A block owns a tile of
 // kTX x kTY cells and walks a run of bins.  Per bin: (1) the tile plus two
-// ghost layers of (E, f) and the alpha_F ring are staged in LDS (f = F/E is
-// formed once per cell), (2) every x- and y-face flux of the tile is computed
-// exactly once into LDS, (3) each lane updates its cells (two per lane),
-// applies the causality clamp and the implicit source, and writes E**, F**.
+// ghost layers of the state (E, f) and the alpha_F ring are staged in LDS,
+// (2) every x- and y-face flux of the tile is computed exactly once into LDS,
+// (3) each lane updates its cells (two per lane), applies the causality clamp
+// and the implicit source, and hands E**, F** to its sink (which stores E**
+// and f** = F**/E**, or runs the frequency step on them).
 // Blocks are mapped so that the tiles one XCD runs are contiguous in space
 // (halo rows shared between neighbouring tiles then hit the same L2).
 // 32 x 16 cells: fewer halo cells and faces per cell than 64 x 8 (1.41 vs
@@ -194,9 +142,11 @@ struct WriteSink {
   __device__ __forceinline__ void put(const GridArgs<R>& a, int, int, size_t q, R h, R E, R X,
                                       R Y) {
     (void)h;
+    R fxo, fyo;
+    reduced_flux<R>(E, X, Y, fxo, fyo);
     __builtin_nontemporal_store(E, &a.Eo[q]);
-    __builtin_nontemporal_store(X, &a.Fxo[q]);
-    __builtin_nontemporal_store(Y, &a.Fyo[q]);
+    __builtin_nontemporal_store(fxo, &a.fxo[q]);
+    __builtin_nontemporal_store(fyo, &a.fyo[q]);
   }
   __device__ __forceinline__ void finish(const GridArgs<R>&, const bool*, const size_t*) {}
 };
@@ -319,8 +269,8 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
     const size_t koff = (size_t)k * nc;
     const R* hb = a.hbar + k;
     const R* Ek = a.E + koff;
-    const R* Xk = a.Fx + koff;
-    const R* Yk = a.Fy + koff;
+    const R* Xk = a.fx + koff;
+    const R* Yk = a.fy + koff;
     // (1) stage E and f of the padded tile, and alpha_F of the ring
     if constexpr (kHoist) {
 #pragma unroll
@@ -330,9 +280,8 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
         R ev = R(0), fxv = R(0), fyv = R(0);
         if (soff[m] >= 0) {
           ev = Ek[soff[m]];
-          reduced_flux(ev, Xk[soff[m]], Yk[soff[m]], fxv, fyv);
-          fxv *= ssx[m];
-          fyv *= ssy[m];
+          fxv = Xk[soff[m]] * ssx[m];
+          fyv = Yk[soff[m]] * ssy[m];
         }
         (&S.E[0][0])[e] = ev; (&S.fx[0][0])[e] = fxv; (&S.fy[0][0])[e] = fyv;
       }
@@ -346,9 +295,8 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
         if (ghost_source(x0 + pi - 2, y0 + pj - 2, nx, ny, a.bc, 2, si, sj, sgx, sgy, vac) && !vac) {
           const int q = sj * nx + si;
           ev = Ek[q];
-          reduced_flux(ev, Xk[q], Yk[q], fxv, fyv);
-          fxv *= R(sgx);
-          fyv *= R(sgy);
+          fxv = Xk[q] * R(sgx);
+          fyv = Yk[q] * R(sgy);
         }
         S.E[pj][pi] = ev; S.fx[pj][pi] = fxv; S.fy[pj][pi] = fyv;
       }
@@ -505,18 +453,18 @@ __device__ __forceinline__ void interface_rates(T ql, T Cl, T qr, T Cr, T& gl, T
 
 // Coefficients of bin k of one cell (Appendix A): q = (dnu_k/2)/K_k, with
 // K_k = (dnu_D^2/2) alpha <H>_k (q = 0 flags a bin without line opacity), and
-// C_k = K_k R_k + (nu_k/c) D_k : grad u, from the post-source state (e, X, Y).
+// C_k = K_k R_k + (nu_k/c) D_k : grad u, D from the post-source reduced flux.
 template <typename R, typename T>
 struct FreqCell {
   T dd, hkT, gxx, gyy, gxy, gpp;
   bool recoil, doppler;
-  __device__ __forceinline__ void coeffs(const GridArgs<R>& a, int k, R h, R e, R X, R Y, T& q,
+  __device__ __forceinline__ void coeffs(const GridArgs<R>& a, int k, R h, R fx, R fy, T& q,
                                          T& C) const {
     const T K = dd * (T)h;
     T Cv = T(0);
     if (recoil) Cv += K * (hkT - (T)a.two_nu[k]);
     if (doppler) {
-      const Eddington<T> D = closure_state<T>((T)e, (T)X, (T)Y);
+      const Eddington<T> D = closure_reduced<T>((T)fx, (T)fy);
       Cv += (T)a.nu_c[k] * (D.xx * gxx + D.yy * gyy + D.xy * gxy + D.pp * gpp);
     }
     C = Cv;
@@ -562,23 +510,24 @@ __device__ __forceinline__ void freq_forward(const GridArgs<R>& a, const FreqCel
   const int nb = a.nb;
   const double ctdt = (double)a.ctdt;
   double fx = 0.0, fy = 0.0, gx = 0.0, gy = 0.0;
-  auto force = [&](int k, R h, R X, R Y) {
+  auto force = [&](int k, R h, R e, R rx, R ry) {
     // force density: sum_k dnu_k alpha_F,k F**_k (and the line part)
     const double dn = a.dnu[k];
     const double aH = (double)al * (double)h;
     const double aF = aH + acF;
-    fx += dn * aF * (double)X;
-    fy += dn * aF * (double)Y;
-    gx += dn * aH * (double)X;
-    gy += dn * aH * (double)Y;
+    const double X = (double)rx * (double)e, Y = (double)ry * (double)e;
+    fx += dn * aF * X;
+    fy += dn * aF * Y;
+    gx += dn * aH * X;
+    gy += dn * aH * Y;
   };
   constexpr bool kAhead = sizeof(R) == 8;
   R e0 = Ein[c], x0 = Xin[c], y0 = Yin[c], h0 = hb[0];
   R e1 = R(0), x1 = R(0), y1 = R(0), h1 = R(0);
   if (kAhead && nb > 1) { e1 = Ein[nc + c]; x1 = Xin[nc + c]; y1 = Yin[nc + c]; h1 = hb[1]; }
   T qc, Cc;
-  fc.coeffs(a, 0, h0, e0, x0, y0, qc, Cc);
-  force(0, h0, x0, y0);
+  fc.coeffs(a, 0, h0, x0, y0, qc, Cc);
+  force(0, h0, e0, x0, y0);
   FreqRow row;
   for (int k = 0; k < nb; ++k) {
     R e2 = R(0), x2 = R(0), y2 = R(0), h2 = R(0);
@@ -594,8 +543,8 @@ __device__ __forceinline__ void freq_forward(const GridArgs<R>& a, const FreqCel
     double a_k = 0.0, b_next = 0.0;
     if (k + 1 < nb) {
       T qn, Cn;
-      fc.coeffs(a, k + 1, h1, e1, x1, y1, qn, Cn);
-      force(k + 1, h1, x1, y1);
+      fc.coeffs(a, k + 1, h1, x1, y1, qn, Cn);
+      force(k + 1, h1, e1, x1, y1);
       T gl, gr;
       if (qc > T(0) && qn > T(0)) {
         interface_rates<T>(qc, Cc, qn, Cn, gl, gr);
@@ -615,12 +564,11 @@ __device__ __forceinline__ void freq_forward(const GridArgs<R>& a, const FreqCel
   f4[0] = fx; f4[1] = fy; f4[2] = gx; f4[3] = gy;
 }
 
-// Back substitution y_k = z_k + w_k y_{k+1} and the H rescale
-// F^{n+1} = (F**/E**) E^{n+1}, in place over the state.
+// Back substitution y_k = z_k + w_k y_{k+1}, E^{n+1} = y/dnu, in place.  The
+// H rescale F^{n+1} = (F**/E**) E^{n+1} keeps the stored reduced flux.
 template <typename R>
 __device__ __forceinline__ void freq_backward(const GridArgs<R>& a, size_t c, size_t nc,
-                                              R* __restrict__ Eio, R* __restrict__ Xio,
-                                              R* __restrict__ Yio,
+                                              R* __restrict__ Eio,
                                               const ZW<R>* __restrict__ zw) {
   double y = 0.0;
   for (int k = a.nb - 1; k >= 0; --k) {
@@ -629,12 +577,7 @@ __device__ __forceinline__ void freq_backward(const GridArgs<R>& a, size_t c, si
     v.z = __builtin_nontemporal_load(&zw[idx].z);
     v.w = __builtin_nontemporal_load(&zw[idx].w);
     y = (double)v.z + (double)v.w * y;
-    const R En = (R)(y * a.inv_dnu[k]);
-    R fxo, fyo;
-    reduced_flux<R>(Eio[idx], Xio[idx], Yio[idx], fxo, fyo);
-    __builtin_nontemporal_store(En, &Eio[idx]);
-    __builtin_nontemporal_store(fxo * En, &Xio[idx]);
-    __builtin_nontemporal_store(fyo * En, &Yio[idx]);
+    __builtin_nontemporal_store((R)(y * a.inv_dnu[k]), &Eio[idx]);
   }
 }
 
@@ -666,9 +609,9 @@ __device__ void freq_cell(const GridArgs<R>& a, size_t c) {
   fc.doppler = a.doppler != 0 &&
       ((fc.gxx != T(0)) || (fc.gyy != T(0)) || (fc.gxy != T(0)) || (fc.gpp != T(0)));
   double f4[4];
-  freq_forward<R, T>(a, fc, c, nc, a.Eo, a.Fxo, a.Fyo, a.hbar + (size_t)cl * a.nb, a.zw,
+  freq_forward<R, T>(a, fc, c, nc, a.Eo, a.fxo, a.fyo, a.hbar + (size_t)cl * a.nb, a.zw,
                      al, (double)a.acF[c], f4);
-  freq_backward<R>(a, c, nc, a.Eo, a.Fxo, a.Fyo, a.zw);
+  freq_backward<R>(a, c, nc, a.Eo, a.zw);
   a.force[c] = f4[0];
   a.force[nc + c] = f4[1];
   a.force[2 * nc + c] = f4[2];
@@ -728,7 +671,7 @@ void k_freq_batched(const GridArgs<R>* __restrict__ args,
 // at once (the rates of interface k-1|k need both bins, so row k-1 is
 // eliminated when bin k arrives), and after the last bin the block
 // back-substitutes its cells.  E** never goes to memory; f** = F**/E** is
-// kept in the output flux arrays until the back substitution replaces it.
+// the reduced flux of the new state and goes straight to the output.
 // The arithmetic is that of advect_block + freq_cell<float, float> step for
 // step, so both paths give identical bits.
 struct FusedSink {
@@ -767,17 +710,18 @@ struct FusedSink {
                                       float E, float X, float Y) {
     float fxo, fyo;
     reduced_flux<float>(E, X, Y, fxo, fyo);
-    __builtin_nontemporal_store(fxo, &a.Fxo[q]);
-    __builtin_nontemporal_store(fyo, &a.Fyo[q]);
+    __builtin_nontemporal_store(fxo, &a.fxo[q]);
+    __builtin_nontemporal_store(fyo, &a.fyo[q]);
     float qk, Ck;
-    fc[m].coeffs(a, k, h, E, X, Y, qk, Ck);
+    fc[m].coeffs(a, k, h, fxo, fyo, qk, Ck);
     const double dn = a.dnu[k];
     const double aH = (double)al[m] * (double)h;
     const double aF = aH + acF[m];
-    f4[m][0] += dn * aF * (double)X;
-    f4[m][1] += dn * aF * (double)Y;
-    f4[m][2] += dn * aH * (double)X;
-    f4[m][3] += dn * aH * (double)Y;
+    const double Xd = (double)fxo * (double)E, Yd = (double)fyo * (double)E;
+    f4[m][0] += dn * aF * Xd;
+    f4[m][1] += dn * aF * Yd;
+    f4[m][2] += dn * aH * Xd;
+    f4[m][3] += dn * aH * Yd;
     if (k > 0) {
       float gl, gr;
       if (qp[m] > 0.0f && qk > 0.0f) {
@@ -806,24 +750,9 @@ struct FusedSink {
       if (own[m])
         row[m].eliminate<float>(nb - 1, a.dnu[nb - 1] * (double)ep[m], 0.0, 0.0,
                                 &a.zw[(size_t)(nb - 1) * nc + cidx[m]]);
-    double y[2] = {0.0, 0.0};
-    for (int k = nb - 1; k >= 0; --k) {
 #pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        if (!own[m]) continue;
-        const size_t idx = (size_t)k * nc + cidx[m];
-        ZW<float> v;
-        v.z = __builtin_nontemporal_load(&a.zw[idx].z);
-        v.w = __builtin_nontemporal_load(&a.zw[idx].w);
-        y[m] = (double)v.z + (double)v.w * y[m];
-        const float En = (float)(y[m] * a.inv_dnu[k]);
-        const float fxo = __builtin_nontemporal_load(&a.Fxo[idx]);
-        const float fyo = __builtin_nontemporal_load(&a.Fyo[idx]);
-        __builtin_nontemporal_store(En, &a.Eo[idx]);
-        __builtin_nontemporal_store(fxo * En, &a.Fxo[idx]);
-        __builtin_nontemporal_store(fyo * En, &a.Fyo[idx]);
-      }
-    }
+    for (int m = 0; m < 2; ++m)
+      if (own[m]) freq_backward<float>(a, cidx[m], nc, a.Eo, a.zw);
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       if (!own[m]) continue;
@@ -895,23 +824,39 @@ __global__ void k_residual_final(const double* __restrict__ partial, int nblk,
 }
 
 // ------------------------------------------------------- copies with scale
-template <typename S, typename D>
-__global__ void k_scale_copy(const S* __restrict__ src, D* __restrict__ dst, size_t n, int e2) {
-  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
-       q += (size_t)gridDim.x * blockDim.x)
-    dst[q] = (D)ldexp((double)src[q], e2);
-}
-
-// dst[k][jj][ii] = 2^e2 src[k][j0 + jj][i0 + ii] for a w x h window of every bin.
+// Physical state out of the internal one: E_phys = 2^e2 E, F_phys = 2^e2 f E
+// (product in double), for the w x h window (i0, j0) of every bin; the whole
+// grid is the window (0, 0, nx, ny).  Null outputs are skipped.
 template <typename S>
-__global__ void k_region_copy(const S* __restrict__ src, double* __restrict__ dst, int nx, int ny,
-                              int nb, int i0, int j0, int w, int h, int e2) {
+__global__ void k_state_out(const S* __restrict__ E, const S* __restrict__ fx,
+                            const S* __restrict__ fy, int nx, int ny, int nb, int i0, int j0,
+                            int w, int h, int e2, double* __restrict__ dE,
+                            double* __restrict__ dFx, double* __restrict__ dFy) {
   const size_t per = (size_t)w * h, n = per * nb;
   for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
        q += (size_t)gridDim.x * blockDim.x) {
     const size_t k = q / per, r = q % per;
     const int jj = (int)(r / w), ii = (int)(r % w);
-    dst[q] = ldexp((double)src[(k * ny + j0 + jj) * nx + i0 + ii], e2);
+    const size_t src = (k * ny + j0 + jj) * nx + i0 + ii;
+    const double e = (double)E[src];
+    if (dE) dE[q] = ldexp(e, e2);
+    if (dFx) dFx[q] = ldexp((double)fx[src] * e, e2);
+    if (dFy) dFy[q] = ldexp((double)fy[src] * e, e2);
+  }
+}
+
+// Internal state from the physical one: E = 2^e2 E_phys, f = F/E (0 where E <= 0).
+template <typename D>
+__global__ void k_state_in(const double* __restrict__ sE, const double* __restrict__ sFx,
+                           const double* __restrict__ sFy, size_t n, int e2, D* __restrict__ E,
+                           D* __restrict__ fx, D* __restrict__ fy) {
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += (size_t)gridDim.x * blockDim.x) {
+    const double e = sE[q];
+    const bool pos = e > 0.0;
+    E[q] = (D)ldexp(e, e2);
+    fx[q] = pos ? (D)(sFx[q] / e) : D(0);
+    fy[q] = pos ? (D)(sFy[q] / e) : D(0);
   }
 }
 
@@ -1020,26 +965,34 @@ hipError_t launch_residual(const R* E0, const R* E1, size_t n, double* partial, 
   return hipGetLastError();
 }
 
-template <typename S, typename D>
-hipError_t launch_scale_copy(const S* src, D* dst, size_t n, int e2, hipStream_t s) {
-  unsigned g = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
-  hipLaunchKernelGGL((k_scale_copy<S, D>), dim3(g ? g : 1), dim3(256), 0, s, src, dst, n, e2);
-  return hipGetLastError();
-}
-
 template <typename S>
-hipError_t launch_region_copy(const S* src, double* dst, int nx, int ny, int nb, int i0, int j0,
-                              int w, int h, int e2, hipStream_t s) {
+hipError_t launch_state_out(const S* E, const S* fx, const S* fy, int nx, int ny, int nb, int i0,
+                            int j0, int w, int h, int e2, double* dE, double* dFx, double* dFy,
+                            hipStream_t s) {
   const size_t n = (size_t)w * h * nb;
   unsigned g = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
-  hipLaunchKernelGGL((k_region_copy<S>), dim3(g ? g : 1), dim3(256), 0, s, src, dst, nx, ny, nb,
-                     i0, j0, w, h, e2);
+  hipLaunchKernelGGL((k_state_out<S>), dim3(g ? g : 1), dim3(256), 0, s, E, fx, fy, nx, ny, nb,
+                     i0, j0, w, h, e2, dE, dFx, dFy);
   return hipGetLastError();
 }
-template hipError_t launch_region_copy<float>(const float*, double*, int, int, int, int, int, int,
-                                              int, int, hipStream_t);
-template hipError_t launch_region_copy<double>(const double*, double*, int, int, int, int, int, int,
-                                               int, int, hipStream_t);
+template <typename D>
+hipError_t launch_state_in(const double* sE, const double* sFx, const double* sFy, size_t n,
+                           int e2, D* E, D* fx, D* fy, hipStream_t s) {
+  unsigned g = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL((k_state_in<D>), dim3(g ? g : 1), dim3(256), 0, s, sE, sFx, sFy, n, e2, E, fx,
+                     fy);
+  return hipGetLastError();
+}
+template hipError_t launch_state_out<float>(const float*, const float*, const float*, int, int, int,
+                                            int, int, int, int, int, double*, double*, double*,
+                                            hipStream_t);
+template hipError_t launch_state_out<double>(const double*, const double*, const double*, int, int,
+                                             int, int, int, int, int, int, double*, double*,
+                                             double*, hipStream_t);
+template hipError_t launch_state_in<float>(const double*, const double*, const double*, size_t, int,
+                                           float*, float*, float*, hipStream_t);
+template hipError_t launch_state_in<double>(const double*, const double*, const double*, size_t,
+                                            int, double*, double*, double*, hipStream_t);
 
 hipError_t launch_force_out(const double* force, size_t nc, int e2, double* fx, double* fy,
                             double* gx, double* gy, hipStream_t s) {
@@ -1064,8 +1017,5 @@ template hipError_t launch_freq<float>(const GridArgs<float>&, hipStream_t);
 template hipError_t launch_freq<double>(const GridArgs<double>&, hipStream_t);
 template hipError_t launch_residual<float>(const float*, const float*, size_t, double*, int, double*, hipStream_t);
 template hipError_t launch_residual<double>(const double*, const double*, size_t, double*, int, double*, hipStream_t);
-template hipError_t launch_scale_copy<float, double>(const float*, double*, size_t, int, hipStream_t);
-template hipError_t launch_scale_copy<double, float>(const double*, float*, size_t, int, hipStream_t);
-template hipError_t launch_scale_copy<double, double>(const double*, double*, size_t, int, hipStream_t);
 
 }  // namespace m1
