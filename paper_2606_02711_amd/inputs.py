@@ -215,6 +215,36 @@ def uniform_cloud(geom, n, log10_NHI, T, dust_solar, L_box=PC, steps=500, fields
     return p
 
 
+def cone_cloud(n=256, R_cl=PC, tau_cl=1.0e8, tau_cone=1.0e5, T=1.0e4, mu_cone=2 ** -0.5,
+               dmu=0.025):
+    """Anisotropic-escape cloud of Section 4 (Test 6): a spherical cloud of
+    radius R_cl at T with a bipolar low-density cone (half-opening angle
+    acos(mu_cone), tanh transition of width dmu in mu = |Z|/r), neutral
+    fraction 1 in the shell 0.5 R_cl < r <= R_cl and 1e-4 inside, uniform
+    emission inside 0.5 R_cl, vacuum outside.  Densities from
+    tau = n_H sigma0(T) R_cl.  Box [0, 1.1 R_cl]^2 in (R, Z): reflecting axis
+    and midplane, outflow at the outer edges; c_tilde = c; recoil on, no
+    continuum absorption, no destruction."""
+    half = 1.1 * R_cl
+    p = base_problem("cyl", n, n, 0.0, half, 0.0, half,
+                     ("reflect", "vacuum", "reflect", "vacuum"), c_tilde_frac=1.0)
+    R, Z = cell_centres(p)
+    r = np.sqrt(R[None, :] ** 2 + Z[:, None] ** 2)
+    mu = np.where(r > 0, np.abs(Z)[:, None] / np.where(r > 0, r, 1.0), 0.0)
+    sig0 = SIGMA0_1E4 * (T / 1.0e4) ** -0.5
+    n_cl, n_cone = tau_cl / (sig0 * R_cl), tau_cone / (sig0 * R_cl)
+    n_H = n_cone + 0.5 * (n_cl - n_cone) * (1.0 - np.tanh((mu - mu_cone) / dmu))
+    eps = np.where(r <= 0.5 * R_cl, 1.0e-4, 1.0)
+    f = uniform_fields(p, 0.0, T)
+    f["n_HI"] = np.where(r <= R_cl, eps * n_H, 0.0)
+    src = (r <= 0.5 * R_cl).astype(float)
+    f["emis"] = src / float(np.sum(src * cell_volumes(p)))      # 1 erg/s in the box
+    p["fields"] = f
+    p["R_cl"] = R_cl
+    p["t_max"] = 4.0 * max((4.7e-4 * (T / 1.0e4) ** -0.5 * tau_cl) ** (1.0 / 3.0), 3.0) * R_cl / C_LIGHT
+    return p
+
+
 def config3(n_grids=64, lo=64, hi=512, config_id=3, steps=500):
     rng = rng_for(config_id)
     probs = []
