@@ -54,6 +54,25 @@ def measured_traffic(kernel, prec):
     return rec.get("bytes_per_launch") if rec else None
 
 
+VALU_PEAK = 1024 * 16 * 2.4e9      # lane-instructions/s: 1024 SIMDs x 16 lanes x 2.4 GHz
+
+
+def measured_valu(kernel, prec):
+    """VALU lane-instructions per cell-bin from the committed counter run, if
+    it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "valu_counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    rec = d.get("kernels", {}).get(f"{kernel}:{prec}")
+    return rec.get("valu_per_cell_bin") if rec else None
+
+
 def run_path(p, prec, steps, warmup, fp64_tau=float("inf")):
     import torch
     from paper_2606_02711_amd import m1
@@ -287,6 +306,12 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
     }
+    valu = measured_valu(dom, "fp32")
+    if valu is not None:
+        rate = valu * r32["cell_bins"] / (dom_ms * 1e-3)
+        out["roofline_valu"] = {"bound": "alu", "kernel": dom, "achieved": rate, "peak": VALU_PEAK,
+                                "unit": "VALU lane-instr/s", "frac": rate / VALU_PEAK,
+                                "valu_per_cell_bin": valu}
     if r64 is not None:
         out["fp64_value"] = r64["rate"]
         out["fp64_ms_per_step"] = 1e3 * r64["wall"] / args.steps

@@ -161,6 +161,8 @@ int validate_config(const m1_config* c, int* nb_out) {
   if (c->prec != M1_FP64 && c->prec != M1_FP32) return fail(M1_EINVAL, "bad precision");
   if (c->recoil != 0 && c->recoil != 1) return fail(M1_EINVAL, "recoil must be 0/1");
   if (c->doppler != 0 && c->doppler != 1) return fail(M1_EINVAL, "doppler must be 0/1");
+  if ((int64_t)c->nx * c->ny > (int64_t(1) << 29))
+    return fail(M1_EUNSUPPORTED, "more than 2^29 cells in one grid");
   if (isnan(c->fp64_tau)) return fail(M1_EINVAL, "fp64_tau is NaN");
   FreqGrid g;
   int st = build_grid(*c, g);

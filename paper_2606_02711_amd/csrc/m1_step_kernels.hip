@@ -91,6 +91,7 @@ constexpr int kNYF = (kTY + 1) * kTX;         // y-faces of a tile
 template <typename R>
 struct AdvShared {
   R E[kPY][kPX], fx[kPY][kPX], fy[kPY][kPX];  // staged state: E and f = F/E
+  int src[kPY * kPX];                          // staging sources (see advect_block)
   R aF[kRY][kRX];                              // alpha_F of the ring, this bin
   R fle[kNXF + kNYF], flx[kNXF + kNYF], fly[kNXF + kNYF];  // face fluxes
   R un[kNXF + kNYF];                           // face-normal velocity / c
@@ -243,26 +244,18 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
   const R ctdt = a.ctdt, ctdt_c = a.ctdt_c;
   sink.init(a, own, cidx, ccls);
 
-  // staging entries of this lane (fixed for all bins): source offset within a
-  // bin, or -1 for a vacuum / unused entry, and the mirror signs of f
-  // (hoisted only for double: in float the registers cost an occupancy step)
-  constexpr bool kHoist = sizeof(R) == 8;
-  constexpr int kStage = kHoist ? (kPX * kPY + 255) / 256 : 1;
-  int soff[kStage];
-  R ssx[kStage], ssy[kStage];
-#pragma unroll
-  for (int m = 0; m < kStage; ++m) {
-    const int e = tid + 256 * m;
-    soff[m] = -1; ssx[m] = R(1); ssy[m] = R(1);
-    if (e < kPX * kPY) {
-      const int pi = e % kPX, pj = e / kPX;
-      int si, sj, sgx, sgy;
-      bool vac;
-      if (ghost_source(x0 + pi - 2, y0 + pj - 2, nx, ny, a.bc, 2, si, sj, sgx, sgy, vac) && !vac) {
-        soff[m] = sj * nx + si;
-        ssx[m] = R(sgx); ssy[m] = R(sgy);
-      }
-    }
+  // staging sources, fixed for all bins: the source cell's offset within a
+  // bin shifted left by 2, bit 0 / bit 1 set where f_x / f_y change sign
+  // (mirror image), -1 for a vacuum ghost.  Each lane reads back only the
+  // entries it wrote, so no barrier is needed.
+  for (int e = tid; e < kPX * kPY; e += 256) {
+    const int pi = e % kPX, pj = e / kPX;
+    int si, sj, sgx, sgy;
+    bool vac;
+    int v = -1;
+    if (ghost_source(x0 + pi - 2, y0 + pj - 2, nx, ny, a.bc, 2, si, sj, sgx, sgy, vac) && !vac)
+      v = ((sj * nx + si) << 2) | (sgx < 0 ? 1 : 0) | (sgy < 0 ? 2 : 0);
+    S.src[e] = v;
   }
 
   for (int k = k0; k < kend; ++k) {
@@ -272,34 +265,18 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
     const R* Xk = a.fx + koff;
     const R* Yk = a.fy + koff;
     // (1) stage E and f of the padded tile, and alpha_F of the ring
-    if constexpr (kHoist) {
-#pragma unroll
-    for (int m = 0; m < kStage; ++m) {
-      const int e = tid + 256 * m;
-      if (e < kPX * kPY) {
-        R ev = R(0), fxv = R(0), fyv = R(0);
-        if (soff[m] >= 0) {
-          ev = Ek[soff[m]];
-          fxv = Xk[soff[m]] * ssx[m];
-          fyv = Yk[soff[m]] * ssy[m];
-        }
-        (&S.E[0][0])[e] = ev; (&S.fx[0][0])[e] = fxv; (&S.fy[0][0])[e] = fyv;
+    for (int e = tid; e < kPX * kPY; e += 256) {
+      const int v = S.src[e];
+      R ev = R(0), fxv = R(0), fyv = R(0);
+      if (v >= 0) {
+        const int q = v >> 2;
+        ev = Ek[q];
+        fxv = Xk[q];
+        fyv = Yk[q];
+        fxv = (v & 1) ? -fxv : fxv;
+        fyv = (v & 2) ? -fyv : fyv;
       }
-    }
-    } else {
-      for (int e = tid; e < kPX * kPY; e += 256) {
-        const int pi = e % kPX, pj = e / kPX;
-        int si, sj, sgx, sgy;
-        bool vac;
-        R ev = R(0), fxv = R(0), fyv = R(0);
-        if (ghost_source(x0 + pi - 2, y0 + pj - 2, nx, ny, a.bc, 2, si, sj, sgx, sgy, vac) && !vac) {
-          const int q = sj * nx + si;
-          ev = Ek[q];
-          fxv = Xk[q] * R(sgx);
-          fyv = Yk[q] * R(sgy);
-        }
-        S.E[pj][pi] = ev; S.fx[pj][pi] = fxv; S.fy[pj][pi] = fyv;
-      }
+      (&S.E[0][0])[e] = ev; (&S.fx[0][0])[e] = fxv; (&S.fy[0][0])[e] = fyv;
     }
 #pragma unroll
     for (int m = 0; m < kRingPerLane; ++m) {
