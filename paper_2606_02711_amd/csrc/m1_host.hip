@@ -105,6 +105,15 @@ struct Layout {
 
 constexpr int kResBlocks = 1024;
 
+// Device bytes the set-up needs for temporaries: the input fields (when they
+// come from the host), class sums and tables, face velocities in double.
+size_t init_temp_need(size_t nc, int nb, int64_t ncls, int nx, int ny, bool host_fields) {
+  size_t need = host_fields ? 8 * align_up(nc * sizeof(double)) : 0;
+  need += 2 * align_up(ncls * sizeof(double)) + align_up((size_t)ncls * nb * sizeof(double));
+  need += 2 * ((size_t)(nx + 1) * ny + (size_t)nx * (ny + 1)) * sizeof(double);
+  return need;
+}
+
 Layout make_layout(int nx, int ny, int nb, int64_t ncls, size_t rs) {
   Layout L;
   size_t off = 0;
@@ -113,6 +122,11 @@ Layout make_layout(int nx, int ny, int nb, int64_t ncls, size_t rs) {
   for (int b = 0; b < 2; ++b)
     for (int f = 0; f < 3; ++f) L.state[b][f] = take(nbc * rs);
   L.zw = take(2 * nbc * rs);
+  // the set-up borrows the second state buffer and the scratch; with few
+  // bins that span is padded up to the set-up's need
+  const size_t span = off - L.state[1][0];
+  const size_t need = init_temp_need(nc, nb, ncls > 0 ? ncls : (int64_t)nc, nx, ny, true);
+  if (span < need) take(need - span);
   L.force = take(4 * nc * sizeof(double));
   L.cls = take(nc * sizeof(int32_t));
   L.island = take(nc);
@@ -454,12 +468,6 @@ int init_typed(m1_handle* h, const m1_fields* f, const std::vector<std::vector<d
   return M1_OK;
 }
 
-size_t init_temp_need(size_t nc, int nb, int64_t ncls, int nx, int ny, bool host_fields) {
-  size_t need = host_fields ? 8 * align_up(nc * sizeof(double)) : 0;
-  need += 2 * align_up(ncls * sizeof(double)) + align_up((size_t)ncls * nb * sizeof(double));
-  need += 2 * ((size_t)(nx + 1) * ny + (size_t)nx * (ny + 1)) * sizeof(double);
-  return need;
-}
 
 }  // namespace
 

@@ -152,3 +152,23 @@ def test_server_bookkeeping_without_device_work():
     cfg = m1.make_config(small, "fp32")
     assert L.m1_server_submit(h, ctypes.byref(cfg), 1, 0.0, 100, ctypes.byref(rid)) == m1.M1_EINVAL
     m1.check(L.m1_server_free(h))
+
+
+@pytest.mark.parametrize("nx,ny,code", [(0, 8, m1.M1_EINVAL), (-4, 8, m1.M1_EINVAL),
+                                        (1 << 15, 1 << 15, m1.M1_EUNSUPPORTED)])
+def test_empty_and_oversized_grids_rejected(nx, ny, code):
+    p = inputs.config1()
+    c = m1.make_config(p)
+    c.nx, c.ny = nx, ny
+    b = ctypes.c_size_t()
+    assert m1.lib().m1_workspace_bytes(ctypes.byref(c), 1, ctypes.byref(b)) == code
+    assert len(m1.lib().m1_last_error()) > 0
+
+
+def test_empty_batch_rejected():
+    b = ctypes.c_size_t()
+    arr = (ctypes.c_void_p * 1)()
+    assert m1.lib().m1_batch_workspace_bytes(arr, 0, ctypes.byref(b)) == m1.M1_EINVAL
+    assert m1.lib().m1_batch_workspace_bound(0, m1.M1_FP32, ctypes.byref(b)) == m1.M1_EINVAL
+    h = ctypes.c_void_p()
+    assert m1.lib().m1_batch_init(arr, 0, 256, 1 << 20, 0, ctypes.byref(h)) == m1.M1_EINVAL
