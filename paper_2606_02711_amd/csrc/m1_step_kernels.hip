@@ -22,23 +22,14 @@ struct Flux3 {
   R e, x, y;
 };
 
-// Flux of (E, F_x, F_y) through one face with normal n (0: x, 1: y).
-// Cells along the normal: LL, L | face | R, RR (values e*, fx*, fy*).
-// iLL = 1/(c_L - c_LL), iLR = 1/(c_R - c_L), iRR = 1/(c_RR - c_R) are inverse
-// centroid distances; hL = x_f - c_L > 0, hR = x_f - c_R < 0.
+// Flux of (E, F_x, F_y) through one face with normal n (0: x, 1: y), from
+// the reconstructed states on its two sides (EL, fxL, fyL | ER, fxR, fyR),
+// the cell values eL, eR (diffusion term), the centroid distances
+// hL = x_f - c_L > 0 and hR = x_f - c_R < 0, the flux opacities of the two
+// cells and the face-normal velocity over c.
 template <typename R, int N>
-__device__ __forceinline__ Flux3<R> face_flux(R eLL, R xLL, R yLL, R eL, R xL, R yL,
-                                              R eR, R xR, R yR, R eRR, R xRR, R yRR,
-                                              R iLL, R iLR, R iRR, R hL, R hR,
-                                              R aFL, R aFR, R un_c) {
-  // MinMod slopes of E, f_x, f_y on both sides and reconstructed face states
-  R dE = (eR - eL) * iLR, dX = (xR - xL) * iLR, dY = (yR - yL) * iLR;
-  R EL = eL + minmod((eL - eLL) * iLL, dE) * hL;
-  R fxL = xL + minmod((xL - xLL) * iLL, dX) * hL;
-  R fyL = yL + minmod((yL - yLL) * iLL, dY) * hL;
-  R ER = eR + minmod(dE, (eRR - eR) * iRR) * hR;
-  R fxR = xR + minmod(dX, (xRR - xR) * iRR) * hR;
-  R fyR = yR + minmod(dY, (yRR - yR) * iRR) * hR;
+__device__ __forceinline__ Flux3<R> face_flux(R EL, R fxL, R fyL, R ER, R fxR, R fyR, R eL,
+                                              R eR, R hL, R hR, R aFL, R aFR, R un_c) {
   // causality at the interface: |f| > 1 is scaled back to 1
   const R nL = fxL * fxL + fyL * fyL, nR = fxR * fxR + fyR * fyR;
   if (nL > R(1) || nR > R(1)) [[unlikely]] {    // rare: one branch for both sides
@@ -132,6 +123,56 @@ __device__ __forceinline__ bool ghost_source(int ii, int jj, int nx, int ny, con
 }
 
 constexpr int kRingPerLane = (kRX * kRY + 255) / 256;   // 3
+
+// Runs of faces: 128 lanes take the kTY x (kTX + 1) x-faces, 128 the
+// kTX x (kTY + 1) y-faces, so each lane walks 4-5 faces along one line.
+constexpr int kRunsX = 128 / kTY;     // runs per tile row
+constexpr int kRunsY = 128 / kTX;     // runs per tile column
+static_assert(128 % kTY == 0 && 128 % kTX == 0, "runs must tile the faces");
+
+// Faces [c0, c1) along line `line` (N = 0: tile row, faces between padded
+// columns c+1 and c+2; N = 1: tile column, faces between padded rows c+1 and
+// c+2).  MinMod slopes on centroid distances: each cell's slope and each
+// difference between neighbours is formed once and carried along the run.
+template <typename R, int N>
+__device__ __forceinline__ void face_run(AdvShared<R>& S, int line, int c0, int c1) {
+  auto ld = [&](int p, R& e, R& x, R& y) {
+    if (N == 0) { e = S.E[line + 2][p]; x = S.fx[line + 2][p]; y = S.fy[line + 2][p]; }
+    else        { e = S.E[p][line + 2]; x = S.fx[p][line + 2]; y = S.fy[p][line + 2]; }
+  };
+  const R* idl = N == 0 ? S.xidl : S.yidl;
+  const R* hp = N == 0 ? S.xhp : S.yhp;
+  const R* hm = N == 0 ? S.xhm : S.yhm;
+  R e0, x0, y0, e1, x1, y1, e2, x2, y2;
+  ld(c0, e0, x0, y0);
+  ld(c0 + 1, e1, x1, y1);
+  ld(c0 + 2, e2, x2, y2);
+  const R i01 = idl[c0];
+  R i12 = idl[c0 + 1];
+  R dE = (e2 - e1) * i12, dX = (x2 - x1) * i12, dY = (y2 - y1) * i12;
+  R sE = minmod((e1 - e0) * i01, dE), sX = minmod((x1 - x0) * i01, dX),
+    sY = minmod((y1 - y0) * i01, dY);
+  for (int c = c0; c < c1; ++c) {
+    R e3, x3, y3;
+    ld(c + 3, e3, x3, y3);
+    const R i23 = idl[c + 2];
+    const R dE3 = (e3 - e2) * i23, dX3 = (x3 - x2) * i23, dY3 = (y3 - y2) * i23;
+    const R tE = minmod(dE, dE3), tX = minmod(dX, dX3), tY = minmod(dY, dY3);
+    const R hL = hp[c], hR = hm[c + 1];
+    R aFL, aFR;
+    int f;
+    if (N == 0) { aFL = S.aF[line + 1][c]; aFR = S.aF[line + 1][c + 1]; f = line * (kTX + 1) + c; }
+    else        { aFL = S.aF[c][line + 1]; aFR = S.aF[c + 1][line + 1]; f = kNXF + c * kTX + line; }
+    const Flux3<R> r = face_flux<R, N>(e1 + sE * hL, x1 + sX * hL, y1 + sY * hL,
+                                       e2 + tE * hR, x2 + tX * hR, y2 + tY * hR,
+                                       e1, e2, hL, hR, aFL, aFR, S.un[f]);
+    S.fle[f] = r.e; S.flx[f] = r.x; S.fly[f] = r.y;
+    e1 = e2; x1 = x2; y1 = y2;
+    e2 = e3; x2 = x3; y2 = y3;
+    dE = dE3; dX = dX3; dY = dY3;
+    sE = tE; sX = tX; sY = tY;
+  }
+}
 
 // Where the post-source state E**, F** of an owned cell goes: to the output
 // state (the frequency step runs in its own kernel), or into the frequency
@@ -284,32 +325,15 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
       if (e < kRX * kRY) (&S.aF[0][0])[e] = ral[m] * hb[(size_t)rcls[m] * nb] + racF[m];
     }
     __syncthreads();
-    // (2) every face of the tile once: x-faces [0, kNXF), then y-faces
-    for (int f = tid; f < kNXF + kNYF; f += 256) {
-      Flux3<R> r;
-      if (f < kNXF) {
-        const int fr = f / (kTX + 1), fc = f % (kTX + 1);
-        const int pj = fr + 2, pl = fc + 1;
-        r = face_flux<R, 0>(
-            S.E[pj][pl - 1], S.fx[pj][pl - 1], S.fy[pj][pl - 1],
-            S.E[pj][pl], S.fx[pj][pl], S.fy[pj][pl],
-            S.E[pj][pl + 1], S.fx[pj][pl + 1], S.fy[pj][pl + 1],
-            S.E[pj][pl + 2], S.fx[pj][pl + 2], S.fy[pj][pl + 2],
-            S.xidl[fc], S.xidl[fc + 1], S.xidl[fc + 2], S.xhp[fc], S.xhm[fc + 1],
-            S.aF[fr + 1][fc], S.aF[fr + 1][fc + 1], S.un[f]);
-      } else {
-        const int g = f - kNXF;
-        const int fr = g / kTX, fc = g % kTX;
-        const int pi = fc + 2, pl = fr + 1;
-        r = face_flux<R, 1>(
-            S.E[pl - 1][pi], S.fx[pl - 1][pi], S.fy[pl - 1][pi],
-            S.E[pl][pi], S.fx[pl][pi], S.fy[pl][pi],
-            S.E[pl + 1][pi], S.fx[pl + 1][pi], S.fy[pl + 1][pi],
-            S.E[pl + 2][pi], S.fx[pl + 2][pi], S.fy[pl + 2][pi],
-            S.yidl[fr], S.yidl[fr + 1], S.yidl[fr + 2], S.yhp[fr], S.yhm[fr + 1],
-            S.aF[fr][fc + 1], S.aF[fr + 1][fc + 1], S.un[f]);
-      }
-      S.fle[f] = r.e; S.flx[f] = r.x; S.fly[f] = r.y;
+    // (2) every face of the tile once, in runs of 4-5 consecutive faces along
+    // a line: waves 0-1 the x-faces (runs along rows), waves 2-3 the y-faces
+    // (runs along columns).
+    if (tid < 128) {
+      const int r = tid / kRunsX, s = tid % kRunsX;
+      face_run<R, 0>(S, r, s * (kTX + 1) / kRunsX, (s + 1) * (kTX + 1) / kRunsX);
+    } else {
+      const int u = tid - 128, c = u / kRunsY, s = u % kRunsY;
+      face_run<R, 1>(S, c, s * (kTY + 1) / kRunsY, (s + 1) * (kTY + 1) / kRunsY);
     }
     __syncthreads();
     // (3) update, causality clamp, implicit source
@@ -348,8 +372,13 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
   sink.finish(a, own, cidx);
 }
 
+// Float: five waves per SIMD, the block count LDS allows per CU.
+template <typename R>
+constexpr int kAdvectWaves = sizeof(R) == 4 ? 5 : 1;
+
 template <typename R, int BK>
-__global__ __launch_bounds__(256) void k_advect_source(GridArgs<R> a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kAdvectWaves<R>)))
+void k_advect_source(GridArgs<R> a) {
   __shared__ AdvShared<R> S;
   WriteSink<R> sink;
   advect_block<R, BK>(a, xcd_logical_block(), S, sink);
@@ -360,7 +389,8 @@ __global__ __launch_bounds__(256) void k_advect_source(GridArgs<R> a) {
 // first work item of grid g (off[n] = total); args holds both ping-pong
 // directions, [2][n]; grid g uses direction par[g] ^ sp.
 template <typename R, int BK>
-__global__ __launch_bounds__(256) void k_advect_batched(const GridArgs<R>* __restrict__ args,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kAdvectWaves<R>)))
+void k_advect_batched(const GridArgs<R>* __restrict__ args,
                                                         const int* __restrict__ par, int n,
                                                         int sp, const int* __restrict__ off) {
   __shared__ AdvShared<R> S;
