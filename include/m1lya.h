@@ -154,10 +154,12 @@ int32_t m1_solve_steady(m1_handle *h, double rel_tol, int64_t max_steps,
 int32_t m1_residual(m1_handle *h, double *resid);
 
 /* Copy the state out of / into caller device arrays of doubles
- * [N_nu][ny][nx] in physical units (E, F per Hz).  The FP32 path keeps its
- * state scaled by 2^scale_exp2 internally (see m1_get_info), so physical
- * values far below FLT_MIN are still exchanged exactly.  get is blocking;
- * set is asynchronous. */
+ * [N_nu][ny][nx] in physical units (E, F per Hz).  Internally the state is
+ * E (scaled by 2^scale_exp2 in the FP32 path, see m1_get_info, so values far
+ * below FLT_MIN are kept) and the reduced flux f = F/E in the state
+ * precision: get forms F = f E in double (NULL outputs are skipped); set
+ * stores f = F/E and drops the flux where E <= 0.  get is blocking; set is
+ * asynchronous. */
 int32_t m1_get_state(m1_handle *h, double *d_E, double *d_Fx, double *d_Fy);
 int32_t m1_set_state(m1_handle *h, const double *d_E, const double *d_Fx,
                      const double *d_Fy);
