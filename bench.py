@@ -207,7 +207,7 @@ def run_serving(args):
     return out
 
 
-def cpu_baseline(p, steps=2):
+def cpu_baseline(p, steps=10):
     from oracle import m1_oracle
     log(f"[bench] oracle sample: {steps} steps of the full workload on the host")
     o = m1_oracle.Oracle(p)
