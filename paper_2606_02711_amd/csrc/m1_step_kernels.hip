@@ -1,17 +1,20 @@
 // Hot-path kernels of the M1 Lyman-alpha step (gfx950, wave64).
 //
-//   advect_source : Section 2.1 steps 1 and 2 for a run of bins of one cell
-//                   per lane: MinMod reconstruction of E and f, Levermore
-//                   closure, GLF flux (HLL with signal speeds +-c_tilde)
-//                   blended with the diffusion flux by eps(tau), upwind
-//                   velocity advection, work term, hoop pressure (R, z),
-//                   causality clamp, implicit emission/absorption (BDF1).
+//   advect_source : Section 2.1 steps 1 and 2; a block per 32 x 16 tile and
+//                   run of bins, two cells per lane: MinMod reconstruction of
+//                   E and f, Levermore closure, GLF flux (HLL with signal
+//                   speeds +-c_tilde) blended with the diffusion flux by
+//                   eps(tau), upwind velocity advection, work term, hoop
+//                   pressure (R, z), causality clamp, implicit
+//                   emission/absorption (BDF1).
 //   freq_step     : Section 2.3 force density and Appendix A frequency step
 //                   for all bins of one cell per lane: exponential-scheme
 //                   interface rates, subtraction-free elimination of the
 //                   tridiagonal system in photon-number variables.  The H
 //                   rescale F -> F E^{n+1}/E** keeps f = F/E, which is what
 //                   the state stores, so only E is rewritten.
+//   step_fused    : both in one kernel, a block per tile and all bins (a
+//                   batch tile variant).
 //   residual      : deterministic FP64 norms ||E^{n+1} - E^n||, ||E^{n+1}||.
 #include "m1_kernels.h"
 
