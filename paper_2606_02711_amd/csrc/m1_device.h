@@ -58,6 +58,53 @@ struct GridArgs {
   double *force;          // [4][ncell]
 };
 
+// Address-space hints for pointers read from a descriptor table in memory
+// (batches).  Such pointers are generic: the compiler emits flat loads and
+// stores through them, and vector loads even where the index is uniform.
+// An empty move in the target address space (which the optimiser cannot fold
+// away) restores what a kernel argument would tell it.  The pointer must be
+// uniform across the wave: it is held in scalar registers.
+//
+// global_ptr: global memory (state, scratch, force).
+template <typename T>
+__device__ __forceinline__ T* global_ptr(T* p) {
+  typedef __attribute__((address_space(1))) T* gptr;
+  gptr g = (gptr)p;
+  asm("" : "+s"(g));
+  return (T*)g;
+}
+
+// const_ptr: memory that no kernel of the step writes (cell data, profiles,
+// bin and geometry tables), so loads at a uniform index become scalar loads.
+template <typename T>
+__device__ __forceinline__ const T* const_ptr(const T* p) {
+  typedef __attribute__((address_space(4))) const T* cptr;
+  cptr g = (cptr)p;
+  asm("" : "+s"(g));
+  return (const T*)g;
+}
+
+// A grid's arguments read from a descriptor table, with these hints.
+template <typename R>
+__device__ __forceinline__ GridArgs<R> global_args(const GridArgs<R>& s) {
+  GridArgs<R> a = s;
+  a.E = global_ptr(a.E); a.fx = global_ptr(a.fx); a.fy = global_ptr(a.fy);
+  a.Eo = global_ptr(a.Eo); a.fxo = global_ptr(a.fxo); a.fyo = global_ptr(a.fyo);
+  a.zw = global_ptr(a.zw); a.force = global_ptr(a.force);
+  a.cls = const_ptr(a.cls); a.island = const_ptr(a.island);
+  a.alpha = const_ptr(a.alpha); a.acF = const_ptr(a.acF); a.acabs = const_ptr(a.acabs);
+  a.pda = const_ptr(a.pda); a.em = const_ptr(a.em); a.grad = const_ptr(a.grad);
+  a.ufx = const_ptr(a.ufx); a.ufy = const_ptr(a.ufy);
+  a.hbar = const_ptr(a.hbar); a.phi = const_ptr(a.phi);
+  a.dD2h = const_ptr(a.dD2h); a.hkT = const_ptr(a.hkT); a.dnu = const_ptr(a.dnu);
+  a.inv_dnu = const_ptr(a.inv_dnu); a.two_nu = const_ptr(a.two_nu); a.nu_c = const_ptr(a.nu_c);
+  a.xidl = const_ptr(a.xidl); a.xhm = const_ptr(a.xhm); a.xhp = const_ptr(a.xhp);
+  a.cxm = const_ptr(a.cxm); a.cxp = const_ptr(a.cxp); a.chp = const_ptr(a.chp);
+  a.yidl = const_ptr(a.yidl); a.yhm = const_ptr(a.yhm); a.yhp = const_ptr(a.yhp);
+  a.cy = const_ptr(a.cy);
+  return a;
+}
+
 // ---------------------------------------------------------------------------
 // Levermore closure in cancellation-free form.  With f = |F|/E and
 // s = sqrt(4 - 3 f^2):  (1 - chi)/2 = (1 - f^2)/(1 + s) = (s - 1)/3 (since

@@ -388,7 +388,10 @@ void k_advect_source(GridArgs<R> a) {
 }
 
 // Batched, persistent advection: blocks walk the work items (grid, tile x
-// run of bins) of every grid of a batch in a fixed order.  off[g] is the
+// run of bins) of every grid of a batch in a fixed order, strided by the grid
+// size from their XCD-ordered index, so that the blocks of one XCD work on
+// one contiguous range of tiles at a time and share its halo lines in their
+// L2.  off[g] is the
 // first work item of grid g (off[n] = total); args holds both ping-pong
 // directions, [2][n]; grid g uses direction par[g] ^ sp.
 template <typename R, int BK>
@@ -398,13 +401,13 @@ void k_advect_batched(const GridArgs<R>* __restrict__ args,
                                                         int sp, const int* __restrict__ off) {
   __shared__ AdvShared<R> S;
   const int total = off[n];
-  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+  for (int w = (int)xcd_logical_block(); w < total; w += gridDim.x) {
     int lo = 0, hi = n;
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
       if (off[mid] <= w) lo = mid; else hi = mid;
     }
-    const GridArgs<R>& a = args[((par[lo] ^ sp) & 1) * n + lo];
+    const GridArgs<R> a = global_args(args[((par[lo] ^ sp) & 1) * n + lo]);
     WriteSink<R> sink;
     advect_block<R, BK>(a, (unsigned)(w - off[lo]), S, sink);
   }
@@ -668,7 +671,7 @@ void k_freq_batched(const GridArgs<R>* __restrict__ args,
       const int mid = (lo + hi) >> 1;
       if (off[mid] <= w) lo = mid; else hi = mid;
     }
-    const GridArgs<R>& a = args[((par[lo] ^ sp) & 1) * n + lo];
+    const GridArgs<R> a = global_args(args[((par[lo] ^ sp) & 1) * n + lo]);
     const size_t c = (size_t)(w - off[lo]) * 256 + threadIdx.x;
     if (c < (size_t)a.nx * a.ny) freq_dispatch<R, P>(a, c);
   }
@@ -783,13 +786,13 @@ void k_step_fused_batched(const GridArgs<float>* __restrict__ args,
                                                             int sp, const int* __restrict__ off) {
   __shared__ AdvShared<float> S;
   const int total = off[n];
-  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+  for (int w = (int)xcd_logical_block(); w < total; w += gridDim.x) {
     int lo = 0, hi = n;
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
       if (off[mid] <= w) lo = mid; else hi = mid;
     }
-    const GridArgs<float>& a = args[((par[lo] ^ sp) & 1) * n + lo];
+    const GridArgs<float> a = global_args(args[((par[lo] ^ sp) & 1) * n + lo]);
     FusedSink sink;
     advect_block<float, 0>(a, (unsigned)(w - off[lo]), S, sink);
   }
