@@ -159,6 +159,7 @@ class OracleSetup:
         self.bc = [BC_CODE[b] for b in p["bc"]]
         self.recoil = int(p.get("recoil", 1))
         self.doppler = int(p.get("doppler", 1))
+        self.active_frac = float(p.get("active_frac", 0.0))
 
 
 # ------------------------------------------------------------- the C core
@@ -169,7 +170,8 @@ class _Prob(ctypes.Structure):
                  ("c_tilde", ctypes.c_double), ("dt", ctypes.c_double)]
                 + [(n, ctypes.c_void_p) for n in
                    ("xe", "ye", "nu_c", "dnu", "alpha", "acabs", "acF", "pd", "ux",
-                    "uy", "dnuD", "hkT", "emis", "cls", "hbar", "phi")])
+                    "uy", "dnuD", "hkT", "emis", "cls", "hbar", "phi")]
+                + [("active_frac", ctypes.c_double), ("active", ctypes.c_void_p)])
 
 
 def build(force=False):
@@ -236,6 +238,9 @@ class Oracle:
             a = np.ascontiguousarray(arr)
             self._keep.append(a)
             setattr(P, name, a.ctypes.data)
+        P.active_frac = s.active_frac
+        self.active = np.ones(s.nb, dtype=np.int32)   # bins advected by the last step
+        P.active = self.active.ctypes.data
         self.P = P
 
     @property

@@ -16,6 +16,9 @@
  * Layout of every per-bin array: [k][j][i], cell index c = j*nx + i.
  *
  * One call of oracle_step() advances n -> n+1:
+ *   (0) optional active-bin selection (Section 2.1, runtime controls): with
+ *       active_frac > 0 only bins holding more than that fraction of the
+ *       total Lyman-alpha energy in the volume are advected in (1);
  *   (1) advection step per bin (Section 2.1, step 1): MinMod-limited linear
  *       reconstruction of E and f = F/E, Levermore closure, GLF flux blended
  *       with the diffusion flux by epsilon(tau), upwind velocity advection,
@@ -55,6 +58,10 @@ typedef struct {
   const int *cls;            /* temperature class of the cell [ncell] */
   const double *hbar;        /* bin-averaged Voigt <H>_k per class [ncls][nb] */
   const double *phi;         /* bin-averaged emission profile per class [ncls][nb] */
+  double active_frac;        /* 0: advect every bin; > 0: only bins whose energy
+                                exceeds this fraction of the total (Section 2.1,
+                                runtime controls) */
+  int *active;               /* [nb] out: 1 where bin k was advected this step */
 } OracleProblem;
 
 /* ------------------------------------------------------------------------ */
@@ -339,13 +346,31 @@ static void build_velocity(const OracleProblem *P, VelData *V) {
 
 static void free_velocity(VelData *V) { free(V->unx); free(V->uny); free(V->grad); }
 
+/* Advection (when `advect`) and emission/absorption of bin k.  A bin that is
+ * not advected keeps its state through step (1): no fluxes, no work or hoop
+ * term, no clamp (the state is causal already); step (2) acts as usual. */
 static void advect_source_bin(const OracleProblem *P, const Geometry *G,
-                              const VelData *V, int k,
+                              const VelData *V, int k, int advect,
                               const double *E, const double *Fx, const double *Fy,
                               double *Eo, double *Fxo, double *Fyo, PadBin *B,
                               Flux3 *fxf, Flux3 *fyf) {
   int nx = P->nx, ny = P->ny, px = nx + 4;
   size_t nc = (size_t)nx * ny;
+  double ctdt = P->c_tilde * P->dt;
+  if (!advect) {
+    for (size_t c = 0; c < nc; ++c) {
+      size_t ck = (size_t)k * nc + c;
+      double h = P->hbar[(size_t)P->cls[c] * P->nb + k];
+      double aH = P->alpha[c] * h;
+      double kE = P->acabs[c] + P->pd[c] * aH;
+      double aF = aH + P->acF[c];
+      double src = P->emis[c] * P->phi[(size_t)P->cls[c] * P->nb + k] / C_LIGHT;
+      Eo[ck] = (E[ck] + ctdt * src) / (1.0 + ctdt * kE);
+      Fxo[ck] = Fx[ck] / (1.0 + ctdt * aF);
+      Fyo[ck] = Fy[ck] / (1.0 + ctdt * aF);
+    }
+    return;
+  }
   fill_padded_bin(P, k, E, Fx, Fy, B);
   /* x-faces: iface = 0..nx between cells iface-1 and iface */
   for (int j = 0; j < ny; ++j)
@@ -365,7 +390,6 @@ static void advect_source_bin(const OracleProblem *P, const Geometry *G,
       fyf[(size_t)f * nx + i] =
           face_flux(B, G->ycp, P->ye[f], qL - px, qL, qR, qR + px, jL, jR, 1, un);
     }
-  double ctdt = P->c_tilde * P->dt;
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
       size_t c = (size_t)j * nx + i, ck = (size_t)k * nc + c;
@@ -495,6 +519,28 @@ static void frequency_step_cell(const OracleProblem *P, const VelData *V, int i,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Active bins (Section 2.1, runtime controls): the energy of bin k in the
+ * volume is W_k = dnu_k sum_cells dV E_k (E = 4 pi J / c; constant factors
+ * cancel in the ratio), and bin k is advected when W_k > active_frac sum_k W_k.
+ * An empty state advects no bin. */
+static void select_active_bins(const OracleProblem *P, const double *E, int *active) {
+  int nx = P->nx, ny = P->ny, nb = P->nb;
+  size_t nc = (size_t)nx * ny;
+  double *W = (double *)malloc(sizeof(double) * nb);
+  double total = 0.0;
+  for (int k = 0; k < nb; ++k) {
+    double s = 0.0;
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i)
+        s += cell_volume(P, i, j) * E[(size_t)k * nc + (size_t)j * nx + i];
+    W[k] = P->dnu[k] * s;
+    total += W[k];
+  }
+  for (int k = 0; k < nb; ++k) active[k] = W[k] > P->active_frac * total;
+  free(W);
+}
+
+/* ------------------------------------------------------------------------ */
 /* One full RT step.  E, Fx, Fy: state in/out [nb][ncell].
  * force: [4][ncell] = (f_x, f_y, f_x gas part, f_y gas part) of this step.
  * Ess, Xss, Yss: caller scratch of the state size (post-source state). */
@@ -507,6 +553,10 @@ int oracle_step(const OracleProblem *P, double *E, double *Fx, double *Fy,
   VelData V;
   build_velocity(P, &V);
   size_t npad = (size_t)(nx + 4) * (ny + 4);
+  int *active = (int *)malloc(sizeof(int) * nb);
+  if (P->active_frac > 0.0) select_active_bins(P, E, active);
+  else for (int k = 0; k < nb; ++k) active[k] = 1;
+  if (P->active) memcpy(P->active, active, sizeof(int) * nb);
   /* (1)+(2): advection and emission/absorption, bins independent */
 #pragma omp parallel
   {
@@ -520,7 +570,7 @@ int oracle_step(const OracleProblem *P, double *E, double *Fx, double *Fy,
     Flux3 *fyf = (Flux3 *)malloc(sizeof(Flux3) * (size_t)nx * (ny + 1));
 #pragma omp for schedule(dynamic, 1)
     for (int k = 0; k < nb; ++k)
-      advect_source_bin(P, &G, &V, k, E, Fx, Fy, Ess, Xss, Yss, &B, fxf, fyf);
+      advect_source_bin(P, &G, &V, k, active[k], E, Fx, Fy, Ess, Xss, Yss, &B, fxf, fyf);
     free(B.E); free(B.fx); free(B.fy); free(B.aF); free(fxf); free(fyf);
   }
   /* (3) radiation force density, f = sum_k dnu_k alpha_F,k F**_k */
@@ -554,6 +604,7 @@ int oracle_step(const OracleProblem *P, double *E, double *Fx, double *Fy,
                           K, Cc, gl, gr, cp, dp);
     free(K); free(Cc); free(gl); free(gr); free(cp); free(dp);
   }
+  free(active);
   free_geometry(&G);
   free_velocity(&V);
   return 0;

@@ -705,3 +705,97 @@ def test_transport_stage_matches_brute_force_on_8x8(geom, bc):
     Eb, Xb, Yb = _brute_force_transport(p, o, E0, X0, Y0)
     for a, b in ((Ess, Eb), (Xss, Xb), (Yss, Yb)):
         assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b)), np.max(np.abs(a - b))
+
+
+# ------------------------------------------- active bins (runtime controls)
+def _active_after_one_step(p, E, Fx=None, Fy=None):
+    o = M.Oracle(p)
+    z = np.zeros_like(E)
+    o.set_state(E, z if Fx is None else Fx, z if Fy is None else Fy)
+    o.step(1)
+    return o
+
+
+def test_active_bins_shares_of_uniform_state():
+    """Spatially uniform E_k = a_k: bin k's share of the energy is
+    a_k dnu_k / sum_j a_j dnu_j whatever the geometry, so the advected set is
+    fixed in closed form by the bin widths (Section 2.1, runtime controls)."""
+    for geom, bc in (("cart", ("vacuum",) * 4), ("cyl", ("reflect", "vacuum", "vacuum", "vacuum"))):
+        p = make_problem(geom, 6, 5, 1.0e15, bc, half_width=2.0e2)
+        nb = M.frequency_grid(half_width=2.0e2)["nb"]
+        dnu = M.frequency_grid(half_width=2.0e2)["dnu"]
+        a = 10.0 ** (-0.5 * np.arange(nb))
+        share = a * dnu / np.sum(a * dnu)
+        # a threshold in the widest gap between consecutive shares (well away
+        # from every share, so rounding cannot flip a bin)
+        srt = np.sort(share)
+        g = int(np.argmax(np.log(srt[1:] / srt[:-1])))
+        thr = math.sqrt(srt[g] * srt[g + 1])
+        p["active_frac"] = thr
+        E = np.broadcast_to(a[:, None, None], (nb, 5, 6)).copy()
+        o = _active_after_one_step(p, E)
+        assert np.array_equal(o.active.astype(bool), share > thr), (geom, thr)
+        assert 0 < int(o.active.sum()) < nb
+
+
+def test_active_bins_weight_cells_by_volume_in_cylinder():
+    """Bin 0 only in the axis cell (dV = pi dR^2 dz), bin 1 only in the
+    outermost cell (dV = pi (2n - 1) dR^2 dz), values chosen so that bin 1
+    holds 0.6 of the energy: at a threshold of 0.5 only bin 1 is advected.
+    Weighting cells by dR dz instead would make bin 0 dominant."""
+    n = 6
+    p = make_problem("cyl", n, 4, 1.0e15, ("reflect", "vacuum", "vacuum", "vacuum"),
+                     half_width=2.0e2)
+    g = M.frequency_grid(half_width=2.0e2)
+    nb, dnu = g["nb"], g["dnu"]
+    k0, k1 = nb // 2 - 1, nb // 2 + 3
+    E = np.zeros((nb, 4, n))
+    E[k0, 2, 0] = 1.0 / dnu[k0]
+    E[k1, 2, n - 1] = 1.5 / ((2 * n - 1) * dnu[k1])
+    p["active_frac"] = 0.5
+    o = _active_after_one_step(p, E)
+    assert list(np.nonzero(o.active)[0]) == [k1]
+    p["active_frac"] = 0.3
+    o = _active_after_one_step(p, E)
+    assert list(np.nonzero(o.active)[0]) == [k0, k1]
+
+
+def test_inactive_bins_do_not_move():
+    """No opacity, no emission, no velocity: the source step is the identity
+    and the frequency step has nothing to redistribute.  With every bin
+    inactive (threshold above any share) the state is exactly unchanged; with
+    advection on, the pulse spreads to the neighbours."""
+    p = make_problem("cart", 7, 7, 1.0e15, ("vacuum",) * 4, half_width=2.0e2, recoil=0)
+    nb = M.frequency_grid(half_width=2.0e2)["nb"]
+    E = np.zeros((nb, 7, 7))
+    E[nb // 2, 3, 3] = 2.0
+    Fx = np.zeros_like(E)
+    Fx[nb // 2, 3, 3] = 1.0
+    p["active_frac"] = 1.5
+    o = _active_after_one_step(p, E, Fx)
+    assert o.active.sum() == 0
+    assert np.array_equal(o.E, E) and np.array_equal(o.Fx, Fx) and not o.Fy.any()
+    p["active_frac"] = 0.0
+    o = _active_after_one_step(p, E, Fx)
+    assert o.active.all()
+    assert o.E[nb // 2, 3, 4] > 0 and o.E[nb // 2, 3, 3] < 2.0
+
+
+def test_only_empty_bins_inactive_is_full_advection():
+    """A threshold below every nonzero share leaves inactive only bins that
+    are zero in every cell, whose advection is exactly zero: the step equals
+    the step with every bin advected, bit for bit."""
+    p = inputs.random_small("cyl", 9, 8, seed=7, half_width=3.0e2)
+    nb = M.frequency_grid(half_width=3.0e2)["nb"]
+    rng = np.random.default_rng(5)
+    E = rng.uniform(0.5, 1.0, size=(nb, 8, 9))
+    E[::3] = 0.0                                   # every third bin empty
+    Fx = 0.3 * E * rng.uniform(-1, 1, size=E.shape)
+    Fy = 0.3 * E * rng.uniform(-1, 1, size=E.shape)
+    p["active_frac"] = 1e-300
+    a = _active_after_one_step(p, E, Fx, Fy)
+    assert np.array_equal(a.active.astype(bool), np.arange(nb) % 3 != 0)
+    p["active_frac"] = 0.0
+    b = _active_after_one_step(p, E, Fx, Fy)
+    for x, y in ((a.E, b.E), (a.Fx, b.Fx), (a.Fy, b.Fy), (a.force, b.force)):
+        assert np.array_equal(x, y)
