@@ -172,6 +172,44 @@ def run_batch(ps, steps, warmup):
     return out
 
 
+def run_active(ps, steps, warmup, thr=1e-10):
+    """Active-bin advection (the paper's threshold, 1e-10 of the total energy)
+    on the 64-grid batch in FP32, after `warmup` steps beyond the tuning; the
+    rate counts every cell and bin (inactive bins still take the emission/
+    absorption and frequency steps).  Also the fraction of cell-bins in
+    advected bins at the end, and one 512x1024 grid with the threshold."""
+    import torch
+    from paper_2606_02711_amd import inputs, m1
+    log(f"[bench] active bins: {len(ps)} grids, threshold {thr}")
+    stream = torch.cuda.Stream()
+    gs = [m1.M1Grid(dict(p, active_frac=thr), prec="fp32", stream=stream) for p in ps]
+    cell_bins = sum(g.ncell * g.nb for g in gs)
+    b = m1.M1Batch(gs, use_graph=True)
+    b.step(5 * 3 + warmup)
+    stream.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    stream.synchronize()
+    wall = time.perf_counter() - t0
+    adv = sum(int(g.active_bins().sum()) * g.ncell for g in gs)
+    out = {"batch_fp32": cell_bins * steps / wall, "advected_fraction": adv / cell_bins,
+           "tile_bins": b.info()[0], "steps": steps, "warmup": warmup + 15}
+    b.free()
+    for g in gs:
+        g.free()
+    del gs
+    torch.cuda.empty_cache()
+    log("[bench] active bins: 512x1024 grid")
+    g = m1.M1Grid(dict(inputs.config2(), active_frac=thr), prec="fp32")
+    g.step(warmup)
+    a, c = g.step_profiled(steps)
+    out["config2_fp32_ms_per_step"] = (a + c) / steps
+    out["config2_advected_bins"] = int(g.active_bins().sum())
+    g.free()
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_large(steps, warmup):
     """4096 x 8192 cylindrical cloud in FP32, the force density copied out
     (to device arrays) after every step."""
@@ -257,6 +295,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=500,
                     help="steps of the 64-grid batch workload (0 skips it)")
+    ap.add_argument("--active-steps", type=int, default=200,
+                    help="timed steps of the active-bin workload (0 skips it)")
     ap.add_argument("--large-steps", type=int, default=20,
                     help="timed steps of the 4096 x 8192 grid (0 skips it)")
     ap.add_argument("--serve-seconds", type=float, default=30.0,
@@ -270,6 +310,8 @@ def main():
     ap.add_argument("--serve-drain", type=float, default=30.0,
                     help="seconds after the stream ends before the backlog is counted")
     ap.add_argument("--serve-only", action="store_true")
+    ap.add_argument("--active-only", action="store_true",
+                    help="run only the active-bin workload")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the 64-grid batch workload (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -301,6 +343,10 @@ def main():
     if args.batch_only:
         rb = run_batch(inputs.config3(), args.batch_steps, args.warmup)
         print(json.dumps({"batch_64_grids": rb}), flush=True)
+        return
+    if args.active_only:
+        print(json.dumps({"active_bins": run_active(inputs.config3(), args.active_steps, 100)}),
+              flush=True)
         return
     copy_gbs = copy_bandwidth()
     log(f"[bench] device copy: {copy_gbs:.0f} GB/s")
@@ -375,6 +421,8 @@ def main():
             "fp64_loop": rb["fp64_loop"], "unit": "cell-bin updates/s",
             "batched_vs_fp64_loop": rb["fp32_batched"] / rb["fp64_loop"],
             "tile_bins": rb["tile_bins"], "tuning_ms_per_step": rb["tuning_ms_per_step"]}
+    if args.active_steps > 0:
+        out["active_bins"] = run_active(inputs.config3(), args.active_steps, 100)
     if args.large_steps > 0:
         out["large_grid"] = run_large(args.large_steps, 2)
     if args.serve_seconds > 0:

@@ -86,6 +86,19 @@ typedef struct {
                               which a cell's frequency-step coefficients are
                               computed in double (+inf: none, the default;
                               0: all cells) */
+  double active_frac;      /* active-bin advection (Section 2.1, runtime
+                              controls; the paper uses 1e-10): at the start of
+                              every step bin k's energy in the volume,
+                              W_k = dnu_k sum_cells dV E_k, is summed in double,
+                              and only bins with W_k > active_frac sum_k W_k
+                              are advected; the others keep their state
+                              through the transport step, while emission/
+                              absorption and the frequency step act on every
+                              bin.  0 (the default): every bin is advected.
+                              Must be >= 0.  Results then depend on the
+                              selection, which is taken on the state in its
+                              storage precision (FP32 and FP64 paths can differ
+                              for a bin whose share sits at the threshold). */
 } m1_config;
 
 /* Per-cell physical inputs, FP64, [ny][nx].  Host pointers when on_device is
@@ -170,6 +183,13 @@ int32_t m1_set_state(m1_handle *h, const double *d_E, const double *d_Fx,
  * fit beside the workspace.  Blocking. */
 int32_t m1_get_state_region(m1_handle *h, int32_t i0, int32_t i1, int32_t j0, int32_t j1,
                             double *d_E, double *d_Fx, double *d_Fy);
+
+/* Which bins the last step advected (Section 2.1, runtime controls):
+ * flags_host[k] = 1 for an advected bin, 0 otherwise (N_nu int32 entries;
+ * may be NULL), *n_active (may be NULL) their count.  With active_frac = 0
+ * every bin is reported active; before the first step, none is.  Blocking
+ * (waits for the handle's stream). */
+int32_t m1_active_bins(m1_handle *h, int32_t *flags_host, int32_t *n_active);
 
 /* Scalars of a handle: dt [s], N_nu, precision, cells, internal scale 2^e. */
 int32_t m1_get_info(const m1_handle *h, double *dt, int32_t *n_nu, int32_t *prec,

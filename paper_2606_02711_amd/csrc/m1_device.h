@@ -56,6 +56,8 @@ struct GridArgs {
   // frequency step
   ZW<R> *zw;              // scratch [nb][ncell]
   double *force;          // [4][ncell]
+  // active bins: flags [nb] of the bins this step advects (nullptr: all)
+  const int32_t *active;
 };
 
 // Address-space hints for pointers read from a descriptor table in memory
@@ -102,6 +104,7 @@ __device__ __forceinline__ GridArgs<R> global_args(const GridArgs<R>& s) {
   a.cxm = const_ptr(a.cxm); a.cxp = const_ptr(a.cxp); a.chp = const_ptr(a.chp);
   a.yidl = const_ptr(a.yidl); a.yhm = const_ptr(a.yhm); a.yhp = const_ptr(a.yhp);
   a.cy = const_ptr(a.cy);
+  a.active = const_ptr(a.active);
   return a;
 }
 

@@ -99,11 +99,13 @@ struct Layout {
   size_t hbar, phi, dD2h, hkT;
   size_t dnu, inv_dnu, two_nu, nu_c, edges;
   size_t geo, xe, ye, nodes;
+  size_t wx, wy, binpart, active;   // active bins: volume weights, partial sums, flags
   size_t partial, result;
   size_t total;
 };
 
 constexpr int kResBlocks = 1024;
+constexpr int kMaxActiveBins = 8192;    // the selection keeps W_k in LDS (64 KB)
 
 // Device bytes the set-up needs for temporaries: the input fields (when they
 // come from the host), class sums and tables, face velocities in double.
@@ -150,6 +152,10 @@ Layout make_layout(int nx, int ny, int nb, int64_t ncls, size_t rs) {
   L.geo = take((size_t)(3 * (nx + 4) + 3 * nx + 3 * (ny + 4) + ny) * rs);
   L.xe = take((nx + 1) * sizeof(double));
   L.ye = take((ny + 1) * sizeof(double));
+  L.wx = take(nx * sizeof(double));
+  L.wy = take(ny * sizeof(double));
+  L.binpart = take((size_t)nb * energy_chunks(nc) * sizeof(double));
+  L.active = take(nb * sizeof(int32_t));
   L.nodes = take(kDawsonNodes * sizeof(double));
   L.partial = take(3 * kResBlocks * sizeof(double));
   L.result = take(2 * sizeof(double));
@@ -178,9 +184,13 @@ int validate_config(const m1_config* c, int* nb_out) {
   if ((int64_t)c->nx * c->ny > (int64_t(1) << 29))
     return fail(M1_EUNSUPPORTED, "more than 2^29 cells in one grid");
   if (isnan(c->fp64_tau)) return fail(M1_EINVAL, "fp64_tau is NaN");
+  if (!(c->active_frac >= 0.0) || !isfinite(c->active_frac))
+    return fail(M1_EINVAL, "active_frac must be finite and >= 0");
   FreqGrid g;
   int st = build_grid(*c, g);
   if (st) return st;
+  if (c->active_frac > 0.0 && g.nb > kMaxActiveBins)
+    return fail(M1_EUNSUPPORTED, "active-bin selection supports at most %d bins", kMaxActiveBins);
   if (nb_out) *nb_out = g.nb;
   return M1_OK;
 }
@@ -259,6 +269,7 @@ void fill_args(m1_handle* h, GridArgs<R>* a) {
     g.cy = g.yhp + (ny + 4);
     g.zw = (ZW<R>*)(w + L.zw);
     g.force = (double*)(w + L.force);
+    g.active = c.active_frac > 0.0 ? (const int32_t*)(w + L.active) : nullptr;
   }
 }
 
@@ -443,6 +454,15 @@ int init_typed(m1_handle* h, const m1_fields* f, const std::vector<std::vector<d
   HIPCHK(hipMemcpyAsync(w + L.geo, geo.data(), geo.size() * sizeof(R), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(w + L.xe, xe.data(), xe.size() * sizeof(double), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(w + L.ye, ye.data(), ye.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  // cell volumes dV = wx[i] wy[j] (cylindrical: pi (R+^2 - R-^2) dz; slab:
+  // unit depth) for the active-bin energies; no bin is flagged before a step
+  std::vector<double> wxv(nx), wyv(ny);
+  for (int i = 0; i < nx; ++i)
+    wxv[i] = c.geom == M1_CYL_RZ ? kPi * (xe[i + 1] * xe[i + 1] - xe[i] * xe[i]) : xe[i + 1] - xe[i];
+  for (int j = 0; j < ny; ++j) wyv[j] = ye[j + 1] - ye[j];
+  HIPCHK(hipMemcpyAsync(w + L.wx, wxv.data(), nx * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(w + L.wy, wyv.data(), ny * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(w + L.active, 0, nb * sizeof(int32_t), s));
 
   // bin-averaged Voigt profile and emission profile per class
   HIPCHK(launch_class_profiles<R>(d_dD, d_av, ncls, (const double*)(w + L.edges),
@@ -598,6 +618,21 @@ int32_t m1_init(const m1_config* cfg, const m1_fields* f, void* d_ws, size_t ws_
   return M1_OK;
 }
 
+int32_t m1_active_bins(m1_handle* h, int32_t* flags_host, int32_t* n_active) {
+  if (!h) return fail(M1_EINVAL, "handle is NULL");
+  std::vector<int32_t> f(h->nb, 1);
+  if (h->cfg.active_frac > 0.0) {
+    HIPCHK(hipMemcpyAsync(f.data(), h->ws + h->L.active, h->nb * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  int32_t cnt = 0;
+  for (int k = 0; k < h->nb; ++k) cnt += f[k] != 0;
+  if (flags_host) memcpy(flags_host, f.data(), h->nb * sizeof(int32_t));
+  if (n_active) *n_active = cnt;
+  return M1_OK;
+}
+
 int32_t m1_get_info(const m1_handle* h, double* dt, int32_t* n_nu, int32_t* prec, int64_t* ncell,
                     int32_t* scale_exp2) {
   if (!h) return fail(M1_EINVAL, "handle is NULL");
@@ -609,9 +644,30 @@ int32_t m1_get_info(const m1_handle* h, double* dt, int32_t* n_nu, int32_t* prec
   return M1_OK;
 }
 
+// Active-bin flags of the state in buffer `dir` (nothing when every bin is
+// advected).
+static hipError_t launch_selection(m1_handle* h, int dir, hipStream_t s) {
+  if (!(h->cfg.active_frac > 0.0)) return hipSuccess;
+  const Layout& L = h->L;
+  char* w = h->ws;
+  const double* wx = (const double*)(w + L.wx);
+  const double* wy = (const double*)(w + L.wy);
+  const double* dnu = (const double*)(w + L.dnu);
+  double* part = (double*)(w + L.binpart);
+  int32_t* act = (int32_t*)(w + L.active);
+  const int nx = h->cfg.nx, ny = h->cfg.ny;
+  return h->cfg.prec == M1_FP32
+             ? launch_active_bins<float>((const float*)(w + L.state[dir][0]), nx, ny, h->nb, wx,
+                                         wy, dnu, h->cfg.active_frac, part, act, s)
+             : launch_active_bins<double>((const double*)(w + L.state[dir][0]), nx, ny, h->nb, wx,
+                                          wy, dnu, h->cfg.active_frac, part, act, s);
+}
+
 static int enqueue_step(m1_handle* h, hipStream_t s) {
-  hipError_t e = h->cfg.prec == M1_FP32 ? launch_step<float>(h->af[h->cur], s)
-                                        : launch_step<double>(h->ad[h->cur], s);
+  hipError_t e = launch_selection(h, h->cur, s);
+  if (e == hipSuccess)
+    e = h->cfg.prec == M1_FP32 ? launch_step<float>(h->af[h->cur], s)
+                               : launch_step<double>(h->ad[h->cur], s);
   if (e != hipSuccess) {
     h->broken = true;
     return fail(M1_EDEVICE, "step launch failed: %s", hipGetErrorString(e));
@@ -643,8 +699,10 @@ int32_t m1_step_profiled(m1_handle* h, int32_t nsteps, double* ms) {
   int st = M1_OK;
   HIPCHK(hipEventRecord(ev[0], h->stream));
   for (int n = 0; n < nsteps && !st; ++n) {
-    hipError_t e = h->cfg.prec == M1_FP32 ? launch_advect<float>(h->af[h->cur], h->stream)
-                                          : launch_advect<double>(h->ad[h->cur], h->stream);
+    hipError_t e = launch_selection(h, h->cur, h->stream);
+    if (e == hipSuccess)
+      e = h->cfg.prec == M1_FP32 ? launch_advect<float>(h->af[h->cur], h->stream)
+                                 : launch_advect<double>(h->ad[h->cur], h->stream);
     if (e == hipSuccess) e = hipEventRecord(ev[2 * n + 1], h->stream);
     if (e == hipSuccess)
       e = h->cfg.prec == M1_FP32 ? launch_freq<float>(h->af[h->cur], h->stream)
@@ -686,6 +744,7 @@ struct m1_batch {
   int blocks_adv[kNumBatchVariants] = {};
   int blocks_freq = 0;
   int islands = 0;                      // some member may have island cells
+  int active = 0;                       // some member selects active bins
   bool fused_ok = false;                // the fused variant applies (float, no islands)
   int variant = -1;                     // chosen tile variant (-1: tuning)
   int trial_variant = 0, trial_step = 0;
@@ -757,8 +816,12 @@ hipError_t batch_launch_step(m1_batch* b, int variant) {
   const int* par = (const int*)(b->ws + b->par_off);
   const int* offa = (const int*)(b->ws + b->offa_off) + (size_t)variant * (b->n + 1);
   const int* offf = (const int*)(b->ws + b->offf_off);
-  hipError_t e = launch_advect_batched<R>(variant, args, par, b->n, b->sp, offa,
-                                          b->blocks_adv[variant], b->stream);
+  hipError_t e = hipSuccess;
+  for (int q = 0; q < b->n && e == hipSuccess; ++q)
+    e = launch_selection(b->hs[q], (b->par[q] ^ b->sp) & 1, b->stream);
+  if (e == hipSuccess)
+    e = launch_advect_batched<R>(variant, args, par, b->n, b->sp, offa, b->blocks_adv[variant],
+                                 b->active, b->stream);
   if (e != hipSuccess || variant == kFusedVariant) return e;   // fused: no separate freq kernel
   return launch_freq_batched<R>(args, par, b->n, b->sp, offf, b->blocks_freq, b->islands,
                                 b->stream);
@@ -824,8 +887,11 @@ int32_t m1_batch_init(m1_handle* const* hs, int32_t n, void* d_ws, size_t ws_byt
   (void)hipGetDevice(&dev);
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
     ncu = 256;
+  for (int q = 0; q < n; ++q)
+    if (hs[q]->cfg.active_frac > 0.0) b->active = 1;
   for (int v = 0; v < kNumBatchVariants; ++v) {
-    int occ = b->prec == M1_FP32 ? batched_occupancy<float>(v) : batched_occupancy<double>(v);
+    int occ = b->prec == M1_FP32 ? batched_occupancy<float>(v, b->active)
+                                 : batched_occupancy<double>(v, b->active);
     b->blocks_adv[v] = (int)std::min<int64_t>(tot[v], (int64_t)ncu * occ);
   }
   int occf = b->prec == M1_FP32 ? freq_batched_occupancy<float>() : freq_batched_occupancy<double>();

@@ -28,14 +28,22 @@ int advect_blocks(int nx, int ny, int nb, int bk);
 int freq_blocks(int nx, int ny);
 template <typename R>
 hipError_t launch_advect_batched(int variant, const GridArgs<R>* args, const int* par, int n,
-                                 int sp, const int* off, int nblocks, hipStream_t s);
+                                 int sp, const int* off, int nblocks, int active, hipStream_t s);
 template <typename R>
 hipError_t launch_freq_batched(const GridArgs<R>* args, const int* par, int n, int sp,
                                const int* off, int nblocks, int islands, hipStream_t s);
 template <typename R>
-int batched_occupancy(int variant);
+int batched_occupancy(int variant, int active);
 template <typename R>
 int freq_batched_occupancy();
+
+// Active bins of a state E [nb][ny][nx]: per-bin energies with cell volumes
+// wx[i] wy[j] into part [nb][energy_chunks], then flags active[k].
+int energy_chunks(size_t nc);
+template <typename R>
+hipError_t launch_active_bins(const R* E, int nx, int ny, int nb, const double* wx,
+                              const double* wy, const double* dnu, double frac, double* part,
+                              int32_t* active, hipStream_t s);
 
 template <typename R>
 hipError_t launch_residual(const R* E0, const R* E1, size_t n, double* partial, int nblk,

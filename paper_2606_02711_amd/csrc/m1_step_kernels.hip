@@ -197,7 +197,9 @@ struct WriteSink {
 };
 
 // One tile x run of bins (logical block L of grid a); BK = 0: all bins.
-template <typename R, int BK, class Sink>
+// AB: the grid selects active bins (a.active); a separate instantiation, so
+// that grids advecting every bin keep the registers of the plain loop.
+template <typename R, int BK, bool AB, class Sink>
 __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigned L,
                                              AdvShared<R>& S, Sink& sink) {
   const int nx = a.nx, ny = a.ny, nb = a.nb;
@@ -308,6 +310,25 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
     const R* Ek = a.E + koff;
     const R* Xk = a.fx + koff;
     const R* Yk = a.fy + koff;
+    if (AB && a.active != nullptr && a.active[k] == 0) {   // (batches mix grids)
+      // a bin not advected this step keeps its state through the transport
+      // step (the state is causal already); emission/absorption as below
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        if (!own[m]) continue;
+        const size_t c = cidx[m];
+        const R EC = Ek[c], fxc = Xk[c], fyc = Yk[c];
+        const int cc = ccls[m];
+        const R hC = hb[(size_t)cc * nb];
+        const R aFC = a.alpha[c] * hC + a.acF[c];
+        const R src = em[m] * a.phi[(size_t)cc * nb + k];
+        const R kE = acabs[m] + pda[m] * hC;
+        const R dF = frcp(R(1) + ctdt * aFC);
+        sink.put(a, m, k, koff + c, hC, (EC + ctdt * src) * frcp(R(1) + ctdt * kE),
+                 fxc * EC * dF, fyc * EC * dF);
+      }
+      continue;
+    }
     // (1) stage E and f of the padded tile, and alpha_F of the ring
     for (int e = tid; e < kPX * kPY; e += 256) {
       const int v = S.src[e];
@@ -379,12 +400,12 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
 template <typename R>
 constexpr int kAdvectWaves = sizeof(R) == 4 ? 5 : 1;
 
-template <typename R, int BK>
+template <typename R, int BK, bool AB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kAdvectWaves<R>)))
 void k_advect_source(GridArgs<R> a) {
   __shared__ AdvShared<R> S;
   WriteSink<R> sink;
-  advect_block<R, BK>(a, xcd_logical_block(), S, sink);
+  advect_block<R, BK, AB>(a, xcd_logical_block(), S, sink);
 }
 
 // Batched, persistent advection: blocks walk the work items (grid, tile x
@@ -394,7 +415,7 @@ void k_advect_source(GridArgs<R> a) {
 // L2.  off[g] is the
 // first work item of grid g (off[n] = total); args holds both ping-pong
 // directions, [2][n]; grid g uses direction par[g] ^ sp.
-template <typename R, int BK>
+template <typename R, int BK, bool AB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kAdvectWaves<R>)))
 void k_advect_batched(const GridArgs<R>* __restrict__ args,
                                                         const int* __restrict__ par, int n,
@@ -409,7 +430,7 @@ void k_advect_batched(const GridArgs<R>* __restrict__ args,
     }
     const GridArgs<R> a = global_args(args[((par[lo] ^ sp) & 1) * n + lo]);
     WriteSink<R> sink;
-    advect_block<R, BK>(a, (unsigned)(w - off[lo]), S, sink);
+    advect_block<R, BK, AB>(a, (unsigned)(w - off[lo]), S, sink);
   }
 }
 
@@ -780,6 +801,7 @@ struct FusedSink {
 
 // Batched, persistent fused step: work item = one tile (all bins) of a grid.
 // Four waves per SIMD (128 registers).
+template <bool AB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 void k_step_fused_batched(const GridArgs<float>* __restrict__ args,
                                                             const int* __restrict__ par, int n,
@@ -794,7 +816,7 @@ void k_step_fused_batched(const GridArgs<float>* __restrict__ args,
     }
     const GridArgs<float> a = global_args(args[((par[lo] ^ sp) & 1) * n + lo]);
     FusedSink sink;
-    advect_block<float, 0>(a, (unsigned)(w - off[lo]), S, sink);
+    advect_block<float, 0, AB>(a, (unsigned)(w - off[lo]), S, sink);
   }
 }
 
@@ -891,7 +913,10 @@ template <typename R>
 hipError_t launch_advect(const GridArgs<R>& a, hipStream_t s) {
   const unsigned nbx = (a.nx + kTX - 1) / kTX, nby = (a.ny + kTY - 1) / kTY;
   const unsigned nbz = (a.nb + kBK - 1) / kBK;
-  hipLaunchKernelGGL((k_advect_source<R, kBK>), dim3(nbx * nby * nbz), dim3(256), 0, s, a);
+  if (a.active)
+    hipLaunchKernelGGL((k_advect_source<R, kBK, true>), dim3(nbx * nby * nbz), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_advect_source<R, kBK, false>), dim3(nbx * nby * nbz), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -904,6 +929,92 @@ hipError_t launch_freq(const GridArgs<R>& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------ active bins
+// Section 2.1, runtime controls: bin k is advected when its energy in the
+// volume, W_k = dnu_k sum_c dV_c E_k,c, exceeds active_frac sum_k W_k.  The
+// sums are double and deterministic: fixed partial sums of kEnergyCells
+// cells per block (k_bin_energy), then one block adds them in order and sets
+// the flags (k_bin_select).  The FP32 state carries the scale 2^e2, which
+// cancels in the ratio.
+constexpr int kEnergyCells = 8192;
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_bin_energy(const R* __restrict__ E, int nx, size_t nc,
+                                                    const double* __restrict__ wx,
+                                                    const double* __restrict__ wy,
+                                                    double* __restrict__ part, int nchunk) {
+  __shared__ double red[4];
+  const int k = blockIdx.y, q = blockIdx.x;
+  const size_t c0 = (size_t)q * kEnergyCells;
+  const size_t c1 = c0 + kEnergyCells < nc ? c0 + kEnergyCells : nc;
+  const R* Ek = E + (size_t)k * nc;
+  size_t c = c0 + threadIdx.x;
+  int j = (int)(c / (size_t)nx), i = (int)(c - (size_t)j * nx);
+  auto next = [&](int& ii, int& jj) {     // the cell 256 further on
+    ii += 256;
+    while (ii >= nx) { ii -= nx; ++jj; }
+  };
+  // four cells 256 apart per iteration: four loads in flight, four sums
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (; c + 768 < c1; c += 1024) {
+    int i1 = i, j1 = j;
+    next(i1, j1);
+    int i2 = i1, j2 = j1;
+    next(i2, j2);
+    int i3 = i2, j3 = j2;
+    next(i3, j3);
+    const double e0 = (double)Ek[c], e1 = (double)Ek[c + 256], e2 = (double)Ek[c + 512],
+                 e3 = (double)Ek[c + 768];
+    s0 += wx[i] * wy[j] * e0;
+    s1 += wx[i1] * wy[j1] * e1;
+    s2 += wx[i2] * wy[j2] * e2;
+    s3 += wx[i3] * wy[j3] * e3;
+    i = i3; j = j3;
+    next(i, j);
+  }
+  for (; c < c1; c += 256) {
+    s0 += wx[i] * wy[j] * (double)Ek[c];
+    next(i, j);
+  }
+  double s = (s0 + s1) + (s2 + s3);
+  // fixed-order reduction: within the wave, then the four waves in order
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(size_t)k * nchunk + q] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// One block; dynamic LDS of nb doubles.
+__global__ __launch_bounds__(256) void k_bin_select(const double* __restrict__ part, int nchunk,
+                                                    int nb, const double* __restrict__ dnu,
+                                                    double frac, int32_t* __restrict__ active) {
+  extern __shared__ double W[];
+  for (int k = threadIdx.x; k < nb; k += 256) {
+    double s = 0.0;
+    for (int q = 0; q < nchunk; ++q) s += part[(size_t)k * nchunk + q];
+    W[k] = dnu[k] * s;
+  }
+  __syncthreads();
+  double tot = 0.0;
+  for (int k = 0; k < nb; ++k) tot += W[k];
+  for (int k = threadIdx.x; k < nb; k += 256) active[k] = W[k] > frac * tot ? 1 : 0;
+}
+
+int energy_chunks(size_t nc) { return (int)((nc + kEnergyCells - 1) / kEnergyCells); }
+
+template <typename R>
+hipError_t launch_active_bins(const R* E, int nx, int ny, int nb, const double* wx,
+                              const double* wy, const double* dnu, double frac, double* part,
+                              int32_t* active, hipStream_t s) {
+  const size_t nc = (size_t)nx * ny;
+  const int nchunk = energy_chunks(nc);
+  hipLaunchKernelGGL((k_bin_energy<R>), dim3(nchunk, nb), dim3(256), 0, s, E, nx, nc, wx, wy,
+                     part, nchunk);
+  hipLaunchKernelGGL(k_bin_select, dim3(1), dim3(256), nb * sizeof(double), s, part, nchunk, nb,
+                     dnu, frac, active);
+  return hipGetLastError();
+}
+
 int tile_count(int nx, int ny) { return ((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY); }
 int advect_blocks(int nx, int ny, int nb, int bk) {
   return tile_count(nx, ny) * (bk > 0 ? (nb + bk - 1) / bk : 1);
@@ -913,24 +1024,31 @@ int freq_blocks(int nx, int ny) { return (int)(((size_t)nx * ny + 255) / 256); }
 
 const int kBatchBK[kNumBatchVariants] = {7, 14, 28, 49, -1};
 
-template <typename R>
-hipError_t launch_advect_batched(int variant, const GridArgs<R>* args, const int* par, int n,
-                                 int sp, const int* off, int nblocks, hipStream_t s) {
+template <typename R, bool AB>
+hipError_t launch_advect_batched_ab(int variant, const GridArgs<R>* args, const int* par, int n,
+                                    int sp, const int* off, int nblocks, hipStream_t s) {
   dim3 g(nblocks), b(256);
   switch (variant) {
-    case 0: hipLaunchKernelGGL((k_advect_batched<R, 7>), g, b, 0, s, args, par, n, sp, off); break;
-    case 1: hipLaunchKernelGGL((k_advect_batched<R, 14>), g, b, 0, s, args, par, n, sp, off); break;
-    case 2: hipLaunchKernelGGL((k_advect_batched<R, 28>), g, b, 0, s, args, par, n, sp, off); break;
-    case 3: hipLaunchKernelGGL((k_advect_batched<R, 49>), g, b, 0, s, args, par, n, sp, off); break;
+    case 0: hipLaunchKernelGGL((k_advect_batched<R, 7, AB>), g, b, 0, s, args, par, n, sp, off); break;
+    case 1: hipLaunchKernelGGL((k_advect_batched<R, 14, AB>), g, b, 0, s, args, par, n, sp, off); break;
+    case 2: hipLaunchKernelGGL((k_advect_batched<R, 28, AB>), g, b, 0, s, args, par, n, sp, off); break;
+    case 3: hipLaunchKernelGGL((k_advect_batched<R, 49, AB>), g, b, 0, s, args, par, n, sp, off); break;
     default:
       if constexpr (sizeof(R) == 4)
-        hipLaunchKernelGGL(k_step_fused_batched, g, b, 0, s, (const GridArgs<float>*)args, par, n,
-                           sp, off);
+        hipLaunchKernelGGL(k_step_fused_batched<AB>, g, b, 0, s, (const GridArgs<float>*)args, par,
+                           n, sp, off);
       else
         return hipErrorInvalidValue;              // fused: float storage only
       break;
   }
   return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_advect_batched(int variant, const GridArgs<R>* args, const int* par, int n,
+                                 int sp, const int* off, int nblocks, int active, hipStream_t s) {
+  return active ? launch_advect_batched_ab<R, true>(variant, args, par, n, sp, off, nblocks, s)
+                : launch_advect_batched_ab<R, false>(variant, args, par, n, sp, off, nblocks, s);
 }
 
 template <typename R>
@@ -942,18 +1060,23 @@ hipError_t launch_freq_batched(const GridArgs<R>* args, const int* par, int n, i
   return hipGetLastError();
 }
 
-template <typename R>
-int batched_occupancy(int variant) {
+template <typename R, bool AB>
+int batched_occupancy_ab(int variant) {
   int nb = 0;
   hipError_t e;
   switch (variant) {
-    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_advect_batched<R, 7>, 256, 0); break;
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_advect_batched<R, 14>, 256, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_advect_batched<R, 28>, 256, 0); break;
-    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_advect_batched<R, 49>, 256, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_fused_batched, 256, 0); break;
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_advect_batched<R, 7, AB>, 256, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_advect_batched<R, 14, AB>, 256, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_advect_batched<R, 28, AB>, 256, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_advect_batched<R, 49, AB>, 256, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_fused_batched<AB>, 256, 0); break;
   }
   return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
+template <typename R>
+int batched_occupancy(int variant, int active) {
+  return active ? batched_occupancy_ab<R, true>(variant) : batched_occupancy_ab<R, false>(variant);
 }
 
 template <typename R>
@@ -1016,17 +1139,23 @@ hipError_t launch_force_out(const double* force, size_t nc, int e2, double* fx, 
 
 template hipError_t launch_step<float>(const GridArgs<float>&, hipStream_t);
 template hipError_t launch_step<double>(const GridArgs<double>&, hipStream_t);
-template hipError_t launch_advect_batched<float>(int, const GridArgs<float>*, const int*, int, int, const int*, int, hipStream_t);
-template hipError_t launch_advect_batched<double>(int, const GridArgs<double>*, const int*, int, int, const int*, int, hipStream_t);
+template hipError_t launch_advect_batched<float>(int, const GridArgs<float>*, const int*, int, int, const int*, int, int, hipStream_t);
+template hipError_t launch_advect_batched<double>(int, const GridArgs<double>*, const int*, int, int, const int*, int, int, hipStream_t);
 template hipError_t launch_freq_batched<float>(const GridArgs<float>*, const int*, int, int, const int*, int, int, hipStream_t);
 template hipError_t launch_freq_batched<double>(const GridArgs<double>*, const int*, int, int, const int*, int, int, hipStream_t);
-template int batched_occupancy<float>(int);
-template int batched_occupancy<double>(int);
+template int batched_occupancy<float>(int, int);
+template int batched_occupancy<double>(int, int);
 template int freq_batched_occupancy<float>();
 template int freq_batched_occupancy<double>();
 template hipError_t launch_advect<float>(const GridArgs<float>&, hipStream_t);
 template hipError_t launch_advect<double>(const GridArgs<double>&, hipStream_t);
 template hipError_t launch_freq<float>(const GridArgs<float>&, hipStream_t);
+template hipError_t launch_active_bins<float>(const float*, int, int, int, const double*,
+                                              const double*, const double*, double, double*,
+                                              int32_t*, hipStream_t);
+template hipError_t launch_active_bins<double>(const double*, int, int, int, const double*,
+                                               const double*, const double*, double, double*,
+                                               int32_t*, hipStream_t);
 template hipError_t launch_freq<double>(const GridArgs<double>&, hipStream_t);
 template hipError_t launch_residual<float>(const float*, const float*, size_t, double*, int, double*, hipStream_t);
 template hipError_t launch_residual<double>(const double*, const double*, size_t, double*, int, double*, hipStream_t);

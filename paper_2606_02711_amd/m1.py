@@ -39,7 +39,8 @@ class m1_config(ctypes.Structure):
                 ("q", ctypes.c_double), ("half_width", ctypes.c_double),
                 ("c_tilde", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("recoil", ctypes.c_int32), ("doppler", ctypes.c_int32),
-                ("prec", ctypes.c_int32), ("fp64_tau", ctypes.c_double)]
+                ("prec", ctypes.c_int32), ("fp64_tau", ctypes.c_double),
+                ("active_frac", ctypes.c_double)]
 
 
 class m1_fields(ctypes.Structure):
@@ -91,6 +92,7 @@ def lib():
         "m1_set_state": (I32, [VP, VP, VP, VP]),
         "m1_get_state_region": (I32, [VP, I32, I32, I32, I32, VP, VP, VP]),
         "m1_get_info": (I32, [VP, P(D), P(I32), P(I32), P(I64), P(I32)]),
+        "m1_active_bins": (I32, [VP, VP, P(I32)]),
         "m1_batch_workspace_bytes": (I32, [P(VP), I32, P(ctypes.c_size_t)]),
         "m1_batch_init": (I32, [P(VP), I32, VP, ctypes.c_size_t, I32, P(VP)]),
         "m1_batch_step": (I32, [VP, I32]),
@@ -125,6 +127,7 @@ def exported_symbols():
     return ["m1_default_config", "m1_num_bins", "m1_workspace_bytes",
             "m1_count_temperature_classes", "m1_init", "m1_step", "m1_force",
             "m1_solve_steady", "m1_residual", "m1_get_state", "m1_set_state", "m1_get_state_region", "m1_get_info",
+            "m1_active_bins",
             "m1_batch_workspace_bytes", "m1_batch_init", "m1_batch_step", "m1_batch_info",
             "m1_batch_free", "m1_batch_set_tile", "m1_batch_workspace_bound",
             "m1_server_create", "m1_server_submit", "m1_server_run", "m1_server_poll",
@@ -155,6 +158,7 @@ def make_config(p, prec="fp64", fp64_tau=float("inf")):
     c.recoil, c.doppler = int(p.get("recoil", 1)), int(p.get("doppler", 1))
     c.prec = M1_FP32 if prec == "fp32" else M1_FP64
     c.fp64_tau = float(fp64_tau)
+    c.active_frac = float(p.get("active_frac", 0.0))
     return c
 
 
@@ -286,6 +290,13 @@ class M1Grid:
         torch.cuda.current_stream().synchronize()     # inputs written on torch's stream
         check(lib().m1_set_state(self.h, *[t.data_ptr() for t in self._set]))
         self.sync()
+
+    def active_bins(self):
+        """Flags (int32 [N_nu]) of the bins the last step advected."""
+        f = np.zeros(self.nb, dtype=np.int32)
+        n = ctypes.c_int32()
+        check(lib().m1_active_bins(self.h, f.ctypes.data, ctypes.byref(n)))
+        return f
 
     def force(self, out=None):
         torch = _torch()

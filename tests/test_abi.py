@@ -47,7 +47,8 @@ def test_workspace_bytes_scale():
     assert m1.workspace_bytes(c64, 0) > b64          # worst case: a class per cell
 
 
-@pytest.mark.parametrize("bad", ["geom", "nx", "ctilde", "cfl", "axis", "q"])
+@pytest.mark.parametrize("bad", ["geom", "nx", "ctilde", "cfl", "axis", "q", "active_neg",
+                                 "active_nan", "active_inf"])
 def test_config_validation(bad):
     p = inputs.config1()
     c = m1.make_config(p)
@@ -57,6 +58,9 @@ def test_config_validation(bad):
     if bad == "cfl": c.cfl = 0.0
     if bad == "axis": c.geom = m1.M1_CYL_RZ; c.x0 = 0.5
     if bad == "q": c.q = 1.0
+    if bad == "active_neg": c.active_frac = -1e-10
+    if bad == "active_nan": c.active_frac = float("nan")
+    if bad == "active_inf": c.active_frac = float("inf")
     n = ctypes.c_int32()
     assert m1.lib().m1_num_bins(ctypes.byref(c), ctypes.byref(n)) == m1.M1_EINVAL
     assert len(m1.lib().m1_last_error()) > 0
@@ -172,3 +176,13 @@ def test_empty_batch_rejected():
     assert m1.lib().m1_batch_workspace_bound(0, m1.M1_FP32, ctypes.byref(b)) == m1.M1_EINVAL
     h = ctypes.c_void_p()
     assert m1.lib().m1_batch_init(arr, 0, 256, 1 << 20, 0, ctypes.byref(h)) == m1.M1_EINVAL
+
+
+def test_active_bin_config_accepted_and_sized():
+    """The paper's threshold is a valid config; the selection's flags and
+    partial sums are part of the workspace either way."""
+    p = dict(inputs.config1(), active_frac=1e-10)
+    c = m1.make_config(p, "fp32")
+    assert c.active_frac == 1e-10
+    assert m1.num_bins(c) == 194
+    assert m1.workspace_bytes(c, 1) == m1.workspace_bytes(m1.make_config(inputs.config1(), "fp32"), 1)
