@@ -160,6 +160,7 @@ class OracleSetup:
         self.recoil = int(p.get("recoil", 1))
         self.doppler = int(p.get("doppler", 1))
         self.active_frac = float(p.get("active_frac", 0.0))
+        self.substep_rule = int(p.get("substep_rule", 0))
 
 
 # ------------------------------------------------------------- the C core
@@ -171,7 +172,8 @@ class _Prob(ctypes.Structure):
                 + [(n, ctypes.c_void_p) for n in
                    ("xe", "ye", "nu_c", "dnu", "alpha", "acabs", "acF", "pd", "ux",
                     "uy", "dnuD", "hkT", "emis", "cls", "hbar", "phi")]
-                + [("active_frac", ctypes.c_double), ("active", ctypes.c_void_p)])
+                + [("active_frac", ctypes.c_double), ("active", ctypes.c_void_p),
+                   ("substep_rule", ctypes.c_int), ("substeps", ctypes.c_void_p)])
 
 
 def build(force=False):
@@ -241,6 +243,9 @@ class Oracle:
         P.active_frac = s.active_frac
         self.active = np.ones(s.nb, dtype=np.int32)   # bins advected by the last step
         P.active = self.active.ctypes.data
+        P.substep_rule = s.substep_rule
+        self.substeps = np.ones((s.ny, s.nx), dtype=np.int32)   # accepted substeps per cell
+        P.substeps = self.substeps.ctypes.data
         self.P = P
 
     @property

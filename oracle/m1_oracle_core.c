@@ -23,8 +23,13 @@
  *       reconstruction of E and f = F/E, Levermore closure, GLF flux blended
  *       with the diffusion flux by epsilon(tau), upwind velocity advection,
  *       radiation-pressure work term, explicit Euler update, causality clamp;
- *   (2) implicit emission/absorption step (Section 2.1, step 2, BDF1);
- *   (3) radiation force density (Section 2.3), f = sum_k dnu_k alpha_F,k F_k;
+ *   (2) implicit emission/absorption step (Section 2.1, step 2, BDF1), in
+ *       one substep, or with substep_rule set, per cell in substeps accepted
+ *       when the cell's energy density changes by less than 10 % (halved and
+ *       redone otherwise);
+ *   (3) radiation force density (Section 2.3), f = sum_k dnu_k alpha_F,k F_k
+ *       (with substeps: the substep forces sum_k dnu_k (F. - F..)/(c dt_sub)
+ *       averaged over the step);
  *   (4) implicit frequency step per cell (Section 2.1, step 3; Appendix A):
  *       exponential-scheme leakage coefficients, tridiagonal solve
  *       (Thomas algorithm in long double), H rescaled by J_new/J_old.
@@ -62,6 +67,10 @@ typedef struct {
                                 exceeds this fraction of the total (Section 2.1,
                                 runtime controls) */
   int *active;               /* [nb] out: 1 where bin k was advected this step */
+  int substep_rule;          /* 1: emission/absorption in substeps under the
+                                10 % energy rule (Section 2.1, step 2) */
+  int *substeps;             /* [ncell] out (may be NULL): accepted substeps of
+                                each cell in the last step */
 } OracleProblem;
 
 /* ------------------------------------------------------------------------ */
@@ -350,7 +359,7 @@ static void free_velocity(VelData *V) { free(V->unx); free(V->uny); free(V->grad
  * not advected keeps its state through step (1): no fluxes, no work or hoop
  * term, no clamp (the state is causal already); step (2) acts as usual. */
 static void advect_source_bin(const OracleProblem *P, const Geometry *G,
-                              const VelData *V, int k, int advect,
+                              const VelData *V, int k, int advect, int source,
                               const double *E, const double *Fx, const double *Fy,
                               double *Eo, double *Fxo, double *Fyo, PadBin *B,
                               Flux3 *fxf, Flux3 *fyf) {
@@ -360,6 +369,7 @@ static void advect_source_bin(const OracleProblem *P, const Geometry *G,
   if (!advect) {
     for (size_t c = 0; c < nc; ++c) {
       size_t ck = (size_t)k * nc + c;
+      if (!source) { Eo[ck] = E[ck]; Fxo[ck] = Fx[ck]; Fyo[ck] = Fy[ck]; continue; }
       double h = P->hbar[(size_t)P->cls[c] * P->nb + k];
       double aH = P->alpha[c] * h;
       double kE = P->acabs[c] + P->pd[c] * aH;
@@ -418,6 +428,7 @@ static void advect_source_bin(const OracleProblem *P, const Geometry *G,
         double nF = hypot(Xs, Ys);
         if (nF > Es) { Xs *= Es / nF; Ys *= Es / nF; }
       }
+      if (!source) { Eo[ck] = Es; Fxo[ck] = Xs; Fyo[ck] = Ys; continue; }
       /* implicit emission / absorption / destruction (BDF1, one substep) */
       double h = P->hbar[(size_t)P->cls[c] * P->nb + k];
       double aH = P->alpha[c] * h;
@@ -541,6 +552,62 @@ static void select_active_bins(const OracleProblem *P, const double *E, int *act
 }
 
 /* ------------------------------------------------------------------------ */
+/* Emission/absorption of one cell in substeps (Section 2.1, step 2).  A
+ * substep of length h maps J. -> J.. = (J. + c h j)/(1 + c h kE) and
+ * H. -> H.. = H./(1 + c h aF) in every bin; it is accepted when
+ * |e.. - e.| < 0.1 (e. + e_floor), e = sum_k dnu_k E_k (the energy density),
+ * e_floor = 4 pi J_floor / c with J_floor = 1e-15 erg cm^-2 s^-1 sr^-1, and
+ * otherwise halved and redone.  After an accepted substep the next one tries
+ * twice the length, clipped to the time left (a reading: the paper does not
+ * say how the substep grows back).  A substep 2^-60 of the step, or the
+ * 4096th attempt, is accepted as it is, so the loop always ends.
+ * E, F (in/out, [nb] with stride nc) go from the post-transport to the
+ * post-source state; f4 receives the step-averaged force, the sum over
+ * substeps of (h/dt) sum_k dnu_k (F. - F..)/(c h), and its line part. */
+#define SUB_MAX_ATTEMPTS 4096
+static int source_substeps_cell(const OracleProblem *P, size_t c, size_t nc, double *E,
+                                double *Fx, double *Fy, double *f4, double *Et) {
+  int nb = P->nb;
+  const double e_floor = 4.0 * ORACLE_PI * 1.0e-15 / C_LIGHT;
+  const double dt = P->dt, ct = P->c_tilde;
+  int cl = P->cls[c];
+  double done = 0.0, h = dt;
+  int accepted = 0;
+  for (int q = 0; q < 4; ++q) f4[q] = 0.0;
+  for (int attempt = 1; done < dt; ++attempt) {
+    if (h > dt - done) h = dt - done;
+    double e0 = 0.0, e1 = 0.0;
+    for (int k = 0; k < nb; ++k) {
+      size_t ck = (size_t)k * nc + c;
+      double hb = P->hbar[(size_t)cl * nb + k];
+      double kE = P->acabs[c] + P->pd[c] * P->alpha[c] * hb;
+      double src = P->emis[c] * P->phi[(size_t)cl * nb + k] / C_LIGHT;
+      Et[k] = (E[ck] + ct * h * src) / (1.0 + ct * h * kE);
+      e0 += P->dnu[k] * E[ck];
+      e1 += P->dnu[k] * Et[k];
+    }
+    int ok = fabs(e1 - e0) < 0.1 * (e0 + e_floor) || h <= ldexp(dt, -60) ||
+             attempt >= SUB_MAX_ATTEMPTS;
+    if (!ok) { h *= 0.5; continue; }
+    for (int k = 0; k < nb; ++k) {
+      size_t ck = (size_t)k * nc + c;
+      double hb = P->hbar[(size_t)cl * nb + k];
+      double aH = P->alpha[c] * hb, aF = aH + P->acF[c];
+      double gx = Fx[ck] / (1.0 + ct * h * aF), gy = Fy[ck] / (1.0 + ct * h * aF);
+      /* substep force sum_k dnu_k (F. - F..)/(c_tilde h), weighted by h/dt */
+      double wx = P->dnu[k] * (Fx[ck] - gx) / (ct * dt), wy = P->dnu[k] * (Fy[ck] - gy) / (ct * dt);
+      f4[0] += wx; f4[1] += wy;
+      f4[2] += (aH / aF) * wx; f4[3] += (aH / aF) * wy;   /* line (gas) share */
+      E[ck] = Et[k]; Fx[ck] = gx; Fy[ck] = gy;
+    }
+    done += h;
+    ++accepted;
+    h *= 2.0;
+  }
+  return accepted;
+}
+
+/* ------------------------------------------------------------------------ */
 /* One full RT step.  E, Fx, Fy: state in/out [nb][ncell].
  * force: [4][ncell] = (f_x, f_y, f_x gas part, f_y gas part) of this step.
  * Ess, Xss, Yss: caller scratch of the state size (post-source state). */
@@ -570,12 +637,30 @@ int oracle_step(const OracleProblem *P, double *E, double *Fx, double *Fy,
     Flux3 *fyf = (Flux3 *)malloc(sizeof(Flux3) * (size_t)nx * (ny + 1));
 #pragma omp for schedule(dynamic, 1)
     for (int k = 0; k < nb; ++k)
-      advect_source_bin(P, &G, &V, k, active[k], E, Fx, Fy, Ess, Xss, Yss, &B, fxf, fyf);
+      advect_source_bin(P, &G, &V, k, active[k], !P->substep_rule, E, Fx, Fy, Ess, Xss, Yss,
+                        &B, fxf, fyf);
     free(B.E); free(B.fx); free(B.fy); free(B.aF); free(fxf); free(fyf);
   }
-  /* (3) radiation force density, f = sum_k dnu_k alpha_F,k F**_k */
+  /* (2) with the substep rule: emission/absorption per cell, force with it */
+  if (P->substep_rule) {
+#pragma omp parallel
+    {
+      double *Et = (double *)malloc(sizeof(double) * nb);
+#pragma omp for schedule(dynamic, 64)
+      for (long c = 0; c < (long)nc; ++c) {
+        double f4[4];
+        int n = source_substeps_cell(P, (size_t)c, nc, Ess, Xss, Yss, f4, Et);
+        if (P->substeps) P->substeps[c] = n;
+        for (int q = 0; q < 4; ++q) force[(size_t)q * nc + c] = f4[q];
+      }
+      free(Et);
+    }
+  }
+  /* (3) radiation force density, f = sum_k dnu_k alpha_F,k F**_k (one
+   * substep; the substep path formed it above) */
+  long ncf = P->substep_rule ? 0 : (long)nc;
 #pragma omp parallel for schedule(static)
-  for (long c = 0; c < (long)nc; ++c) {
+  for (long c = 0; c < ncf; ++c) {
     double sx = 0, sy = 0, gx = 0, gy = 0;
     int cl = P->cls[c];
     for (int k = 0; k < nb; ++k) {

@@ -799,3 +799,95 @@ def test_only_empty_bins_inactive_is_full_advection():
     b = _active_after_one_step(p, E, Fx, Fy)
     for x, y in ((a.E, b.E), (a.Fx, b.Fx), (a.Fy, b.Fy), (a.force, b.force)):
         assert np.array_equal(x, y)
+
+
+# ------------------------------------ emission/absorption substeps (10 % rule)
+E_FLOOR = 4.0 * math.pi * 1.0e-15 / M.C_LIGHT          # erg cm^-3 (J_floor = 1e-15)
+
+
+def _interior(a):
+    return a[..., 2:-2, 2:-2]
+
+
+def test_substeps_pure_absorption_closed_form():
+    """No line opacity and no emission, continuum absorption with
+    c dt kappa = 1 in a uniform box: a substep of dt/8 changes e by
+    1/9 > 10 %, one of dt/16 by 1/17 < 10 %, and every attempt to double
+    from dt/16 fails again, so the step is 16 substeps of dt/16:
+    E = E0 (1 + 1/16)^-16, F likewise, and the step-averaged force is
+    sum_k dnu_k (F0 - F)/(c dt) (Section 2.1, step 2; Section 2.3).
+    Away from the walls a uniform state does not move in one step."""
+    p = make_problem("cart", 10, 10, 1.0e15, ("vacuum",) * 4, n_HI=0.0, half_width=2.0e2,
+                     recoil=0)
+    o = M.Oracle(p)
+    ctdt = p["c_tilde"] * o.dt
+    kappa = 1.0 / ctdt
+    p = make_problem("cart", 10, 10, 1.0e15, ("vacuum",) * 4, n_HI=0.0, acabs=kappa,
+                     acF=kappa, half_width=2.0e2, recoil=0)
+    p["substep_rule"] = 1
+    o = M.Oracle(p)
+    nb = o.s.nb
+    E0 = np.ones((nb, 10, 10))
+    F0 = 0.5 * E0
+    o.set_state(E0, F0, np.zeros_like(E0))
+    o.step(1)
+    decay = (1.0 + 1.0 / 16.0) ** -16
+    assert np.all(_interior(o.substeps) == 16)
+    assert np.allclose(_interior(o.E), decay, rtol=1e-13, atol=0)
+    assert np.allclose(_interior(o.Fx), 0.5 * decay, rtol=1e-13, atol=0)
+    dnu = o.s.grid["dnu"]
+    f_expect = float(np.sum(dnu * 0.5 * (1.0 - decay))) / ctdt
+    assert np.allclose(_interior(o.force[0]), f_expect, rtol=1e-12, atol=0)
+    assert np.all(_interior(o.force[2]) == 0.0)           # no line opacity: no gas share
+    # one substep would have given E0 / 2
+    p["substep_rule"] = 0
+    q = M.Oracle(p)
+    q.set_state(E0, F0, np.zeros_like(E0))
+    q.step(1)
+    assert np.allclose(_interior(q.E), 0.5, rtol=1e-14, atol=0)
+
+
+def test_substeps_pure_emission_end_at_the_full_step():
+    """Emission into an empty uniform box without absorption: each substep
+    adds c h S_k, so whatever the accepted sequence, the step ends at
+    E = c dt S_k (the substeps add up to dt).  The emission is strong enough
+    against e_floor for the rule to split the step."""
+    p = make_problem("cart", 8, 8, 1.0e15, ("vacuum",) * 4, n_HI=0.0, half_width=2.0e2,
+                     recoil=0)
+    o = M.Oracle(p)
+    ctdt = p["c_tilde"] * o.dt
+    emis = 1.0e3 * E_FLOOR * M.C_LIGHT / ctdt           # c dt (emis / c) = 1e3 e_floor
+    p = make_problem("cart", 8, 8, 1.0e15, ("vacuum",) * 4, n_HI=0.0, emis=emis,
+                     half_width=2.0e2, recoil=0)
+    p["substep_rule"] = 1
+    o = M.Oracle(p)
+    o.step(1)
+    S = emis * o.s.phi[0] / M.C_LIGHT                     # one temperature class
+    assert np.all(_interior(o.substeps) > 10)
+    assert np.allclose(_interior(o.E), (ctdt * S)[:, None, None], rtol=1e-12, atol=0)
+    e = np.tensordot(o.s.grid["dnu"], _interior(o.E), axes=(0, 0))
+    assert np.allclose(e, 1.0e3 * E_FLOOR, rtol=1e-12)
+
+
+def test_substeps_that_all_pass_equal_one_substep():
+    """Weak sources against a large state: every cell accepts the whole step
+    at once, and the state equals the one-substep path bit for bit; the force
+    (the substep form sum dnu (F. - F..)/(c dt)) agrees to rounding."""
+    p = inputs.random_small("cyl", 11, 9, seed=21, half_width=3.0e2)
+    nb = M.frequency_grid(half_width=3.0e2)["nb"]
+    rng = np.random.default_rng(3)
+    E = rng.uniform(0.5, 1.0, size=(nb, 9, 11))
+    Fx = 0.3 * E * rng.uniform(-1, 1, size=E.shape)
+    Fy = 0.3 * E * rng.uniform(-1, 1, size=E.shape)
+    out = []
+    for rule in (0, 1):
+        p["substep_rule"] = rule
+        o = M.Oracle(p)
+        o.set_state(E, Fx, Fy)
+        o.step(1)
+        out.append(o)
+    a, b = out
+    assert np.all(b.substeps == 1)
+    for x, y in ((a.E, b.E), (a.Fx, b.Fx), (a.Fy, b.Fy)):
+        assert np.array_equal(x, y)
+    assert np.allclose(a.force, b.force, rtol=1e-11, atol=1e-11 * np.abs(a.force).max())
