@@ -173,7 +173,8 @@ class _Prob(ctypes.Structure):
                    ("xe", "ye", "nu_c", "dnu", "alpha", "acabs", "acF", "pd", "ux",
                     "uy", "dnuD", "hkT", "emis", "cls", "hbar", "phi")]
                 + [("active_frac", ctypes.c_double), ("active", ctypes.c_void_p),
-                   ("substep_rule", ctypes.c_int), ("substeps", ctypes.c_void_p)])
+                   ("substep_rule", ctypes.c_int), ("substeps", ctypes.c_void_p),
+                   ("sub_margin", ctypes.c_void_p)])
 
 
 def build(force=False):
@@ -246,6 +247,8 @@ class Oracle:
         P.substep_rule = s.substep_rule
         self.substeps = np.ones((s.ny, s.nx), dtype=np.int32)   # accepted substeps per cell
         P.substeps = self.substeps.ctypes.data
+        self.sub_margin = np.full((s.ny, s.nx), np.inf)        # closest call to the 10 % rule
+        P.sub_margin = self.sub_margin.ctypes.data
         self.P = P
 
     @property

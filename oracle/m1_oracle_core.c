@@ -71,6 +71,10 @@ typedef struct {
                                 10 % energy rule (Section 2.1, step 2) */
   int *substeps;             /* [ncell] out (may be NULL): accepted substeps of
                                 each cell in the last step */
+  double *sub_margin;        /* [ncell] out (may be NULL): over the attempts of
+                                the last step, the smallest |r/0.1 - 1|, r the
+                                attempt's relative energy change (how close a
+                                decision came to the 10 % boundary) */
 } OracleProblem;
 
 /* ------------------------------------------------------------------------ */
@@ -563,16 +567,20 @@ static void select_active_bins(const OracleProblem *P, const double *E, int *act
  * 4096th attempt, is accepted as it is, so the loop always ends.
  * E, F (in/out, [nb] with stride nc) go from the post-transport to the
  * post-source state; f4 receives the step-averaged force, the sum over
- * substeps of (h/dt) sum_k dnu_k (F. - F..)/(c h), and its line part. */
+ * substeps of (h/dt) sum_k dnu_k (F. - F..)/(c h), and its line part.  Since
+ * F. - F.. = c h aF F.. exactly (the implicit update), each substep's force is
+ * formed as sum_k dnu_k aF F.., free of the cancellation of the difference. */
 #define SUB_MAX_ATTEMPTS 4096
 static int source_substeps_cell(const OracleProblem *P, size_t c, size_t nc, double *E,
-                                double *Fx, double *Fy, double *f4, double *Et) {
+                                double *Fx, double *Fy, double *f4, double *Et,
+                                double *margin) {
   int nb = P->nb;
   const double e_floor = 4.0 * ORACLE_PI * 1.0e-15 / C_LIGHT;
   const double dt = P->dt, ct = P->c_tilde;
   int cl = P->cls[c];
   double done = 0.0, h = dt;
   int accepted = 0;
+  *margin = INFINITY;
   for (int q = 0; q < 4; ++q) f4[q] = 0.0;
   for (int attempt = 1; done < dt; ++attempt) {
     if (h > dt - done) h = dt - done;
@@ -586,6 +594,8 @@ static int source_substeps_cell(const OracleProblem *P, size_t c, size_t nc, dou
       e0 += P->dnu[k] * E[ck];
       e1 += P->dnu[k] * Et[k];
     }
+    double r = fabs(e1 - e0) / (e0 + e_floor);
+    if (fabs(r / 0.1 - 1.0) < *margin) *margin = fabs(r / 0.1 - 1.0);
     int ok = fabs(e1 - e0) < 0.1 * (e0 + e_floor) || h <= ldexp(dt, -60) ||
              attempt >= SUB_MAX_ATTEMPTS;
     if (!ok) { h *= 0.5; continue; }
@@ -594,8 +604,9 @@ static int source_substeps_cell(const OracleProblem *P, size_t c, size_t nc, dou
       double hb = P->hbar[(size_t)cl * nb + k];
       double aH = P->alpha[c] * hb, aF = aH + P->acF[c];
       double gx = Fx[ck] / (1.0 + ct * h * aF), gy = Fy[ck] / (1.0 + ct * h * aF);
-      /* substep force sum_k dnu_k (F. - F..)/(c_tilde h), weighted by h/dt */
-      double wx = P->dnu[k] * (Fx[ck] - gx) / (ct * dt), wy = P->dnu[k] * (Fy[ck] - gy) / (ct * dt);
+      /* substep force sum_k dnu_k (F. - F..)/(c_tilde h) = sum_k dnu_k aF F..,
+       * weighted by h/dt */
+      double wx = P->dnu[k] * aF * gx * (h / dt), wy = P->dnu[k] * aF * gy * (h / dt);
       f4[0] += wx; f4[1] += wy;
       f4[2] += (aH / aF) * wx; f4[3] += (aH / aF) * wy;   /* line (gas) share */
       E[ck] = Et[k]; Fx[ck] = gx; Fy[ck] = gy;
@@ -648,9 +659,10 @@ int oracle_step(const OracleProblem *P, double *E, double *Fx, double *Fy,
       double *Et = (double *)malloc(sizeof(double) * nb);
 #pragma omp for schedule(dynamic, 64)
       for (long c = 0; c < (long)nc; ++c) {
-        double f4[4];
-        int n = source_substeps_cell(P, (size_t)c, nc, Ess, Xss, Yss, f4, Et);
+        double f4[4], mg;
+        int n = source_substeps_cell(P, (size_t)c, nc, Ess, Xss, Yss, f4, Et, &mg);
         if (P->substeps) P->substeps[c] = n;
+        if (P->sub_margin) P->sub_margin[c] = mg;
         for (int q = 0; q < 4; ++q) force[(size_t)q * nc + c] = f4[q];
       }
       free(Et);
