@@ -99,6 +99,19 @@ typedef struct {
                               selection, which is taken on the state in its
                               storage precision (FP32 and FP64 paths can differ
                               for a bin whose share sits at the threshold). */
+  int32_t substep_rule;    /* 0/1: emission/absorption in substeps (Section
+                              2.1, step 2): per cell, a substep is accepted
+                              when the energy density sum_k dnu_k E_k changes
+                              by less than 10 % of (e + e_floor), e_floor =
+                              4 pi J_floor / c with J_floor = 1e-15 erg cm^-2
+                              s^-1 sr^-1, and halved and redone otherwise; the
+                              next substep tries twice the accepted length
+                              (clipped to the time left); a substep of 2^-60
+                              of the step or the 4096th attempt is accepted as
+                              it is.  The force is the substep forces averaged
+                              over the step.  0 (the default): one substep.
+                              Single-grid stepping only (batches refuse such
+                              handles with M1_EUNSUPPORTED). */
 } m1_config;
 
 /* Per-cell physical inputs, FP64, [ny][nx].  Host pointers when on_device is
@@ -287,7 +300,9 @@ int32_t m1_server_create(const m1_server_config *cfg, void *d_arena, size_t aren
                          void *stream, m1_fields_cb cb, void *user, m1_server **out);
 /* Queues a request.  cfg is copied; n_temp_classes as for m1_workspace_bytes.
  * A request that cannot fit an empty arena is recorded as rejected (it is
- * reported by the next m1_server_poll) and *id still receives its id. */
+ * reported by the next m1_server_poll) and *id still receives its id.  A
+ * batched server refuses a config with substep_rule set (M1_EUNSUPPORTED,
+ * nothing queued). */
 int32_t m1_server_submit(m1_server *s, const m1_config *cfg, int64_t n_temp_classes,
                          double rel_tol, int64_t max_steps, int64_t *id);
 /* Runs up to `rounds` rounds (admission, steps, residual checks; blocking)

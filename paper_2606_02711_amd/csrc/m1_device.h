@@ -58,6 +58,10 @@ struct GridArgs {
   double *force;          // [4][ncell]
   // active bins: flags [nb] of the bins this step advects (nullptr: all)
   const int32_t *active;
+  // emission/absorption in substeps under the 10 % energy rule (0/1), and the
+  // energy-density floor of the rule in state units
+  int substeps;
+  double e_floor;
 };
 
 // Address-space hints for pointers read from a descriptor table in memory

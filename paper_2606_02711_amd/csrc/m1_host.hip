@@ -186,6 +186,7 @@ int validate_config(const m1_config* c, int* nb_out) {
   if (isnan(c->fp64_tau)) return fail(M1_EINVAL, "fp64_tau is NaN");
   if (!(c->active_frac >= 0.0) || !isfinite(c->active_frac))
     return fail(M1_EINVAL, "active_frac must be finite and >= 0");
+  if (c->substep_rule != 0 && c->substep_rule != 1) return fail(M1_EINVAL, "substep_rule must be 0/1");
   FreqGrid g;
   int st = build_grid(*c, g);
   if (st) return st;
@@ -270,6 +271,10 @@ void fill_args(m1_handle* h, GridArgs<R>* a) {
     g.zw = (ZW<R>*)(w + L.zw);
     g.force = (double*)(w + L.force);
     g.active = c.active_frac > 0.0 ? (const int32_t*)(w + L.active) : nullptr;
+    g.substeps = c.substep_rule;
+    // e_floor = 4 pi J_floor / c, J_floor = 1e-15 erg cm^-2 s^-1 sr^-1, in
+    // the scaled state units
+    g.e_floor = ldexp(4.0 * kPi * 1.0e-15 / kC, h->e2);
   }
 }
 
@@ -776,6 +781,8 @@ int check_members(m1_handle* const* hs, int n) {
     if (hs[q]->broken) return fail(M1_ESTATE, "handle %d had a device error", q);
     if (hs[q]->cfg.prec != hs[0]->cfg.prec) return fail(M1_EINVAL, "mixed precisions in a batch");
     if (hs[q]->stream != hs[0]->stream) return fail(M1_EINVAL, "batch members must share a stream");
+    if (hs[q]->cfg.substep_rule)
+      return fail(M1_EUNSUPPORTED, "handle %d uses the substep rule: step it alone", q);
     for (int r = 0; r < q; ++r)
       if (hs[r] == hs[q]) return fail(M1_EINVAL, "handle %d appears twice", q);
   }

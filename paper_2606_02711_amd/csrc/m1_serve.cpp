@@ -302,6 +302,8 @@ int32_t m1_server_submit(m1_server* s, const m1_config* cfg, int64_t n_temp_clas
   if (!(rel_tol > 0) || max_steps < 1) return err(M1_EINVAL, "need rel_tol > 0 and max_steps >= 1");
   m1_config c = *cfg;
   c.prec = s->c.prec;
+  if (s->c.batched && c.substep_rule)
+    return err(M1_EUNSUPPORTED, "the substep rule needs single-grid stepping (batched server)");
   size_t ws = 0;
   int st = m1_workspace_bytes(&c, n_temp_classes, &ws);
   if (st) return st;

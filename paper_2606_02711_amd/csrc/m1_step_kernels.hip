@@ -199,7 +199,9 @@ struct WriteSink {
 // One tile x run of bins (logical block L of grid a); BK = 0: all bins.
 // AB: the grid selects active bins (a.active); a separate instantiation, so
 // that grids advecting every bin keep the registers of the plain loop.
-template <typename R, int BK, bool AB, class Sink>
+// SUB: emission/absorption is left to the frequency kernel (substep rule);
+// the sink gets the post-transport state.
+template <typename R, int BK, bool AB, bool SUB, class Sink>
 __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigned L,
                                              AdvShared<R>& S, Sink& sink) {
   const int nx = a.nx, ny = a.ny, nb = a.nb;
@@ -320,6 +322,10 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
         const R EC = Ek[c], fxc = Xk[c], fyc = Yk[c];
         const int cc = ccls[m];
         const R hC = hb[(size_t)cc * nb];
+        if constexpr (SUB) {
+          sink.put(a, m, k, koff + c, hC, EC, fxc * EC, fyc * EC);
+          continue;
+        }
         const R aFC = a.alpha[c] * hC + a.acF[c];
         const R src = em[m] * a.phi[(size_t)cc * nb + k];
         const R kE = acabs[m] + pda[m] * hC;
@@ -385,9 +391,13 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
       const int cc = ccls[m];
       const R hC = hb[(size_t)cc * nb];
       const R aFC = S.aF[lj + 1][tx + 1];
+      const size_t q = koff + cidx[m];
+      if constexpr (SUB) {
+        sink.put(a, m, k, q, hC, Es, Xs, Ys);
+        continue;
+      }
       const R src = em[m] * a.phi[(size_t)cc * nb + k];
       const R kE = acabs[m] + pda[m] * hC;
-      const size_t q = koff + cidx[m];
       const R dF = frcp(R(1) + ctdt * aFC);
       sink.put(a, m, k, q, hC, (Es + ctdt * src) * frcp(R(1) + ctdt * kE), Xs * dF, Ys * dF);
     }
@@ -400,12 +410,12 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
 template <typename R>
 constexpr int kAdvectWaves = sizeof(R) == 4 ? 5 : 1;
 
-template <typename R, int BK, bool AB>
+template <typename R, int BK, bool AB, bool SUB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kAdvectWaves<R>)))
 void k_advect_source(GridArgs<R> a) {
   __shared__ AdvShared<R> S;
   WriteSink<R> sink;
-  advect_block<R, BK, AB>(a, xcd_logical_block(), S, sink);
+  advect_block<R, BK, AB, SUB>(a, xcd_logical_block(), S, sink);
 }
 
 // Batched, persistent advection: blocks walk the work items (grid, tile x
@@ -430,7 +440,7 @@ void k_advect_batched(const GridArgs<R>* __restrict__ args,
     }
     const GridArgs<R> a = global_args(args[((par[lo] ^ sp) & 1) * n + lo]);
     WriteSink<R> sink;
-    advect_block<R, BK, AB>(a, (unsigned)(w - off[lo]), S, sink);
+    advect_block<R, BK, AB, false>(a, (unsigned)(w - off[lo]), S, sink);
   }
 }
 
@@ -679,6 +689,193 @@ void k_freq(GridArgs<R> a) {
   freq_dispatch<R, P>(a, c);
 }
 
+// ------------------------------------------- K3 with the substep rule
+// Section 2.1, step 2, with substeps: the advection kernel leaves the
+// emission/absorption to this kernel, which runs it per cell over all bins.
+// A substep of a fraction h of the step maps E -> (E + ctdt h S)/(1 + ctdt h kE)
+// and F -> F/(1 + ctdt h aF) in every bin (S = em phi_k, kE = acabs + pda
+// h_k, aF = alpha h_k + acF); it is accepted when the energy density
+// e = sum_k dnu_k E_k changes by less than 0.1 (e + e_floor), else halved and
+// redone; after an accepted substep the next one tries twice its length,
+// clipped to the time left.  A substep of 2^-60 of the step, or the 4096th
+// attempt, is accepted as it is.  Sums, decisions and updates in double.
+template <typename R>
+struct SourceCell {
+  const R* hb;      // the cell's class row of hbar
+  const R* ph;      // and of phi
+  double em, acabs, pda, al, acF;
+  __device__ __forceinline__ void at(int k, double& S, double& kE, double& aH, double& aF) const {
+    const double h = (double)hb[k];
+    S = em * (double)ph[k];
+    kE = acabs + pda * h;
+    aH = al * h;
+    aF = aH + acF;
+  }
+};
+
+constexpr int kSubMaxAttempts = 4096;
+
+// Whether the whole step passes the rule (then nothing is written and the
+// forward sweep applies the single substep); otherwise the substeps are
+// applied to the stored state (E and f, in place) and f4 gets the
+// step-averaged force sum_s h_s sum_k dnu_k aF F_k(after s) and its line part.
+template <typename R>
+__device__ bool source_substeps(const GridArgs<R>& a, size_t c, size_t nc,
+                                const SourceCell<R>& sc, double* f4) {
+  const int nb = a.nb;
+  const double ctdt = (double)a.ctdt, efl = a.e_floor;
+  R* __restrict__ Ek = a.Eo;
+  R* __restrict__ Xk = a.fxo;
+  R* __restrict__ Yk = a.fyo;
+  auto energies = [&](double ch, double& e0, double& e1) {
+    e0 = 0.0; e1 = 0.0;
+    for (int k = 0; k < nb; ++k) {
+      double S, kE, aH, aF;
+      sc.at(k, S, kE, aH, aF);
+      const double E = (double)Ek[(size_t)k * nc + c];
+      e0 += a.dnu[k] * E;
+      e1 += a.dnu[k] * ((E + ch * S) / (1.0 + ch * kE));
+    }
+  };
+  double e0, e1;
+  energies(ctdt, e0, e1);
+  f4[0] = f4[1] = f4[2] = f4[3] = 0.0;
+  if (fabs(e1 - e0) < 0.1 * (e0 + efl)) return true;
+  double done = 0.0, h = 0.5;
+  for (int attempt = 2; done < 1.0; ++attempt) {
+    if (h > 1.0 - done) h = 1.0 - done;
+    const double ch = ctdt * h;
+    energies(ch, e0, e1);
+    const bool ok = fabs(e1 - e0) < 0.1 * (e0 + efl) || h <= 0x1p-60 ||
+                    attempt >= kSubMaxAttempts;
+    if (!ok) { h *= 0.5; continue; }
+    for (int k = 0; k < nb; ++k) {
+      double S, kE, aH, aF;
+      sc.at(k, S, kE, aH, aF);
+      const size_t i = (size_t)k * nc + c;
+      const double E = (double)Ek[i];
+      const double E1 = (E + ch * S) / (1.0 + ch * kE);
+      const double d = 1.0 / (1.0 + ch * aF);
+      const double Fx = (double)Xk[i] * E * d, Fy = (double)Yk[i] * E * d;
+      // substep force sum_k dnu_k (F. - F..)/(c dt_sub) = sum_k dnu_k aF F..,
+      // weighted by the substep's share h of the step
+      const double w = a.dnu[k] * h;
+      f4[0] += w * aF * Fx; f4[1] += w * aF * Fy;
+      f4[2] += w * aH * Fx; f4[3] += w * aH * Fy;
+      Ek[i] = (R)E1;
+      Xk[i] = E1 > 0.0 ? (R)(Fx / E1) : R(0);
+      Yk[i] = E1 > 0.0 ? (R)(Fy / E1) : R(0);
+    }
+    done += h;
+    h *= 2.0;
+  }
+  return false;
+}
+
+// Forward elimination of one cell reading the post-transport state (full:
+// the single substep is applied to each bin on the way, the reduced flux
+// after it stored, and the force accumulated) or the post-source state left
+// by the substeps.  The steps of freq_forward, a bin at a time.
+template <typename R, typename T>
+__device__ void freq_forward_sub(const GridArgs<R>& a, const FreqCell<R, T>& fc,
+                                 const SourceCell<R>& sc, size_t c, size_t nc, bool full,
+                                 double* f4) {
+  const int nb = a.nb;
+  const double ctdt = (double)a.ctdt;
+  T qp = T(0), Cp = T(0);
+  R ep = R(0);
+  FreqRow row;
+  for (int k = 0; k < nb; ++k) {
+    const size_t i = (size_t)k * nc + c;
+    R e = a.Eo[i], x = a.fxo[i], y = a.fyo[i];
+    const R h = sc.hb[k];
+    if (full) {
+      double S, kE, aH, aF;
+      sc.at(k, S, kE, aH, aF);
+      const double E = (double)e;
+      const double E1 = (E + ctdt * S) / (1.0 + ctdt * kE);
+      const double d = 1.0 / (1.0 + ctdt * aF);
+      const double Fx = (double)x * E * d, Fy = (double)y * E * d;
+      e = (R)E1;
+      x = E1 > 0.0 ? (R)(Fx / E1) : R(0);
+      y = E1 > 0.0 ? (R)(Fy / E1) : R(0);
+      a.fxo[i] = x;
+      a.fyo[i] = y;
+      const double X = (double)x * (double)e, Y = (double)y * (double)e;
+      const double aHr = sc.al * (double)h, aFr = aHr + sc.acF;
+      f4[0] += a.dnu[k] * aFr * X; f4[1] += a.dnu[k] * aFr * Y;
+      f4[2] += a.dnu[k] * aHr * X; f4[3] += a.dnu[k] * aHr * Y;
+    }
+    T qk, Ck;
+    fc.coeffs(a, k, h, x, y, qk, Ck);
+    if (k > 0) {
+      T gl, gr;
+      if (qp > T(0) && qk > T(0)) {
+        interface_rates<T>(qp, Cp, qk, Ck, gl, gr);
+      } else {
+        gl = Cp < T(0) ? -Cp : T(0);
+        gr = Ck > T(0) ? Ck : T(0);
+      }
+      const double a_k = ctdt * (double)gl * a.inv_dnu[k - 1];
+      const double b_next = ctdt * (double)gr * a.inv_dnu[k];
+      row.eliminate<R>(k - 1, a.dnu[k - 1] * (double)ep, a_k, b_next,
+                       &a.zw[(size_t)(k - 1) * nc + c]);
+    }
+    qp = qk;
+    Cp = Ck;
+    ep = e;
+  }
+  row.eliminate<R>(nb - 1, a.dnu[nb - 1] * (double)ep, 0.0, 0.0,
+                   &a.zw[(size_t)(nb - 1) * nc + c]);
+}
+
+template <typename R, typename T>
+__device__ void freq_cell_sub(const GridArgs<R>& a, size_t c) {
+  const size_t nc = (size_t)a.nx * a.ny;
+  const int cl = a.cls[c];
+  FreqCell<R, T> fc;
+  const T al = (T)a.alpha[c];
+  fc.gxx = (T)a.grad[c];
+  fc.gyy = (T)a.grad[nc + c];
+  fc.gxy = (T)a.grad[2 * nc + c];
+  fc.gpp = (T)a.grad[3 * nc + c];
+  fc.dd = (T)a.dD2h[cl] * al;
+  fc.hkT = (T)a.hkT[cl];
+  fc.recoil = a.recoil != 0;
+  fc.doppler = a.doppler != 0 &&
+      ((fc.gxx != T(0)) || (fc.gyy != T(0)) || (fc.gxy != T(0)) || (fc.gpp != T(0)));
+  SourceCell<R> sc;
+  sc.hb = a.hbar + (size_t)cl * a.nb;
+  sc.ph = a.phi + (size_t)cl * a.nb;
+  sc.em = (double)a.em[c];
+  sc.acabs = (double)a.acabs[c];
+  sc.pda = (double)a.pda[c];
+  sc.al = (double)a.alpha[c];
+  sc.acF = (double)a.acF[c];
+  double f4[4];
+  const bool full = source_substeps<R>(a, c, nc, sc, f4);
+  freq_forward_sub<R, T>(a, fc, sc, c, nc, full, f4);
+  freq_backward<R>(a, c, nc, a.Eo, a.zw);
+  a.force[c] = f4[0];
+  a.force[nc + c] = f4[1];
+  a.force[2 * nc + c] = f4[2];
+  a.force[3 * nc + c] = f4[3];
+}
+
+// Pass P as in k_freq (float: island cells in their own pass).
+template <typename R, int P>
+__global__ __launch_bounds__(256) void k_freq_sub(GridArgs<R> a) {
+  const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (size_t)a.nx * a.ny) return;
+  if constexpr (sizeof(R) == 8) {
+    freq_cell_sub<R, double>(a, c);
+  } else if constexpr (P == 0) {
+    if (!a.island[c]) freq_cell_sub<R, float>(a, c);
+  } else {
+    if (a.island[c]) freq_cell_sub<R, double>(a, c);
+  }
+}
+
 // Batched, persistent frequency step: work item = 256 cells of one grid.
 template <typename R, int P>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFreqWaves<R, P>)))
@@ -816,7 +1013,7 @@ void k_step_fused_batched(const GridArgs<float>* __restrict__ args,
     }
     const GridArgs<float> a = global_args(args[((par[lo] ^ sp) & 1) * n + lo]);
     FusedSink sink;
-    advect_block<float, 0, AB>(a, (unsigned)(w - off[lo]), S, sink);
+    advect_block<float, 0, AB, false>(a, (unsigned)(w - off[lo]), S, sink);
   }
 }
 
@@ -913,10 +1110,14 @@ template <typename R>
 hipError_t launch_advect(const GridArgs<R>& a, hipStream_t s) {
   const unsigned nbx = (a.nx + kTX - 1) / kTX, nby = (a.ny + kTY - 1) / kTY;
   const unsigned nbz = (a.nb + kBK - 1) / kBK;
-  if (a.active)
-    hipLaunchKernelGGL((k_advect_source<R, kBK, true>), dim3(nbx * nby * nbz), dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_advect_source<R, kBK, false>), dim3(nbx * nby * nbz), dim3(256), 0, s, a);
+  const dim3 g(nbx * nby * nbz), b(256);
+  if (a.substeps) {
+    if (a.active) hipLaunchKernelGGL((k_advect_source<R, kBK, true, true>), g, b, 0, s, a);
+    else          hipLaunchKernelGGL((k_advect_source<R, kBK, false, true>), g, b, 0, s, a);
+  } else {
+    if (a.active) hipLaunchKernelGGL((k_advect_source<R, kBK, true, false>), g, b, 0, s, a);
+    else          hipLaunchKernelGGL((k_advect_source<R, kBK, false, false>), g, b, 0, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -924,6 +1125,11 @@ template <typename R>
 hipError_t launch_freq(const GridArgs<R>& a, hipStream_t s) {
   size_t nc = (size_t)a.nx * a.ny;
   const dim3 g((unsigned)((nc + 255) / 256));
+  if (a.substeps) {
+    hipLaunchKernelGGL((k_freq_sub<R, 0>), g, dim3(256), 0, s, a);
+    if (sizeof(R) == 4 && a.islands) hipLaunchKernelGGL((k_freq_sub<R, 1>), g, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL((k_freq<R, 0>), g, dim3(256), 0, s, a);
   if (sizeof(R) == 4 && a.islands) hipLaunchKernelGGL((k_freq<R, 1>), g, dim3(256), 0, s, a);
   return hipGetLastError();

@@ -40,7 +40,7 @@ class m1_config(ctypes.Structure):
                 ("c_tilde", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("recoil", ctypes.c_int32), ("doppler", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("fp64_tau", ctypes.c_double),
-                ("active_frac", ctypes.c_double)]
+                ("active_frac", ctypes.c_double), ("substep_rule", ctypes.c_int32)]
 
 
 class m1_fields(ctypes.Structure):
@@ -159,6 +159,7 @@ def make_config(p, prec="fp64", fp64_tau=float("inf")):
     c.prec = M1_FP32 if prec == "fp32" else M1_FP64
     c.fp64_tau = float(fp64_tau)
     c.active_frac = float(p.get("active_frac", 0.0))
+    c.substep_rule = int(p.get("substep_rule", 0))
     return c
 
 

@@ -48,7 +48,7 @@ def test_workspace_bytes_scale():
 
 
 @pytest.mark.parametrize("bad", ["geom", "nx", "ctilde", "cfl", "axis", "q", "active_neg",
-                                 "active_nan", "active_inf"])
+                                 "active_nan", "active_inf", "substep"])
 def test_config_validation(bad):
     p = inputs.config1()
     c = m1.make_config(p)
@@ -61,6 +61,7 @@ def test_config_validation(bad):
     if bad == "active_neg": c.active_frac = -1e-10
     if bad == "active_nan": c.active_frac = float("nan")
     if bad == "active_inf": c.active_frac = float("inf")
+    if bad == "substep": c.substep_rule = 2
     n = ctypes.c_int32()
     assert m1.lib().m1_num_bins(ctypes.byref(c), ctypes.byref(n)) == m1.M1_EINVAL
     assert len(m1.lib().m1_last_error()) > 0
@@ -155,6 +156,12 @@ def test_server_bookkeeping_without_device_work():
     rid = ctypes.c_int64()
     cfg = m1.make_config(small, "fp32")
     assert L.m1_server_submit(h, ctypes.byref(cfg), 1, 0.0, 100, ctypes.byref(rid)) == m1.M1_EINVAL
+    # a batched engine refuses the substep rule (single-grid stepping only)
+    cfg = m1.make_config(dict(small, substep_rule=1), "fp32")
+    assert L.m1_server_submit(h, ctypes.byref(cfg), 1, 1e-6, 100, ctypes.byref(rid)) == \
+        m1.M1_EUNSUPPORTED
+    m1.check(L.m1_server_stats(h, *(ctypes.byref(x) for x in (q, r, f, rounds, used, largest))))
+    assert q.value == 2                      # nothing queued
     m1.check(L.m1_server_free(h))
 
 

@@ -1,0 +1,92 @@
+"""GPU parity of the emission/absorption substeps under the 10 % energy rule
+(Section 2.1, step 2; m1_config.substep_rule).
+
+The emission of the parity problems is scaled up against e_floor so that the
+rule splits the step in hundreds of cells (up to ~150 substeps).  FP64: six
+steps against the oracle at 1e-12, on a case whose closest decision is more
+than 1e-11 (relative) away from the 10 % boundary, so both sides take the
+same substeps.  FP32: one step from a state shared with the oracle; the
+cells whose decisions all keep a 1e-3 margin are compared at the FP32 bar
+(1e-5 on E and F, 1e-4 on the force), the few others only checked for
+validity, since a ~1e-6 state difference may legitimately change a decision
+taken within it.
+"""
+import numpy as np
+import pytest
+
+from oracle import m1_oracle as M
+from paper_2606_02711_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+E_FLOOR = 4.0 * np.pi * 1.0e-15 / M.C_LIGHT
+
+
+def rel(a, b):
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(a - b)) / nb if nb > 0 else float(np.linalg.norm(a))
+
+
+def _problem(geom, nx, ny, seed, scale):
+    p = inputs.random_small(geom, nx, ny, seed, half_width=1e3, log_nHI=(-4.0, 1.0))
+    p["substep_rule"] = 1
+    ctdt = p["c_tilde"] * M.Oracle(p).dt
+    em = p["fields"]["emis"]
+    p["fields"]["emis"] = em * (E_FLOOR * M.C_LIGHT / ctdt) / np.mean(em) / scale
+    return p
+
+
+def test_substeps_fp64_parity():
+    from paper_2606_02711_amd import m1
+    p = _problem("cyl", 24, 20, 31, 1e-4)
+    o = M.Oracle(p)
+    steps, split, margin = 6, 0, np.inf
+    for _ in range(steps):
+        o.step(1)
+        split += int((o.substeps > 1).sum())
+        margin = min(margin, float(o.sub_margin.min()))
+    assert split > 1000 and margin > 1e-11, (split, margin)
+    print("[gpu] substeps fp64 cyl 24x20", flush=True)
+    g = m1.M1Grid(p, prec="fp64")
+    g.step(steps)
+    E, Fx, Fy = [t.cpu().numpy() for t in g.state()]
+    f = g.force().cpu().numpy()
+    errs = dict(E=rel(E, o.E), Fx=rel(Fx, o.Fx), Fy=rel(Fy, o.Fy), force=rel(f, o.force))
+    print("   rel-L2", errs, flush=True)
+    assert max(errs.values()) <= 1e-12, errs
+    g.free()
+
+
+@pytest.mark.parametrize("geom,nx,ny,seed", [("cyl", 24, 20, 31), ("cart", 21, 18, 32)])
+def test_substeps_fp32_one_step_from_shared_state(geom, nx, ny, seed):
+    from paper_2606_02711_amd import m1
+    p = _problem(geom, nx, ny, seed, 1e-4)
+    o = M.Oracle(p)
+    o.step(3)                                     # a developed state, shared below
+    E0, X0, Y0 = o.E.copy(), o.Fx.copy(), o.Fy.copy()
+    o.step(1)
+    assert int((o.substeps > 1).sum()) > 100
+    ok = o.sub_margin > 1e-3                      # cells whose decisions are safe in FP32
+    assert ok.mean() > 0.9, ok.mean()
+    print(f"[gpu] substeps fp32 {geom} {nx}x{ny}, {int(ok.sum())} safe cells", flush=True)
+    g = m1.M1Grid(p, prec="fp32")
+    import torch
+    g.set_state(*[torch.from_numpy(a).cuda() for a in (E0, X0, Y0)])
+    g.step(1)
+    E, Fx, Fy = [t.double().cpu().numpy() for t in g.state()]
+    f = g.force().cpu().numpy()
+    errs = dict(E=rel(E[:, ok], o.E[:, ok]), Fx=rel(Fx[:, ok], o.Fx[:, ok]),
+                Fy=rel(Fy[:, ok], o.Fy[:, ok]), force=rel(f[:, ok], o.force[:, ok]))
+    print("   rel-L2 on safe cells", errs, flush=True)
+    assert max(errs["E"], errs["Fx"], errs["Fy"]) <= 1e-5 and errs["force"] <= 1e-4, errs
+    assert np.all(np.isfinite(E)) and E.min() >= 0 and np.all(np.isfinite(f))
+    g.free()
+
+
+def test_substeps_refused_in_a_batch():
+    from paper_2606_02711_amd import m1
+    p = _problem("cart", 9, 12, 1, 1e-4)
+    g = m1.M1Grid(p, prec="fp32")
+    with pytest.raises(m1.M1Error):
+        m1.M1Batch([g], use_graph=False)
+    g.free()
