@@ -210,6 +210,25 @@ def run_active(ps, steps, warmup, thr=1e-10):
     return out
 
 
+def run_substeps(steps, L=1.0e38):
+    """The 10 % substep rule on the 512x1024 workload with its source at
+    L erg/s (FP32, from an empty state, while the energy density grows and the
+    rule splits steps), against one substep per step."""
+    import torch
+    from paper_2606_02711_amd import inputs, m1
+    p = inputs.config2()
+    p["fields"]["emis"] = p["fields"]["emis"] * L
+    out = {"luminosity_erg_s": L, "steps": steps}
+    for rule in (0, 1):
+        log(f"[bench] substeps: rule {rule}")
+        g = m1.M1Grid(dict(p, substep_rule=rule), prec="fp32")
+        a, c = g.step_profiled(steps)
+        out["ms_per_step_rule" if rule else "ms_per_step_one_substep"] = (a + c) / steps
+        g.free()
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_large(steps, warmup):
     """4096 x 8192 cylindrical cloud in FP32, the force density copied out
     (to device arrays) after every step."""
@@ -297,6 +316,8 @@ def main():
                     help="steps of the 64-grid batch workload (0 skips it)")
     ap.add_argument("--active-steps", type=int, default=200,
                     help="timed steps of the active-bin workload (0 skips it)")
+    ap.add_argument("--substep-steps", type=int, default=200,
+                    help="steps of the substep-rule workload (0 skips it)")
     ap.add_argument("--large-steps", type=int, default=20,
                     help="timed steps of the 4096 x 8192 grid (0 skips it)")
     ap.add_argument("--serve-seconds", type=float, default=30.0,
@@ -345,8 +366,8 @@ def main():
         print(json.dumps({"batch_64_grids": rb}), flush=True)
         return
     if args.active_only:
-        print(json.dumps({"active_bins": run_active(inputs.config3(), args.active_steps, 100)}),
-              flush=True)
+        print(json.dumps({"active_bins": run_active(inputs.config3(), args.active_steps, 100),
+                          "substeps": run_substeps(args.substep_steps)}), flush=True)
         return
     copy_gbs = copy_bandwidth()
     log(f"[bench] device copy: {copy_gbs:.0f} GB/s")
@@ -423,6 +444,8 @@ def main():
             "tile_bins": rb["tile_bins"], "tuning_ms_per_step": rb["tuning_ms_per_step"]}
     if args.active_steps > 0:
         out["active_bins"] = run_active(inputs.config3(), args.active_steps, 100)
+    if args.substep_steps > 0:
+        out["substeps"] = run_substeps(args.substep_steps)
     if args.large_steps > 0:
         out["large_grid"] = run_large(args.large_steps, 2)
     if args.serve_seconds > 0:
