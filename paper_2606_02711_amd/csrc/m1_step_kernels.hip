@@ -126,6 +126,7 @@ __device__ __forceinline__ bool ghost_source(int ii, int jj, int nx, int ny, con
 }
 
 constexpr int kRingPerLane = (kRX * kRY + 255) / 256;   // 3
+constexpr int kStagePerLane = (kPX * kPY + 255) / 256;  // 3
 
 // Runs of faces: 128 lanes take the kTY x (kTX + 1) x-faces, 128 the
 // kTX x (kTY + 1) y-faces, so each lane walks 4-5 faces along one line.
@@ -335,24 +336,36 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
       }
       continue;
     }
-    // (1) stage E and f of the padded tile, and alpha_F of the ring
-    for (int e = tid; e < kPX * kPY; e += 256) {
-      const int v = S.src[e];
-      R ev = R(0), fxv = R(0), fyv = R(0);
-      if (v >= 0) {
-        const int q = v >> 2;
-        ev = Ek[q];
-        fxv = Xk[q];
-        fyv = Yk[q];
-        fxv = (v & 1) ? -fxv : fxv;
-        fyv = (v & 2) ? -fyv : fyv;
+    // (1) stage E and f of the padded tile, and alpha_F of the ring.  Every
+    // load of a lane is issued before the first of them is used (a vacuum
+    // ghost reads cell 0 of the bin and drops it), so the block waits on
+    // memory once per bin rather than once per entry.
+    int sv[kStagePerLane];
+    R ev[kStagePerLane], xv[kStagePerLane], yv[kStagePerLane], hr[kRingPerLane];
+#pragma unroll
+    for (int m = 0; m < kStagePerLane; ++m) {
+      const int e = tid + 256 * m;
+      sv[m] = e < kPX * kPY ? S.src[e] : -1;
+      const int q = sv[m] >= 0 ? sv[m] >> 2 : 0;
+      ev[m] = Ek[q];
+      xv[m] = Xk[q];
+      yv[m] = Yk[q];
+    }
+#pragma unroll
+    for (int m = 0; m < kRingPerLane; ++m) hr[m] = hb[(size_t)rcls[m] * nb];
+#pragma unroll
+    for (int m = 0; m < kStagePerLane; ++m) {
+      const int e = tid + 256 * m, v = sv[m];
+      if (e < kPX * kPY) {
+        (&S.E[0][0])[e] = v >= 0 ? ev[m] : R(0);
+        (&S.fx[0][0])[e] = v < 0 ? R(0) : ((v & 1) ? -xv[m] : xv[m]);
+        (&S.fy[0][0])[e] = v < 0 ? R(0) : ((v & 2) ? -yv[m] : yv[m]);
       }
-      (&S.E[0][0])[e] = ev; (&S.fx[0][0])[e] = fxv; (&S.fy[0][0])[e] = fyv;
     }
 #pragma unroll
     for (int m = 0; m < kRingPerLane; ++m) {
       const int e = tid + 256 * m;
-      if (e < kRX * kRY) (&S.aF[0][0])[e] = ral[m] * hb[(size_t)rcls[m] * nb] + racF[m];
+      if (e < kRX * kRY) (&S.aF[0][0])[e] = ral[m] * hr[m] + racF[m];
     }
     __syncthreads();
     // (2) every face of the tile once, in runs of 4-5 consecutive faces along
