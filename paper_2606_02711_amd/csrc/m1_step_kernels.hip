@@ -353,6 +353,12 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
     }
 #pragma unroll
     for (int m = 0; m < kRingPerLane; ++m) hr[m] = hb[(size_t)rcls[m] * nb];
+    R hcell[2], pcell[2];                 // profiles of the owned cells for step (3)
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      hcell[m] = hb[(size_t)ccls[m] * nb];
+      pcell[m] = a.phi[(size_t)ccls[m] * nb + k];
+    }
 #pragma unroll
     for (int m = 0; m < kStagePerLane; ++m) {
       const int e = tid + 256 * m, v = sv[m];
@@ -401,15 +407,14 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
       Xs = pos ? Xs * cl : R(0);
       Ys = pos ? Ys * cl : R(0);
       Es = pos ? Es : R(0);
-      const int cc = ccls[m];
-      const R hC = hb[(size_t)cc * nb];
+      const R hC = hcell[m];
       const R aFC = S.aF[lj + 1][tx + 1];
       const size_t q = koff + cidx[m];
       if constexpr (SUB) {
         sink.put(a, m, k, q, hC, Es, Xs, Ys);
         continue;
       }
-      const R src = em[m] * a.phi[(size_t)cc * nb + k];
+      const R src = em[m] * pcell[m];
       const R kE = acabs[m] + pda[m] * hC;
       const R dF = frcp(R(1) + ctdt * aFC);
       sink.put(a, m, k, q, hC, (Es + ctdt * src) * frcp(R(1) + ctdt * kE), Xs * dF, Ys * dF);
