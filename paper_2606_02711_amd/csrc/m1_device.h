@@ -140,7 +140,7 @@ template <typename R>
 __device__ __forceinline__ Eddington<R> closure_f(R fx, R fy) {
   const R xx2 = fx * fx, yy2 = fy * fy;
   R f2 = xx2 + yy2;
-  f2 = f2 > R(1) ? R(1) : f2;
+  f2 = fmin(f2, R(1));
   const R s = fsqrt(R(4) - R(3) * f2);    // in [1, 2]
   const R g = R(3) * frcp(R(2) + s);
   const R iso = (s - R(1)) * R(1.0 / 3.0);

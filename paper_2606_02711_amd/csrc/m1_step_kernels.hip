@@ -156,6 +156,10 @@ __device__ __forceinline__ void face_run(AdvShared<R>& S, int line, int c0, int 
   R dE = (e2 - e1) * i12, dX = (x2 - x1) * i12, dY = (y2 - y1) * i12;
   R sE = minmod((e1 - e0) * i01, dE), sX = minmod((x1 - x0) * i01, dX),
     sY = minmod((y1 - y0) * i01, dY);
+  // double: two faces per iteration (no register rotation); float: one (the
+  // unrolled loop spills at five waves per SIMD)
+  constexpr int kUnroll = sizeof(R) == 8 ? 2 : 1;
+#pragma unroll kUnroll
   for (int c = c0; c < c1; ++c) {
     R e3, x3, y3;
     ld(c + 3, e3, x3, y3);
