@@ -129,10 +129,14 @@ constexpr int kRingPerLane = (kRX * kRY + 255) / 256;   // 3
 constexpr int kStagePerLane = (kPX * kPY + 255) / 256;  // 3
 
 // Runs of faces: 128 lanes take the kTY x (kTX + 1) x-faces, 128 the
-// kTX x (kTY + 1) y-faces, so each lane walks 4-5 faces along one line.
+// kTX x (kTY + 1) y-faces, each lane four faces along one line; the last face
+// of every line is taken by a second, one-face run (x: wave 0, y: wave 2), so
+// no lane of a wave walks a longer run than the others.
 constexpr int kRunsX = 128 / kTY;     // runs per tile row
 constexpr int kRunsY = 128 / kTX;     // runs per tile column
 static_assert(128 % kTY == 0 && 128 % kTX == 0, "runs must tile the faces");
+constexpr int kRun = 4;               // faces per run; the last face of a line apart
+static_assert(kRunsX * kRun == kTX && kRunsY * kRun == kTY, "runs of four cover a line but its last face");
 
 // Faces [c0, c1) along line `line` (N = 0: tile row, faces between padded
 // columns c+1 and c+2; N = 1: tile column, faces between padded rows c+1 and
@@ -378,15 +382,17 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
       if (e < kRX * kRY) (&S.aF[0][0])[e] = ral[m] * hr[m] + racF[m];
     }
     __syncthreads();
-    // (2) every face of the tile once, in runs of 4-5 consecutive faces along
-    // a line: waves 0-1 the x-faces (runs along rows), waves 2-3 the y-faces
-    // (runs along columns).
+    // (2) every face of the tile once, in runs of four consecutive faces
+    // along a line: waves 0-1 the x-faces (runs along rows), waves 2-3 the
+    // y-faces (runs along columns); then the last face of each line.
     if (tid < 128) {
       const int r = tid / kRunsX, s = tid % kRunsX;
-      face_run<R, 0>(S, r, s * (kTX + 1) / kRunsX, (s + 1) * (kTX + 1) / kRunsX);
+      face_run<R, 0>(S, r, s * kRun, s * kRun + kRun);
+      if (tid < kTY) face_run<R, 0>(S, tid, kTX, kTX + 1);     // last face of row tid
     } else {
       const int u = tid - 128, c = u / kRunsY, s = u % kRunsY;
-      face_run<R, 1>(S, c, s * (kTY + 1) / kRunsY, (s + 1) * (kTY + 1) / kRunsY);
+      face_run<R, 1>(S, c, s * kRun, s * kRun + kRun);
+      if (u < kTX) face_run<R, 1>(S, u, kTY, kTY + 1);         // last face of column u
     }
     __syncthreads();
     // (3) update, causality clamp, implicit source
