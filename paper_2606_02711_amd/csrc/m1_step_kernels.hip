@@ -186,23 +186,33 @@ __device__ __forceinline__ void face_run(AdvShared<R>& S, int line, int c0, int 
   }
 }
 
+// Element c of a bin plane starting at `plane`, addressed as the plane (a
+// block-uniform pointer) plus a 32-bit byte offset: a grid holds at most 2^29
+// cells, so c * sizeof(R) < 2^32 and the scalar-base + vector-offset form of
+// the memory instructions applies.
+template <typename R>
+__device__ __forceinline__ R* plane_at(R* plane, unsigned c) {
+  return (R*)((char*)plane + c * (unsigned)sizeof(R));
+}
+
 // Where the post-source state E**, F** of an owned cell goes: to the output
 // state (the frequency step runs in its own kernel), or into the frequency
-// step of the same block (fused).
+// step of the same block (fused).  A cell is addressed by the offset koff of
+// its bin plane and its index c in the plane.
 template <typename R>
 struct WriteSink {
-  __device__ __forceinline__ void init(const GridArgs<R>&, const bool*, const size_t*,
+  __device__ __forceinline__ void init(const GridArgs<R>&, const bool*, const unsigned*,
                                        const int*) {}
-  __device__ __forceinline__ void put(const GridArgs<R>& a, int, int, size_t q, R h, R E, R X,
-                                      R Y) {
+  __device__ __forceinline__ void put(const GridArgs<R>& a, int, int, size_t koff, unsigned c,
+                                      R h, R E, R X, R Y) {
     (void)h;
     R fxo, fyo;
     reduced_flux<R>(E, X, Y, fxo, fyo);
-    __builtin_nontemporal_store(E, &a.Eo[q]);
-    __builtin_nontemporal_store(fxo, &a.fxo[q]);
-    __builtin_nontemporal_store(fyo, &a.fyo[q]);
+    __builtin_nontemporal_store(E, plane_at(a.Eo + koff, c));
+    __builtin_nontemporal_store(fxo, plane_at(a.fxo + koff, c));
+    __builtin_nontemporal_store(fyo, plane_at(a.fyo + koff, c));
   }
-  __device__ __forceinline__ void finish(const GridArgs<R>&, const bool*, const size_t*) {}
+  __device__ __forceinline__ void finish(const GridArgs<R>&, const bool*, const unsigned*) {}
 };
 
 // One tile x run of bins (logical block L of grid a); BK = 0: all bins.
@@ -275,7 +285,7 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
   // ---- per-lane cells: (tx, ty) and (tx, ty + kRowsPerPass)
   const int tx = tid % kTX, ty = tid / kTX;
   bool own[2];
-  size_t cidx[2];
+  unsigned cidx[2];                 // cell index in a bin plane (< 2^29)
   int ccls[2];
   R acabs[2], pda[2], em[2], gxx[2], gyy[2], gxy[2], gpp[2], cy[2];
   const int gi = x0 + tx;
@@ -286,7 +296,7 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
   for (int m = 0; m < 2; ++m) {
     const int gj = y0 + ty + kRowsPerPass * m;
     own[m] = colok && gj < ny;
-    cidx[m] = own[m] ? (size_t)gj * nx + gi : 0;
+    cidx[m] = own[m] ? (unsigned)(gj * nx + gi) : 0u;
     const size_t c = cidx[m];
     ccls[m] = own[m] ? a.cls[c] : 0;
     acabs[m] = own[m] ? a.acabs[c] : R(0);
@@ -327,19 +337,19 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
 #pragma unroll
       for (int m = 0; m < 2; ++m) {
         if (!own[m]) continue;
-        const size_t c = cidx[m];
+        const unsigned c = cidx[m];
         const R EC = Ek[c], fxc = Xk[c], fyc = Yk[c];
         const int cc = ccls[m];
         const R hC = hb[(size_t)cc * nb];
         if constexpr (SUB) {
-          sink.put(a, m, k, koff + c, hC, EC, fxc * EC, fyc * EC);
+          sink.put(a, m, k, koff, c, hC, EC, fxc * EC, fyc * EC);
           continue;
         }
         const R aFC = a.alpha[c] * hC + a.acF[c];
         const R src = em[m] * a.phi[(size_t)cc * nb + k];
         const R kE = acabs[m] + pda[m] * hC;
         const R dF = frcp(R(1) + ctdt * aFC);
-        sink.put(a, m, k, koff + c, hC, (EC + ctdt * src) * frcp(R(1) + ctdt * kE),
+        sink.put(a, m, k, koff, c, hC, (EC + ctdt * src) * frcp(R(1) + ctdt * kE),
                  fxc * EC * dF, fyc * EC * dF);
       }
       continue;
@@ -419,15 +429,15 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
       Es = pos ? Es : R(0);
       const R hC = hcell[m];
       const R aFC = S.aF[lj + 1][tx + 1];
-      const size_t q = koff + cidx[m];
       if constexpr (SUB) {
-        sink.put(a, m, k, q, hC, Es, Xs, Ys);
+        sink.put(a, m, k, koff, cidx[m], hC, Es, Xs, Ys);
         continue;
       }
       const R src = em[m] * pcell[m];
       const R kE = acabs[m] + pda[m] * hC;
       const R dF = frcp(R(1) + ctdt * aFC);
-      sink.put(a, m, k, q, hC, (Es + ctdt * src) * frcp(R(1) + ctdt * kE), Xs * dF, Ys * dF);
+      sink.put(a, m, k, koff, cidx[m], hC, (Es + ctdt * src) * frcp(R(1) + ctdt * kE), Xs * dF,
+               Ys * dF);
     }
     __syncthreads();
   }
@@ -941,7 +951,7 @@ struct FusedSink {
   FreqRow row[2];
 
   __device__ __forceinline__ void init(const GridArgs<float>& a, const bool* own,
-                                       const size_t* cidx, const int* ccls) {
+                                       const unsigned* cidx, const int* ccls) {
     const size_t nc = (size_t)a.nx * a.ny;
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
@@ -965,8 +975,9 @@ struct FusedSink {
     }
   }
 
-  __device__ __forceinline__ void put(const GridArgs<float>& a, int m, int k, size_t q, float h,
-                                      float E, float X, float Y) {
+  __device__ __forceinline__ void put(const GridArgs<float>& a, int m, int k, size_t koff,
+                                      unsigned c, float h, float E, float X, float Y) {
+    const size_t q = koff + c;
     float fxo, fyo;
     reduced_flux<float>(E, X, Y, fxo, fyo);
     __builtin_nontemporal_store(fxo, &a.fxo[q]);
@@ -1001,7 +1012,7 @@ struct FusedSink {
   }
 
   __device__ __forceinline__ void finish(const GridArgs<float>& a, const bool* own,
-                                         const size_t* cidx) {
+                                         const unsigned* cidx) {
     const size_t nc = (size_t)a.nx * a.ny;
     const int nb = a.nb;
 #pragma unroll
