@@ -160,9 +160,9 @@ __device__ __forceinline__ void face_run(AdvShared<R>& S, int line, int c0, int 
   R dE = (e2 - e1) * i12, dX = (x2 - x1) * i12, dY = (y2 - y1) * i12;
   R sE = minmod((e1 - e0) * i01, dE), sX = minmod((x1 - x0) * i01, dX),
     sY = minmod((y1 - y0) * i01, dY);
-  // double: two faces per iteration (no register rotation); float: one (the
-  // unrolled loop spills at five waves per SIMD)
-  constexpr int kUnroll = sizeof(R) == 8 ? 2 : 1;
+  // unrolled (no register rotation between faces, constant LDS offsets):
+  // float fully (four waves per SIMD leave it the registers), double by two
+  constexpr int kUnroll = sizeof(R) == 8 ? 2 : 4;
 #pragma unroll kUnroll
   for (int c = c0; c < c1; ++c) {
     R e3, x3, y3;
@@ -444,9 +444,10 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
   sink.finish(a, own, cidx);
 }
 
-// Float: five waves per SIMD, the block count LDS allows per CU.
+// Float: four waves per SIMD (128 registers), which the fully unrolled face
+// runs need; at five (the block count LDS would allow) they spill.
 template <typename R>
-constexpr int kAdvectWaves = sizeof(R) == 4 ? 5 : 1;
+constexpr int kAdvectWaves = sizeof(R) == 4 ? 4 : 1;
 
 template <typename R, int BK, bool AB, bool SUB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kAdvectWaves<R>)))
