@@ -69,6 +69,34 @@ def sigma0(T):
     return 5.9e-14 / np.sqrt(np.asarray(T, dtype=np.float64) / 1.0e4)
 
 
+# ------------------------------------------------ dynamic reduced speed of light
+EPS_RSL = 4.0                    # Section 2.1 default
+C_TILDE_MIN = 1.0e7              # 100 km/s
+
+
+def dynamic_c_tilde(p, cs, c_prev=0.0):
+    """The reduced speed of light chosen from the medium (Section 2.1):
+    c_dyn = eps_RSL max over cells of max[1, (a_v tau_0)^(1/3) f_abs] max(|u|, c_s),
+    f_abs = 1 / (1 + (a_v tau_0)^(1/3) tau_c + 0.6 p_d tau_0), where tau_0 is
+    the line-centre depth alpha max(dR, dZ) and tau_c the continuum absorption
+    depth alpha_c (1 - omega) max(dR, dZ) of the cell; then
+    c_tilde = min(max(100 km/s, c_dyn), c), and with a previous value c_prev > 0
+    at most a 25 % decrease or a factor 4 increase from it."""
+    f = p["fields"]
+    dmax = max((p["x1"] - p["x0"]) / p["nx"], (p["y1"] - p["y0"]) / p["ny"])
+    T = np.asarray(f["T"], dtype=np.float64)
+    tau0 = np.asarray(f["n_HI"], dtype=np.float64) * sigma0(T) * dmax
+    tauc = np.asarray(f["alpha_abs"], dtype=np.float64) * dmax
+    at = np.cbrt(voigt_a(T) * tau0)
+    fabs = 1.0 / (1.0 + at * tauc + 0.6 * np.asarray(f["p_d"], dtype=np.float64) * tau0)
+    speed = np.maximum(np.hypot(f["u_x"], f["u_y"]), np.asarray(cs, dtype=np.float64))
+    c_dyn = EPS_RSL * float(np.max(np.maximum(1.0, at * fabs) * speed))
+    c = min(max(C_TILDE_MIN, c_dyn), C_LIGHT)
+    if c_prev > 0.0:
+        c = min(max(c, 0.75 * c_prev), 4.0 * c_prev)
+    return c
+
+
 # ---------------------------------------------------------- frequency grid
 def frequency_grid(T_min=30.0, q=1.1, half_width=1.0e5):
     """Symmetric geometric grid in dnu = nu - nu_Lya (Section 2.1).
