@@ -144,6 +144,21 @@ int32_t m1_num_bins(const m1_config *cfg, int32_t *n_nu);
 int32_t m1_workspace_bytes(const m1_config *cfg, int64_t n_temp_classes, size_t *bytes);
 int32_t m1_count_temperature_classes(const double *T_host, int64_t n, int64_t *n_classes);
 
+/* The reduced speed of light chosen from the medium (Section 2.1, dynamic
+ * RSL): c_dyn = 4 max over cells of max[1, (a_v tau_0)^(1/3) f_abs] max(|u|, c_s),
+ * f_abs = 1 / (1 + (a_v tau_0)^(1/3) tau_c + 0.6 p_d tau_0), with tau_0 the
+ * line-centre depth n_HI sigma_0(T) dmax and tau_c = alpha_abs dmax (dmax the
+ * larger cell side of cfg); then c_tilde = min(max(100 km/s, c_dyn), c), and,
+ * when c_prev > 0 (the previous value), at most a 25 % decrease or a factor 4
+ * increase from it.  fields: device arrays (on_device = 1; emis and
+ * alpha_flux unused); d_cs: device array of sound speeds [cm/s], ncell
+ * doubles; d_work: at least 8192 bytes of caller device memory, 8-byte
+ * aligned.  Runs on `stream` (NULL = default) and waits for it; *c_tilde
+ * [cm/s] receives the result.  M1_EINVAL for NULL or host arrays, a NaN
+ * c_prev or a non-finite term (T <= 0). */
+int32_t m1_dynamic_c_tilde(const m1_config *cfg, const m1_fields *fields, const double *d_cs,
+                           double c_prev, void *d_work, void *stream, double *c_tilde);
+
 /* Validates cfg and fields, lays out the caller-owned workspace d_ws of
  * ws_bytes (>= m1_workspace_bytes for the field's class count, 256-byte
  * aligned), runs the set-up kernels (frequency grid, bin-averaged Voigt

@@ -106,6 +106,9 @@ struct Layout {
 
 constexpr int kResBlocks = 1024;
 constexpr int kMaxActiveBins = 8192;    // the selection keeps W_k in LDS (64 KB)
+constexpr int kDynRslBlocks = 1024;     // block maxima of m1_dynamic_c_tilde (8 KiB of d_work)
+constexpr double kEpsRsl = 4.0;         // Section 2.1 defaults of the dynamic
+constexpr double kCTildeMin = 1.0e7;    // reduced speed of light (100 km/s)
 
 // Device bytes the set-up needs for temporaries: the input fields (when they
 // come from the host), class sums and tables, face velocities in double.
@@ -533,6 +536,36 @@ int32_t m1_num_bins(const m1_config* cfg, int32_t* n_nu) {
   int st = validate_config(cfg, &nb);
   if (st) return st;
   *n_nu = nb;
+  return M1_OK;
+}
+
+int32_t m1_dynamic_c_tilde(const m1_config* cfg, const m1_fields* f, const double* d_cs,
+                           double c_prev, void* d_work, void* stream, double* c_tilde) {
+  int st = validate_config(cfg, nullptr);
+  if (st) return st;
+  if (!f || !d_cs || !d_work || !c_tilde) return fail(M1_EINVAL, "NULL argument");
+  if (!f->on_device) return fail(M1_EINVAL, "fields must be device arrays (on_device = 1)");
+  if (!f->n_HI || !f->T || !f->u_x || !f->u_y || !f->alpha_abs || !f->p_d)
+    return fail(M1_EINVAL, "a field array is NULL");
+  if (((uintptr_t)d_work) & 7) return fail(M1_EINVAL, "d_work not 8-byte aligned");
+  if (!(c_prev >= 0.0) || !isfinite(c_prev)) return fail(M1_EINVAL, "c_prev must be finite and >= 0");
+  const size_t nc = (size_t)cfg->nx * cfg->ny;
+  const double dmax = std::max((cfg->x1 - cfg->x0) / cfg->nx, (cfg->y1 - cfg->y0) / cfg->ny);
+  CellInputs in{f->n_HI, f->T, f->u_x, f->u_y, f->alpha_abs, f->alpha_flux, f->p_d, f->emis};
+  hipStream_t s = (hipStream_t)stream;
+  const int nblk = (int)std::min<size_t>((nc + 255) / 256, kDynRslBlocks);
+  HIPCHK(launch_dyn_rsl(in, d_cs, nc, dmax, (double*)d_work, nblk, s));
+  std::vector<double> part(nblk);
+  HIPCHK(hipMemcpyAsync(part.data(), d_work, nblk * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double m = 0.0;
+  for (double v : part) {
+    if (v != v) return fail(M1_EINVAL, "non-finite trapping term (check T > 0 and the opacities)");
+    m = std::max(m, v);
+  }
+  double c = std::min(std::max(kCTildeMin, kEpsRsl * m), kC);
+  if (c_prev > 0.0) c = std::min(std::max(c, 0.75 * c_prev), 4.0 * c_prev);
+  *c_tilde = c;
   return M1_OK;
 }
 

@@ -86,6 +86,10 @@ hipError_t launch_velocity(const CellInputs& in, int nx, int ny, int geom, const
                            const double* xe, const double* ye, double* tmp, R* ufx, R* ufy,
                            R* grad, hipStream_t s);
 
+// Block maxima of the dynamic reduced-speed-of-light term (cs: sound speed).
+hipError_t launch_dyn_rsl(const CellInputs& in, const double* cs, size_t nc, double dmax,
+                          double* partial, int nblk, hipStream_t s);
+
 // Block partials of max |u|, max emis, min T (for dt and the state scale).
 hipError_t launch_init_reduce(const CellInputs& in, size_t nc, double* partial, int nblk,
                               hipStream_t s);

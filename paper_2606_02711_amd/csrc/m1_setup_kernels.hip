@@ -212,6 +212,47 @@ hipError_t launch_init_reduce(const CellInputs& in, size_t nc, double* partial, 
   return hipGetLastError();
 }
 
+// Dynamic reduced speed of light (Section 2.1): block maxima over the cells
+// of max[1, (a_v tau_0)^(1/3) f_abs] max(|u|, c_s), with tau_0 and tau_c the
+// line-centre and continuum-absorption depths over the larger cell side dmax
+// and f_abs = 1 / (1 + (a_v tau_0)^(1/3) tau_c + 0.6 p_d tau_0).  A maximum
+// does not depend on the order of the reduction.  A cell whose term is not a
+// number (T <= 0, a negative depth) makes the block's result NaN, which the
+// host reports.
+__device__ __forceinline__ double nan_max(double a, double b) {
+  return (a != a || b != b) ? __builtin_nan("") : fmax(a, b);
+}
+
+__global__ __launch_bounds__(256) void k_dyn_rsl(CellInputs in, const double* __restrict__ cs,
+                                                 size_t nc, double dmax,
+                                                 double* __restrict__ partial) {
+  __shared__ double sm[256];
+  double best = 0.0;
+  for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < nc; c += (size_t)gridDim.x * 256) {
+    const double t4 = sqrt(in.T[c] / 1.0e4);
+    const double tau0 = in.n_HI[c] * (5.9e-14 / t4) * dmax;
+    const double tauc = in.acabs[c] * dmax;
+    const double at = cbrt((4.7e-4 / t4) * tau0);
+    const double fabs_ = 1.0 / (1.0 + at * tauc + 0.6 * in.pd[c] * tau0);
+    const double u = sqrt(in.ux[c] * in.ux[c] + in.uy[c] * in.uy[c]);
+    const double term = nan_max(1.0, at * fabs_) * nan_max(u, cs[c]);
+    best = nan_max(best, term);
+  }
+  sm[threadIdx.x] = best;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sm[threadIdx.x] = nan_max(sm[threadIdx.x], sm[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sm[0];
+}
+
+hipError_t launch_dyn_rsl(const CellInputs& in, const double* cs, size_t nc, double dmax,
+                          double* partial, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_dyn_rsl, dim3(nblk), dim3(256), 0, s, in, cs, nc, dmax, partial);
+  return hipGetLastError();
+}
+
 template hipError_t launch_class_profiles<float>(const double*, const double*, int64_t,
                                                  const double*, const double*, int,
                                                  const double*, double*, float*, float*,

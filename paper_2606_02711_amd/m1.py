@@ -93,6 +93,7 @@ def lib():
         "m1_get_state_region": (I32, [VP, I32, I32, I32, I32, VP, VP, VP]),
         "m1_get_info": (I32, [VP, P(D), P(I32), P(I32), P(I64), P(I32)]),
         "m1_active_bins": (I32, [VP, VP, P(I32)]),
+        "m1_dynamic_c_tilde": (I32, [P(m1_config), P(m1_fields), VP, D, VP, VP, P(D)]),
         "m1_batch_workspace_bytes": (I32, [P(VP), I32, P(ctypes.c_size_t)]),
         "m1_batch_init": (I32, [P(VP), I32, VP, ctypes.c_size_t, I32, P(VP)]),
         "m1_batch_step": (I32, [VP, I32]),
@@ -127,7 +128,7 @@ def exported_symbols():
     return ["m1_default_config", "m1_num_bins", "m1_workspace_bytes",
             "m1_count_temperature_classes", "m1_init", "m1_step", "m1_force",
             "m1_solve_steady", "m1_residual", "m1_get_state", "m1_set_state", "m1_get_state_region", "m1_get_info",
-            "m1_active_bins",
+            "m1_active_bins", "m1_dynamic_c_tilde",
             "m1_batch_workspace_bytes", "m1_batch_init", "m1_batch_step", "m1_batch_info",
             "m1_batch_free", "m1_batch_set_tile", "m1_batch_workspace_bound",
             "m1_server_create", "m1_server_submit", "m1_server_run", "m1_server_poll",
@@ -183,6 +184,27 @@ def count_temperature_classes(T):
 
 
 FIELD_ORDER = ("n_HI", "T", "u_x", "u_y", "alpha_abs", "alpha_flux", "p_d", "emis")
+
+
+def dynamic_c_tilde(p, cs, c_prev=0.0):
+    """The reduced speed of light the paper chooses for the medium of p with
+    sound speeds cs [cm/s] (m1_dynamic_c_tilde), the fields copied to the GPU."""
+    torch = _torch()
+    cfg = make_config(p)
+    f = p["fields"]
+    dev = [torch.as_tensor(np.ascontiguousarray(f[n], dtype=np.float64).ravel(), device="cuda")
+           for n in FIELD_ORDER]
+    d_cs = torch.as_tensor(np.ascontiguousarray(cs, dtype=np.float64).ravel(), device="cuda")
+    work = torch.empty(1024, dtype=torch.float64, device="cuda")
+    fl = m1_fields()
+    for n, a in zip(FIELD_ORDER, dev):
+        setattr(fl, n, a.data_ptr())
+    fl.on_device = 1
+    torch.cuda.current_stream().synchronize()      # inputs written on torch's stream
+    out = ctypes.c_double()
+    check(lib().m1_dynamic_c_tilde(ctypes.byref(cfg), ctypes.byref(fl), d_cs.data_ptr(),
+                                   float(c_prev), work.data_ptr(), None, ctypes.byref(out)))
+    return out.value
 
 
 def _torch():

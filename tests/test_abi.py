@@ -193,3 +193,28 @@ def test_active_bin_config_accepted_and_sized():
     assert c.active_frac == 1e-10
     assert m1.num_bins(c) == 194
     assert m1.workspace_bytes(c, 1) == m1.workspace_bytes(m1.make_config(inputs.config1(), "fp32"), 1)
+
+
+def test_dynamic_c_tilde_argument_checks_without_device_work():
+    """Host arrays, NULL pointers and a NaN previous value are refused before
+    any device call."""
+    import ctypes
+    L = m1.lib()
+    p = inputs.config1()
+    cfg = m1.make_config(p)
+    fl = m1.m1_fields()
+    out = ctypes.c_double()
+    fake = 1 << 40                         # never dereferenced
+    for n in m1.FIELD_ORDER:
+        setattr(fl, n, fake)
+    fl.on_device = 0
+    assert L.m1_dynamic_c_tilde(ctypes.byref(cfg), ctypes.byref(fl), fake, 0.0, fake, None,
+                                ctypes.byref(out)) == m1.M1_EINVAL
+    fl.on_device = 1
+    assert L.m1_dynamic_c_tilde(ctypes.byref(cfg), ctypes.byref(fl), None, 0.0, fake, None,
+                                ctypes.byref(out)) == m1.M1_EINVAL
+    assert L.m1_dynamic_c_tilde(ctypes.byref(cfg), ctypes.byref(fl), fake, float("nan"), fake,
+                                None, ctypes.byref(out)) == m1.M1_EINVAL
+    fl.T = None
+    assert L.m1_dynamic_c_tilde(ctypes.byref(cfg), ctypes.byref(fl), fake, 0.0, fake, None,
+                                ctypes.byref(out)) == m1.M1_EINVAL
