@@ -894,7 +894,7 @@ def test_substeps_that_all_pass_equal_one_substep():
 
 
 # -------------------------------- dynamic reduced speed of light (Section 2.1)
-def _uniform_medium(T, n_HI, u=0.0, acabs=0.0, pd=0.0):
+def _rsl_medium(T, n_HI, u=0.0, acabs=0.0, pd=0.0):
     return make_problem("cart", 8, 6, 1.0e16, ("vacuum",) * 4, T=T, n_HI=n_HI, ux=u,
                         acabs=acabs, pd=pd)
 
@@ -904,12 +904,12 @@ def test_dynamic_c_tilde_thick_line_closed_form():
     tau_0 = 1e6 over a cell, no dust, no destruction: f_abs = 1 and
     c_dyn = 4 (470)^(1/3) max(|u|, c_s)."""
     n = 1.0e6 / (5.9e-14 * 1.0e16)
-    p = _uniform_medium(1.0e4, n, u=1.0e6)
+    p = _rsl_medium(1.0e4, n, u=1.0e6)
     cs = np.full((6, 8), 2.0e6)
     want = 4.0 * 470.0 ** (1.0 / 3.0) * 2.0e6
     assert M.dynamic_c_tilde(p, cs) == pytest.approx(want, rel=1e-13)
     # the gas speed counts when it exceeds the sound speed
-    p = _uniform_medium(1.0e4, n, u=3.0e6)
+    p = _rsl_medium(1.0e4, n, u=3.0e6)
     assert M.dynamic_c_tilde(p, cs) == pytest.approx(4.0 * 470.0 ** (1.0 / 3.0) * 3.0e6,
                                                      rel=1e-13)
 
@@ -921,18 +921,18 @@ def test_dynamic_c_tilde_absorption_and_destruction():
     n = 1.0e6 / (5.9e-14 * 1.0e16)
     at = 470.0 ** (1.0 / 3.0)
     cs = np.full((6, 8), 5.0e6)
-    p = _uniform_medium(1.0e4, n, acabs=1000.0 / at / 1.0e16)
+    p = _rsl_medium(1.0e4, n, acabs=1000.0 / at / 1.0e16)
     assert M.dynamic_c_tilde(p, cs) == pytest.approx(2.0e7, rel=1e-13)
-    p = _uniform_medium(1.0e4, n, pd=1000.0 / 0.6 / 1.0e6)
+    p = _rsl_medium(1.0e4, n, pd=1000.0 / 0.6 / 1.0e6)
     assert M.dynamic_c_tilde(p, cs) == pytest.approx(2.0e7, rel=1e-13)
     # halfway: f_abs = 1/2 with tau_c at = 1
-    p = _uniform_medium(1.0e4, n, acabs=1.0 / at / 1.0e16)
+    p = _rsl_medium(1.0e4, n, acabs=1.0 / at / 1.0e16)
     assert M.dynamic_c_tilde(p, cs) == pytest.approx(4.0 * 0.5 * at * 5.0e6, rel=1e-13)
 
 
 def test_dynamic_c_tilde_bounds_and_rate_limits():
     """100 km/s floor, c ceiling, at most -25 % or x4 from the previous value."""
-    cold = _uniform_medium(1.0e4, 0.0)                  # no gas: c_dyn = 4 c_s
+    cold = _rsl_medium(1.0e4, 0.0)                  # no gas: c_dyn = 4 c_s
     cs = np.full((6, 8), 1.0e5)
     assert M.dynamic_c_tilde(cold, cs) == 1.0e7          # floor (4 km/s < 100 km/s)
     assert M.dynamic_c_tilde(cold, np.full((6, 8), 1.0e10)) == M.C_LIGHT   # ceiling
