@@ -79,14 +79,17 @@ constexpr int kRowsPerPass = 256 / kTX;        // tile rows one pass of the bloc
 static_assert(kTX * kTY == 512 && 256 % kTX == 0, "a block owns 512 cells, two per lane");
 constexpr int kPX = kTX + 4, kPY = kTY + 4;   // padded tile, halo 2
 constexpr int kRX = kTX + 2, kRY = kTY + 2;   // opacity ring, halo 1
+// LDS row strides: one word more than a row, odd, so that the four rows a
+// half-wave of row-wise face runs touches fall in distinct banks.
+constexpr int kPS = kPX + 1, kRS = kRX + 1;
 constexpr int kNXF = kTY * (kTX + 1);         // x-faces of a tile
 constexpr int kNYF = (kTY + 1) * kTX;         // y-faces of a tile
 
 template <typename R>
 struct AdvShared {
-  R E[kPY][kPX], fx[kPY][kPX], fy[kPY][kPX];  // staged state: E and f = F/E
+  R E[kPY][kPS], fx[kPY][kPS], fy[kPY][kPS];  // staged state: E and f = F/E
   int src[kPY * kPX];                          // staging sources (see advect_block)
-  R aF[kRY][kRX];                              // alpha_F of the ring, this bin
+  R aF[kRY][kRS];                              // alpha_F of the ring, this bin
   R fle[kNXF + kNYF], flx[kNXF + kNYF], fly[kNXF + kNYF];  // face fluxes
   R un[kNXF + kNYF];                           // face-normal velocity / c
   R xidl[kTX + 3], xhp[kTX + 2], xhm[kTX + 2]; // columns x0-1 .. (geometry)
@@ -381,15 +384,16 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
     for (int m = 0; m < kStagePerLane; ++m) {
       const int e = tid + 256 * m, v = sv[m];
       if (e < kPX * kPY) {
-        (&S.E[0][0])[e] = v >= 0 ? ev[m] : R(0);
-        (&S.fx[0][0])[e] = v < 0 ? R(0) : ((v & 1) ? -xv[m] : xv[m]);
-        (&S.fy[0][0])[e] = v < 0 ? R(0) : ((v & 2) ? -yv[m] : yv[m]);
+        const int d = e + e / kPX;         // entry (e / kPX, e % kPX) at row stride kPS
+        (&S.E[0][0])[d] = v >= 0 ? ev[m] : R(0);
+        (&S.fx[0][0])[d] = v < 0 ? R(0) : ((v & 1) ? -xv[m] : xv[m]);
+        (&S.fy[0][0])[d] = v < 0 ? R(0) : ((v & 2) ? -yv[m] : yv[m]);
       }
     }
 #pragma unroll
     for (int m = 0; m < kRingPerLane; ++m) {
       const int e = tid + 256 * m;
-      if (e < kRX * kRY) (&S.aF[0][0])[e] = ral[m] * hr[m] + racF[m];
+      if (e < kRX * kRY) (&S.aF[0][0])[e + e / kRX] = ral[m] * hr[m] + racF[m];
     }
     __syncthreads();
     // (2) every face of the tile once, in runs of four consecutive faces
@@ -400,7 +404,9 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
       face_run<R, 0>(S, r, s * kRun, s * kRun + kRun);
       if (tid < kTY) face_run<R, 0>(S, tid, kTX, kTX + 1);     // last face of row tid
     } else {
-      const int u = tid - 128, c = u / kRunsY, s = u % kRunsY;
+      // a half-wave takes 32 neighbouring columns at one run position, so
+      // its reads and flux writes fall in distinct banks
+      const int u = tid - 128, c = u % kTX, s = u / kTX;
       face_run<R, 1>(S, c, s * kRun, s * kRun + kRun);
       if (u < kTX) face_run<R, 1>(S, u, kTY, kTY + 1);         // last face of column u
     }
