@@ -141,11 +141,19 @@ static_assert(128 % kTY == 0 && 128 % kTX == 0, "runs must tile the faces");
 constexpr int kRun = 4;               // faces per run; the last face of a line apart
 static_assert(kRunsX * kRun == kTX && kRunsY * kRun == kTY, "runs of four cover a line but its last face");
 
+// Faces per iteration of a run.  Unrolled, a run keeps no register rotation
+// between faces and addresses LDS with constant offsets: float fully (four
+// waves per SIMD leave it the registers), double by two.  The active-bin and
+// substep variants and the fused sink carry more state through the bin loop
+// and would spill, so they keep one face per iteration.
+template <typename R, bool EXTRA>
+constexpr int kFaceUnroll = EXTRA ? 1 : (sizeof(R) == 8 ? 2 : kRun);
+
 // Faces [c0, c1) along line `line` (N = 0: tile row, faces between padded
 // columns c+1 and c+2; N = 1: tile column, faces between padded rows c+1 and
 // c+2).  MinMod slopes on centroid distances: each cell's slope and each
 // difference between neighbours is formed once and carried along the run.
-template <typename R, int N>
+template <typename R, int N, int U>
 __device__ __forceinline__ void face_run(AdvShared<R>& S, int line, int c0, int c1) {
   auto ld = [&](int p, R& e, R& x, R& y) {
     if (N == 0) { e = S.E[line + 2][p]; x = S.fx[line + 2][p]; y = S.fy[line + 2][p]; }
@@ -163,10 +171,8 @@ __device__ __forceinline__ void face_run(AdvShared<R>& S, int line, int c0, int 
   R dE = (e2 - e1) * i12, dX = (x2 - x1) * i12, dY = (y2 - y1) * i12;
   R sE = minmod((e1 - e0) * i01, dE), sX = minmod((x1 - x0) * i01, dX),
     sY = minmod((y1 - y0) * i01, dY);
-  // unrolled (no register rotation between faces, constant LDS offsets):
-  // float fully (four waves per SIMD leave it the registers), double by two
-  constexpr int kUnroll = sizeof(R) == 8 ? 2 : 4;
-#pragma unroll kUnroll
+  // U faces per iteration (see kFaceUnroll)
+#pragma unroll U
   for (int c = c0; c < c1; ++c) {
     R e3, x3, y3;
     ld(c + 3, e3, x3, y3);
@@ -204,6 +210,7 @@ __device__ __forceinline__ R* plane_at(R* plane, unsigned c) {
 // its bin plane and its index c in the plane.
 template <typename R>
 struct WriteSink {
+  static constexpr bool kHeavy = false;     // holds no per-cell state across bins
   __device__ __forceinline__ void init(const GridArgs<R>&, const bool*, const unsigned*,
                                        const int*) {}
   __device__ __forceinline__ void put(const GridArgs<R>& a, int, int, size_t koff, unsigned c,
@@ -401,14 +408,14 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
     // y-faces (runs along columns); then the last face of each line.
     if (tid < 128) {
       const int r = tid / kRunsX, s = tid % kRunsX;
-      face_run<R, 0>(S, r, s * kRun, s * kRun + kRun);
-      if (tid < kTY) face_run<R, 0>(S, tid, kTX, kTX + 1);     // last face of row tid
+      face_run<R, 0, kFaceUnroll<R, AB || SUB || Sink::kHeavy>>(S, r, s * kRun, s * kRun + kRun);
+      if (tid < kTY) face_run<R, 0, 1>(S, tid, kTX, kTX + 1);     // last face of row tid
     } else {
       // a half-wave takes 32 neighbouring columns at one run position, so
       // its reads and flux writes fall in distinct banks
       const int u = tid - 128, c = u % kTX, s = u / kTX;
-      face_run<R, 1>(S, c, s * kRun, s * kRun + kRun);
-      if (u < kTX) face_run<R, 1>(S, u, kTY, kTY + 1);         // last face of column u
+      face_run<R, 1, kFaceUnroll<R, AB || SUB || Sink::kHeavy>>(S, c, s * kRun, s * kRun + kRun);
+      if (u < kTX) face_run<R, 1, 1>(S, u, kTY, kTY + 1);         // last face of column u
     }
     __syncthreads();
     // (3) update, causality clamp, implicit source
@@ -951,6 +958,7 @@ void k_freq_batched(const GridArgs<R>* __restrict__ args,
 // The arithmetic is that of advect_block + freq_cell<float, float> step for
 // step, so both paths give identical bits.
 struct FusedSink {
+  static constexpr bool kHeavy = true;      // elimination state of two cells across bins
   FreqCell<float, float> fc[2];
   float al[2], qp[2], Cp[2], ep[2];
   double acF[2];
