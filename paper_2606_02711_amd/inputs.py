@@ -245,6 +245,30 @@ def cone_cloud(n=256, R_cl=PC, tau_cl=1.0e8, tau_cone=1.0e5, T=1.0e4, mu_cone=2 
     return p
 
 
+def static_sphere(n=64, R_cl=PC, tau_cl=1.0e6, T=1.0e4):
+    """Static dust-free cloud of Section 4 (Test 1): a uniform sphere of
+    radius R_cl at T with line-centre depth tau_cl = n_HI sigma0(T) R_cl and
+    uniform emission (1 erg/s in the box), vacuum outside; box
+    [0, 1.1 R_cl]^2 in (R, Z) with reflecting axis and midplane, outflow at the
+    outer edges; c_tilde = c; no recoil, no continuum absorption, no
+    destruction."""
+    half = 1.1 * R_cl
+    p = base_problem("cyl", n, n, 0.0, half, 0.0, half,
+                     ("reflect", "vacuum", "reflect", "vacuum"), c_tilde_frac=1.0)
+    p["recoil"] = 0
+    R, Z = cell_centres(p)
+    inside = np.sqrt(R[None, :] ** 2 + Z[:, None] ** 2) <= R_cl
+    sig0 = SIGMA0_1E4 * (T / 1.0e4) ** -0.5
+    f = uniform_fields(p, 0.0, T)
+    f["n_HI"] = np.where(inside, tau_cl / (sig0 * R_cl), 0.0)
+    src = inside.astype(float)
+    f["emis"] = src / float(np.sum(src * cell_volumes(p)))
+    p["fields"] = f
+    p["R_cl"] = R_cl
+    p["t_max"] = 4.0 * max((4.7e-4 * (T / 1.0e4) ** -0.5 * tau_cl) ** (1.0 / 3.0), 3.0) * R_cl / C_LIGHT
+    return p
+
+
 def config3(n_grids=64, lo=64, hi=512, config_id=3, steps=500):
     rng = rng_for(config_id)
     probs = []

@@ -1,6 +1,7 @@
 """Force multipliers of a run (Section 4): M_F = (c/L) int dV |f| and
 M_F,radial = (c/L) int dV f . r_hat, r_hat from the cloud centre at the
-origin, and the anisotropic-escape cone test run on the GPU."""
+origin, and the static-cloud (Test 1) and anisotropic-escape (Test 6) runs on
+the GPU."""
 import time
 
 import numpy as np
@@ -23,10 +24,12 @@ def force_multipliers(p, force):
     return mf, mfr
 
 
-def run_cone(n=256, prec="fp32", t_max=None, log=None, checkpoints=4):
+def run_cone(n=256, prec="fp32", t_max=None, log=None, checkpoints=4, problem=None,
+             name="cone"):
     """Cone test to t_max (default 4 max((a tau)^1/3, 3) R_cl/c); returns the
-    multipliers at evenly spaced checkpoints and the final ones."""
-    p = inputs.cone_cloud(n)
+    multipliers at evenly spaced checkpoints and the final ones.  `problem`
+    runs another cloud (e.g. inputs.static_sphere) the same way."""
+    p = inputs.cone_cloud(n) if problem is None else problem
     g = m1.M1Grid(p, prec=prec)
     t_end = p["t_max"] if t_max is None else t_max
     steps = int(np.ceil(t_end / g.dt))
@@ -44,7 +47,7 @@ def run_cone(n=256, prec="fp32", t_max=None, log=None, checkpoints=4):
         mf, mfr = force_multipliers(p, f)
         hist.append((done, done * g.dt * inputs.C_LIGHT / p["R_cl"], mf, mfr))
         if log:
-            log(f"[cone {n}^2 {prec}] step {done}/{steps} t={hist[-1][1]:.1f} R_cl/c "
+            log(f"[{name} {n}^2 {prec}] step {done}/{steps} t={hist[-1][1]:.1f} R_cl/c "
                 f"M_F={mf:.3f} M_F,radial={mfr:.3f}")
     wall = time.perf_counter() - t0
     g.free()
