@@ -15,6 +15,11 @@
 //                   the state stores, so only E is rewritten.
 //   step_fused    : both in one kernel, a block per tile and all bins (a
 //                   batch tile variant).
+//   freq_sub      : the frequency step with the emission/absorption of the
+//                   step in substeps under the 10 % energy rule (Section 2.1,
+//                   step 2; optional).
+//   bin_energy,   : the active-bin selection of Section 2.1 (optional):
+//   bin_select      per-bin energies in double, flags of the advected bins.
 //   residual      : deterministic FP64 norms ||E^{n+1} - E^n||, ||E^{n+1}||.
 #include "m1_kernels.h"
 
