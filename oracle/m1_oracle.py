@@ -1,4 +1,5 @@
-"""FP64 CPU oracle of the M1 Lyman-alpha transfer step -- TEST INFRASTRUCTURE.
+"""FP64 CPU oracle of the M1 Lyman-alpha transfer step (and of the same step
+for broad bands) -- TEST INFRASTRUCTURE.
 
 Only the tests, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import or call this module.  It shares no code with the GPU
@@ -202,7 +203,9 @@ class _Prob(ctypes.Structure):
                     "uy", "dnuD", "hkT", "emis", "cls", "hbar", "phi")]
                 + [("active_frac", ctypes.c_double), ("active", ctypes.c_void_p),
                    ("substep_rule", ctypes.c_int), ("substeps", ctypes.c_void_p),
-                   ("sub_margin", ctypes.c_void_p)])
+                   ("sub_margin", ctypes.c_void_p),
+                   ("band", ctypes.c_int), ("kabs", ctypes.c_void_p),
+                   ("kflux", ctypes.c_void_p), ("jband", ctypes.c_void_p)])
 
 
 def build(force=False):
@@ -318,6 +321,63 @@ class Oracle:
             if r < rel_tol:
                 return True, self.steps, r
         return False, self.steps, r
+
+
+class BandOracle:
+    """Broad-band M1 transport (Section 2.5; Appendix E): the advection and
+    emission/absorption steps of Section 2.1 for each band B with per-cell
+    absorption opacity kappa_abs,B, flux opacity kappa_F,B [cm^-1] and
+    luminosity density L_B [erg s^-1 cm^-3] (source L_B / c in the E
+    equation), no frequency step, force sum_B kappa_F,B F_B.  Band problem
+    dict: geometry keys as for the line problems plus n_band and fields
+    u_x, u_y [ny, nx], kappa_abs, kappa_flux, emis [n_band, ny, nx].  State
+    arrays are [n_band, ny, nx]."""
+
+    def __init__(self, p, dt=None):
+        f = p["fields"]
+        self.nx, self.ny, self.nb = int(p["nx"]), int(p["ny"]), int(p["n_band"])
+        self.dt = rt_time_step(p) if dt is None else float(dt)
+        shape = (self.nb, self.ny, self.nx)
+        self.E = np.zeros(shape)
+        self.Fx = np.zeros(shape)
+        self.Fy = np.zeros(shape)
+        self.force = np.zeros((4, self.ny, self.nx))
+        self._scratch = [np.zeros(shape) for _ in range(3)]
+        self.t = 0.0
+        self.steps = 0
+        P = _Prob()
+        P.nx, P.ny, P.nb = self.nx, self.ny, self.nb
+        P.geom = 1 if p["geom"] == "cyl" else 0
+        for i in range(4):
+            P.bc[i] = BC_CODE[p["bc"][i]]
+        P.c_tilde, P.dt = float(p["c_tilde"]), self.dt
+        xe = p["x0"] + (p["x1"] - p["x0"]) * np.arange(self.nx + 1) / self.nx
+        ye = p["y0"] + (p["y1"] - p["y0"]) * np.arange(self.ny + 1) / self.ny
+        cell = lambda k: np.ascontiguousarray(f[k], dtype=np.float64).reshape(self.ny * self.nx)
+        tab = lambda k: np.ascontiguousarray(f[k], dtype=np.float64).reshape(shape)
+        self._keep = [xe, ye, cell("u_x"), cell("u_y"), tab("kappa_abs"), tab("kappa_flux"),
+                      tab("emis")]
+        for name, a in zip(("xe", "ye", "ux", "uy", "kabs", "kflux", "jband"), self._keep):
+            setattr(P, name, a.ctypes.data)
+        P.band = 1
+        self.P = P
+
+    def set_state(self, E, Fx, Fy):
+        self.E[...] = E
+        self.Fx[...] = Fx
+        self.Fy[...] = Fy
+
+    def step(self, n=1):
+        L = lib()
+        a, b, c = self._scratch
+        for _ in range(n):
+            st = L.oracle_step(ctypes.byref(self.P), _ptr(self.E), _ptr(self.Fx), _ptr(self.Fy),
+                               _ptr(self.force), _ptr(a), _ptr(b), _ptr(c))
+            if st:
+                raise ValueError("band transport takes neither active bins nor substeps")
+            self.t += self.dt
+            self.steps += 1
+        return self
 
 
 def eddington(E, Fx, Fy):

@@ -33,6 +33,11 @@
  *   (4) implicit frequency step per cell (Section 2.1, step 3; Appendix A):
  *       exponential-scheme leakage coefficients, tridiagonal solve
  *       (Thomas algorithm in long double), H rescaled by J_new/J_old.
+ *
+ * With `band` set the same step moves broad bands instead (Section 2.5,
+ * Appendix E): (1) unchanged with the band's flux opacity in the blend,
+ * (2) with the band's absorption opacity and emission, (3) the force
+ * sum_B kappa_F,B F_B, and no step (4).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -75,6 +80,14 @@ typedef struct {
                                 the last step, the smallest |r/0.1 - 1|, r the
                                 attempt's relative energy change (how close a
                                 decision came to the 10 % boundary) */
+  /* Broad-band transport (Section 2.5 and Appendix E: stellar and IR bands): with band set,
+   * each of the nb "bins" is a band B with per-cell absorption opacity
+   * kappa_abs, flux opacity kappa_F [cm^-1] and luminosity density
+   * [erg/s/cm^3], tables [nb][ncell]; the line data above (alpha, hbar,
+   * phi, cls, pd, acabs, acF, emis, nu_c, dnu, dnuD, hkT) are not used, and
+   * there is no frequency step (no frequency-derivative terms). */
+  int band;
+  const double *kabs, *kflux, *jband;
 } OracleProblem;
 
 /* ------------------------------------------------------------------------ */
@@ -210,7 +223,8 @@ static void fill_padded_bin(const OracleProblem *P, int k, const double *E,
       B->E[q] = e;
       B->fx[q] = (e > 0.0) ? sgx * Xk[c] / e : 0.0;
       B->fy[q] = (e > 0.0) ? sgy * Yk[c] / e : 0.0;
-      B->aF[q] = P->alpha[c] * P->hbar[(size_t)P->cls[c] * P->nb + k] + P->acF[c];
+      B->aF[q] = P->band ? P->kflux[(size_t)k * nc + c]
+                         : P->alpha[c] * P->hbar[(size_t)P->cls[c] * P->nb + k] + P->acF[c];
     }
 }
 
@@ -359,6 +373,24 @@ static void build_velocity(const OracleProblem *P, VelData *V) {
 
 static void free_velocity(VelData *V) { free(V->unx); free(V->uny); free(V->grad); }
 
+/* Opacities and source of cell c in bin (or band) k for step (2): kE the
+ * absorption coefficient of E, aF that of F, src the emission term j/c. */
+static void source_coeffs(const OracleProblem *P, int k, size_t c, double *kE, double *aF,
+                          double *src) {
+  size_t nc = (size_t)P->nx * P->ny, ck = (size_t)k * nc + c;
+  if (P->band) {
+    *kE = P->kabs[ck];
+    *aF = P->kflux[ck];
+    *src = P->jband[ck] / C_LIGHT;
+    return;
+  }
+  double h = P->hbar[(size_t)P->cls[c] * P->nb + k];
+  double aH = P->alpha[c] * h;
+  *kE = P->acabs[c] + P->pd[c] * aH;
+  *aF = aH + P->acF[c];
+  *src = P->emis[c] * P->phi[(size_t)P->cls[c] * P->nb + k] / C_LIGHT;
+}
+
 /* Advection (when `advect`) and emission/absorption of bin k.  A bin that is
  * not advected keeps its state through step (1): no fluxes, no work or hoop
  * term, no clamp (the state is causal already); step (2) acts as usual. */
@@ -374,11 +406,8 @@ static void advect_source_bin(const OracleProblem *P, const Geometry *G,
     for (size_t c = 0; c < nc; ++c) {
       size_t ck = (size_t)k * nc + c;
       if (!source) { Eo[ck] = E[ck]; Fxo[ck] = Fx[ck]; Fyo[ck] = Fy[ck]; continue; }
-      double h = P->hbar[(size_t)P->cls[c] * P->nb + k];
-      double aH = P->alpha[c] * h;
-      double kE = P->acabs[c] + P->pd[c] * aH;
-      double aF = aH + P->acF[c];
-      double src = P->emis[c] * P->phi[(size_t)P->cls[c] * P->nb + k] / C_LIGHT;
+      double kE, aF, src;
+      source_coeffs(P, k, c, &kE, &aF, &src);
       Eo[ck] = (E[ck] + ctdt * src) / (1.0 + ctdt * kE);
       Fxo[ck] = Fx[ck] / (1.0 + ctdt * aF);
       Fyo[ck] = Fy[ck] / (1.0 + ctdt * aF);
@@ -434,11 +463,8 @@ static void advect_source_bin(const OracleProblem *P, const Geometry *G,
       }
       if (!source) { Eo[ck] = Es; Fxo[ck] = Xs; Fyo[ck] = Ys; continue; }
       /* implicit emission / absorption / destruction (BDF1, one substep) */
-      double h = P->hbar[(size_t)P->cls[c] * P->nb + k];
-      double aH = P->alpha[c] * h;
-      double kE = P->acabs[c] + P->pd[c] * aH;
-      double aF = aH + P->acF[c];
-      double src = P->emis[c] * P->phi[(size_t)P->cls[c] * P->nb + k] / C_LIGHT;
+      double kE, aF, src;
+      source_coeffs(P, k, c, &kE, &aF, &src);
       Eo[ck] = (Es + ctdt * src) / (1.0 + ctdt * kE);
       Fxo[ck] = Xs / (1.0 + ctdt * aF);
       Fyo[ck] = Ys / (1.0 + ctdt * aF);
@@ -631,6 +657,7 @@ int oracle_step(const OracleProblem *P, double *E, double *Fx, double *Fy,
   VelData V;
   build_velocity(P, &V);
   size_t npad = (size_t)(nx + 4) * (ny + 4);
+  if (P->band && (P->active_frac > 0.0 || P->substep_rule)) return 1;
   int *active = (int *)malloc(sizeof(int) * nb);
   if (P->active_frac > 0.0) select_active_bins(P, E, active);
   else for (int k = 0; k < nb; ++k) active[k] = 1;
@@ -671,6 +698,25 @@ int oracle_step(const OracleProblem *P, double *E, double *Fx, double *Fy,
   /* (3) radiation force density, f = sum_k dnu_k alpha_F,k F**_k (one
    * substep; the substep path formed it above) */
   long ncf = P->substep_rule ? 0 : (long)nc;
+  if (P->band) {
+    /* bands: f = sum_B kappa_F,B F**_B (band-integrated fluxes); the split
+     * between gas and dust is not known here, the line part is left 0 */
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < (long)nc; ++c) {
+      double sx = 0, sy = 0;
+      for (int k = 0; k < nb; ++k) {
+        size_t ck = (size_t)k * nc + c;
+        sx += P->kflux[ck] * Xss[ck];
+        sy += P->kflux[ck] * Yss[ck];
+      }
+      force[c] = sx; force[nc + c] = sy; force[2 * nc + c] = 0.0; force[3 * nc + c] = 0.0;
+    }
+    /* no frequency step: the post-source state is the new state */
+    memcpy(E, Ess, sizeof(double) * nb * nc);
+    memcpy(Fx, Xss, sizeof(double) * nb * nc);
+    memcpy(Fy, Yss, sizeof(double) * nb * nc);
+    ncf = 0;
+  }
 #pragma omp parallel for schedule(static)
   for (long c = 0; c < ncf; ++c) {
     double sx = 0, sy = 0, gx = 0, gy = 0;
@@ -687,6 +733,7 @@ int oracle_step(const OracleProblem *P, double *E, double *Fx, double *Fy,
     force[c] = sx; force[nc + c] = sy; force[2 * nc + c] = gx; force[3 * nc + c] = gy;
   }
   /* (4) frequency step, cells independent */
+  long nfs = P->band ? 0 : (long)nc;
 #pragma omp parallel
   {
     double *K = (double *)malloc(sizeof(double) * nb);
@@ -696,7 +743,7 @@ int oracle_step(const OracleProblem *P, double *E, double *Fx, double *Fy,
     long double *cp = (long double *)malloc(sizeof(long double) * nb);
     long double *dp = (long double *)malloc(sizeof(long double) * nb);
 #pragma omp for schedule(static)
-    for (long c = 0; c < (long)nc; ++c)
+    for (long c = 0; c < nfs; ++c)
       frequency_step_cell(P, &V, (int)(c % nx), (int)(c / nx), E, Fx, Fy, Ess, Xss, Yss,
                           K, Cc, gl, gr, cp, dp);
     free(K); free(Cc); free(gl); free(gr); free(cp); free(dp);

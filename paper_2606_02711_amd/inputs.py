@@ -369,5 +369,123 @@ def random_small(geom, nx, ny, seed, with_velocity=True, with_dust=True,
     return p
 
 
+# --------------------------------------------------------------------------
+# broad bands (stellar and IR transport of Section 2.5)
+# --------------------------------------------------------------------------
+# A band problem carries the line problem's geometry keys plus n_band and
+# fields u_x, u_y (ny, nx) and, per band and cell (n_band, ny, nx):
+#   kappa_abs  = absorption opacity [cm^-1]
+#   kappa_flux = flux-mean opacity [cm^-1]
+#   emis       = luminosity density [erg s^-1 cm^-3]
+BANDS = ("IR", "opt", "FUV", "LW", "EUV1", "EUV2", "EUV3")
+# Dust per band (Section 2.5 table of non-IR band properties): (kappa_abs,
+# kappa_F) of silicate, graphite and PAH grains [cm^2 per g of dust in the
+# bin].  IR: a grey stand-in (the paper's IR opacities are temperature
+# dependent, Appendix E), used only to give the IR band a plausible depth.
+DUST_BAND_KAPPA = {
+    "IR": ((5.0, 5.0), (5.0, 5.0), (5.0, 5.0)),
+    "opt": ((5.98e3, 1.69e4), (2.09e4, 2.61e4), (2.27e5, 2.27e5)),
+    "FUV": ((1.71e4, 2.21e4), (2.29e4, 2.57e4), (2.86e5, 2.86e5)),
+    "LW": ((1.80e4, 2.18e4), (3.88e4, 4.48e4), (5.92e5, 5.92e5)),
+    "EUV1": ((1.53e4, 1.85e4), (5.60e4, 6.22e4), (1.08e6, 1.08e6)),
+    "EUV2": ((1.37e4, 1.46e4), (1.90e4, 2.12e4), (2.83e5, 2.84e5)),
+    "EUV3": ((1.30e4, 1.32e4), (1.04e4, 1.09e4), (8.81e4, 8.82e4)),
+}
+# Band-mean photoionisation cross-sections [cm^2] of H I, He I, He II:
+# order-of-magnitude stand-ins (the paper takes them from its references),
+# used only to shape the inputs.
+GAS_BAND_SIGMA = {
+    "EUV1": (3.0e-18, 0.0, 0.0),
+    "EUV2": (5.7e-19, 4.5e-18, 0.0),
+    "EUV3": (7.9e-20, 1.2e-18, 1.1e-18),
+}
+# Share of the stellar luminosity per band (a hot star; stand-in).
+STAR_BAND_SHARE = {"IR": 0.0, "opt": 0.15, "FUV": 0.30, "LW": 0.10, "EUV1": 0.30,
+                   "EUV2": 0.12, "EUV3": 0.03}
+
+
+def band_opacities(n_H, x_HI, dust_solar, bands=BANDS):
+    """(kappa_abs, kappa_F) [n_band, ...] of dust (mass fractions f_Sil, f_C,
+    f_PAH of the dust) plus gas photoionisation (H I fraction x_HI, helium
+    number ratio 0.08 with its neutral fraction following x_HI)."""
+    n_H = np.asarray(n_H, dtype=np.float64)
+    rho_d = np.asarray(dust_solar) * DUST_TO_GAS_SOLAR * n_H * M_H / 0.75
+    n_HI = np.asarray(x_HI) * n_H
+    n_He = 0.08 * n_H
+    ka, kf = [], []
+    for b in bands:
+        d = DUST_BAND_KAPPA[b]
+        da = sum(f * k[0] for f, k in zip((F_SIL, F_C, F_PAH), d)) * rho_d
+        dF = sum(f * k[1] for f, k in zip((F_SIL, F_C, F_PAH), d)) * rho_d
+        s = GAS_BAND_SIGMA.get(b, (0.0, 0.0, 0.0))
+        gas = s[0] * n_HI + s[1] * n_He * np.asarray(x_HI) + s[2] * n_He * 0.5
+        ka.append(da + gas)
+        kf.append(dF + gas)
+    return np.stack(ka), np.stack(kf)
+
+
+def band_base(p, n_band):
+    q = dict(p)
+    q["n_band"] = int(n_band)
+    for k in ("T_min", "q", "half_width", "recoil", "doppler"):
+        q.pop(k, None)
+    return q
+
+
+def band_random_small(geom, nx, ny, seed, n_band=7, with_velocity=True, L_box=1.0e18,
+                      log_tau_cell=(-4.0, 3.0), bc=None):
+    """Small random band problem for parity tests: per-cell, per-band optical
+    depths log-uniform over log_tau_cell, flux opacity >= absorption
+    opacity, sparse random emission, velocities up to 50 km/s."""
+    rng = np.random.default_rng(np.random.SeedSequence([SEED_BASE, 77, seed]))
+    if geom == "cart":
+        p = base_problem("cart", nx, ny, 0.0, L_box, 0.0, L_box * ny / nx,
+                         bc or ("vacuum",) * 4)
+    else:
+        p = base_problem("cyl", nx, ny, 0.0, L_box, -0.5 * L_box * ny / nx,
+                         0.5 * L_box * ny / nx,
+                         bc or ("reflect", "vacuum", "vacuum", "vacuum"))
+    p = band_base(p, n_band)
+    dx = L_box / nx
+    sh = (n_band, ny, nx)
+    ka = 10.0 ** rng.uniform(*log_tau_cell, size=sh) / dx
+    kf = ka * (1.0 + rng.uniform(0.0, 2.0, size=sh))
+    em = rng.uniform(0.0, 1.0, size=sh) ** 8
+    em *= 1.0 / float(np.sum(em[0] * cell_volumes(p)) + 1e-300)
+    if with_velocity:
+        ux = rng.uniform(-50.0, 50.0, size=sh[1:]) * KMS
+        uy = rng.uniform(-50.0, 50.0, size=sh[1:]) * KMS
+    else:
+        ux, uy = np.zeros(sh[1:]), np.zeros(sh[1:])
+    p["fields"] = dict(u_x=ux, u_y=uy, kappa_abs=ka, kappa_flux=kf, emis=em)
+    return p
+
+
+def band_hii_region(nx=512, ny=1024, L_star=1.0e39, steps=1000):
+    """Seven-band workload: a cylindrical (R, z) = 1 pc x 2 pc cloud with the
+    structure of the line workload (ionised bubble of 0.2 pc in a log-normal
+    neutral shell, radial outflow to 30 km/s, dust 0.01 solar) and a star of
+    L_star [erg/s] on the axis emitting in the non-IR bands with a Gaussian
+    profile of sigma = 3 cells (Section 2.5, single star)."""
+    rng = rng_for(6)
+    p = base_problem("cyl", nx, ny, 0.0, PC, -PC, PC,
+                     ("reflect", "vacuum", "vacuum", "vacuum"), steps=steps)
+    p = band_base(p, len(BANDS))
+    xc, yc = cell_centres(p)
+    r = np.sqrt(xc[None, :] ** 2 + yc[:, None] ** 2)
+    g = gaussian_random_field(rng, ny, nx)
+    n_H = 100.0 * np.exp(0.8 * g)
+    bubble = r < 0.2 * PC
+    x_HI = np.where(bubble, 1.0e-4, 1.0)
+    ka, kf = band_opacities(n_H, x_HI, 0.01)
+    v = 30.0 * KMS * np.minimum(r / (0.2 * PC), 1.0)
+    ux = v * xc[None, :] / np.maximum(r, 1e-30)
+    uy = v * yc[:, None] / np.maximum(r, 1e-30)
+    shape = gaussian_source(p, 0.0, 0.0, 3.0 * PC / nx, L_star)
+    em = np.stack([STAR_BAND_SHARE[b] * shape for b in BANDS])
+    p["fields"] = dict(u_x=ux, u_y=uy, kappa_abs=ka, kappa_flux=kf, emis=em)
+    return p
+
+
 def get_config(cid: int, **kw):
     return {1: config1, 2: config2, 5: config5}[cid](**kw)
