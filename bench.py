@@ -229,6 +229,45 @@ def run_substeps(steps, L=1.0e38):
     return out
 
 
+def band_bytes(nc, nb, prec):
+    """Algorithmic HBM bytes of one band-step launch: per cell and band the
+    state read and written and the three tables read once (9 values); per
+    cell the force (4 doubles) written and the velocity data (4 gradients,
+    2 face velocities) read."""
+    rs = 4 if prec == "fp32" else 8
+    return nc * (9 * rs * nb + 32 + 6 * rs)
+
+
+def run_bands(steps, warmup):
+    """Seven broad bands (IR, optical, FUV, LW, EUV1-3) on the 512 x 1024
+    H II-region workload: one band-step kernel per step (advection,
+    emission/absorption, force), FP32 and FP64."""
+    import torch
+    from paper_2606_02711_amd import inputs, m1
+    p = inputs.band_hii_region()
+    nc, nb = p["nx"] * p["ny"], p["n_band"]
+    out = {"workload": "cylindrical 512x1024 (R,z) H II region: bubble + log-normal shell, "
+                       "outflow 30 km/s, dust 0.01 solar, star on the axis (Gaussian, sigma 3 "
+                       "cells); 7 bands", "steps": steps, "unit": "cell-band updates/s"}
+    for prec in ("fp32", "fp64"):
+        log(f"[bench] bands {prec}")
+        g = m1.BandGrid(p, prec=prec)
+        g.step(warmup)
+        g.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        a, _ = g.step_profiled(steps)
+        wall = time.perf_counter() - t0
+        ms = a / steps
+        alg = band_bytes(nc, nb, prec) / (ms * 1e-3) / 1e9
+        out[prec] = {"value": nc * nb * steps / wall, "ms_per_step": 1e3 * wall / steps,
+                     "kernel_ms": ms, "algorithmic_bytes": band_bytes(nc, nb, prec),
+                     "algorithmic_GBs": alg, "frac": alg / HBM_PEAK_GBS}
+        g.free()
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_large(steps, warmup):
     """4096 x 8192 cylindrical cloud in FP32, the force density copied out
     (to device arrays) after every step."""
@@ -320,6 +359,10 @@ def main():
                     help="steps of the substep-rule workload (0 skips it)")
     ap.add_argument("--large-steps", type=int, default=20,
                     help="timed steps of the 4096 x 8192 grid (0 skips it)")
+    ap.add_argument("--band-steps", type=int, default=500,
+                    help="steps of the seven-band workload (0: skip)")
+    ap.add_argument("--band-only", action="store_true",
+                    help="only the seven-band workload")
     ap.add_argument("--serve-seconds", type=float, default=30.0,
                     help="length of the request stream (0 skips the serving workload)")
     ap.add_argument("--serve-rate", type=float, default=0.5, help="requests per second")
@@ -364,6 +407,9 @@ def main():
     if args.batch_only:
         rb = run_batch(inputs.config3(), args.batch_steps, args.warmup)
         print(json.dumps({"batch_64_grids": rb}), flush=True)
+        return
+    if args.band_only:
+        print(json.dumps({"bands": run_bands(args.band_steps, args.warmup)}), flush=True)
         return
     if args.active_only:
         print(json.dumps({"active_bins": run_active(inputs.config3(), args.active_steps, 100),
@@ -448,6 +494,8 @@ def main():
         out["substeps"] = run_substeps(args.substep_steps)
     if args.large_steps > 0:
         out["large_grid"] = run_large(args.large_steps, 2)
+    if args.band_steps > 0:
+        out["bands"] = run_bands(args.band_steps, args.warmup)
     if args.serve_seconds > 0:
         out["serving"] = run_serving(args)
     if not args.no_cpu:

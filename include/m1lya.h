@@ -223,6 +223,47 @@ int32_t m1_active_bins(m1_handle *h, int32_t *flags_host, int32_t *n_active);
 int32_t m1_get_info(const m1_handle *h, double *dt, int32_t *n_nu, int32_t *prec,
                     int64_t *ncell, int32_t *scale_exp2);
 
+/* ---- broad bands (Section 2.5 and Appendix E): the stellar bands (optical,
+ * FUV, Lyman-Werner, EUV1-3) and the IR band move with the same M1 step:
+ * the advection of Section 2.1 step 1 (MinMod reconstruction, Levermore
+ * closure, corrected GLF flux whose blend eps(tau) takes tau from the band's
+ * flux opacity, upwind velocity advection, work term, hoop pressure,
+ * causality clamp) and the implicit emission/absorption of step 2, with no
+ * frequency-derivative terms, so there is no frequency step.  Opacities and
+ * emission come per band and cell from the caller, whose thermochemistry
+ * (photoionisation, dust temperatures) sets them; it is not part of this
+ * library.  A band grid is an m1_handle: m1_step, m1_step_profiled (all
+ * time in ms[0]), m1_get_state, m1_get_state_region, m1_set_state (per band
+ * instead of per Hz: E = 4 pi J_B / c, F = 4 pi H_B / c), m1_force, m1_residual,
+ * m1_solve_steady, m1_active_bins (every band active), m1_get_info (N_nu =
+ * number of bands), m1_sync and m1_free apply; batches refuse band grids. */
+
+/* Per-band physical inputs, FP64.  Host pointers when on_device is 0,
+ * device pointers otherwise; read once by m1_band_init. */
+typedef struct {
+  const double *u_x, *u_y;    /* gas velocity [cm/s], [ny][nx], |u| < c */
+  const double *kappa_abs;    /* absorption opacity [cm^-1], [n_band][ny][nx], >= 0 */
+  const double *kappa_flux;   /* flux-mean opacity [cm^-1] (sets eps(tau) and the
+                                 force), [n_band][ny][nx], >= 0 */
+  const double *emis;         /* luminosity density [erg s^-1 cm^-3], [n_band][ny][nx],
+                                 >= 0; the E equation gains emis / c per unit length */
+  int32_t on_device;
+} m1_band_fields;
+
+/* Exact device workspace bytes of a grid of n_band bands (1..1024) for cfg. */
+int32_t m1_band_workspace_bytes(const m1_config *cfg, int32_t n_band, size_t *bytes);
+
+/* As m1_init, for n_band broad bands.  cfg supplies the grid, boundaries,
+ * c_tilde, cfl and precision (its frequency-grid, recoil, Doppler and
+ * fp64_tau fields are validated as for m1_init and otherwise unused);
+ * active_frac and substep_rule must be 0 (M1_EUNSUPPORTED otherwise).  The
+ * time step is the line grids' CFL step.  The force of a step (m1_force)
+ * is sum_B kappa_F,B F_B; the line-share outputs are 0.  M1_EINVAL for NULL,
+ * negative or non-finite inputs or |u| >= c, M1_ENOMEM for a short
+ * workspace.  Synchronous; on success *out receives a new handle. */
+int32_t m1_band_init(const m1_config *cfg, int32_t n_band, const m1_band_fields *fields,
+                     void *d_ws, size_t ws_bytes, void *stream, m1_handle **out);
+
 /* ---- batches: many grids advanced by one persistent launch per kernel and
  * step (a throughput addition with no counterpart in the paper).
  * A batch groups n handles of the same precision on the same stream.  Its

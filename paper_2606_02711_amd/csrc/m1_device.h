@@ -62,6 +62,10 @@ struct GridArgs {
   // energy-density floor of the rule in state units
   int substeps;
   double e_floor;
+  // broad bands (a grid of bands instead of line bins): per band and cell
+  // [nb][ncell], absorption and flux opacities and the emission term L/c
+  // (state units); nullptr for line grids
+  const R *kabs, *kflux, *jsrc;
 };
 
 // Address-space hints for pointers read from a descriptor table in memory
@@ -109,6 +113,7 @@ __device__ __forceinline__ GridArgs<R> global_args(const GridArgs<R>& s) {
   a.yidl = const_ptr(a.yidl); a.yhm = const_ptr(a.yhm); a.yhp = const_ptr(a.yhp);
   a.cy = const_ptr(a.cy);
   a.active = const_ptr(a.active);
+  a.kabs = const_ptr(a.kabs); a.kflux = const_ptr(a.kflux); a.jsrc = const_ptr(a.jsrc);
   return a;
 }
 

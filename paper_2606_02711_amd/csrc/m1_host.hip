@@ -100,6 +100,7 @@ struct Layout {
   size_t dnu, inv_dnu, two_nu, nu_c, edges;
   size_t geo, xe, ye, nodes;
   size_t wx, wy, binpart, active;   // active bins: volume weights, partial sums, flags
+  size_t kabs, kflux, jsrc;         // band grids: per band and cell tables
   size_t partial, result;
   size_t total;
 };
@@ -120,7 +121,7 @@ size_t init_temp_need(size_t nc, int nb, int64_t ncls, int nx, int ny, bool host
 }
 
 Layout make_layout(int nx, int ny, int nb, int64_t ncls, size_t rs) {
-  Layout L;
+  Layout L{};
   size_t off = 0;
   size_t nc = (size_t)nx * ny, nbc = (size_t)nb * nc;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
@@ -160,6 +161,44 @@ Layout make_layout(int nx, int ny, int nb, int64_t ncls, size_t rs) {
   L.binpart = take((size_t)nb * energy_chunks(nc) * sizeof(double));
   L.active = take(nb * sizeof(int32_t));
   L.nodes = take(kDawsonNodes * sizeof(double));
+  L.partial = take(3 * kResBlocks * sizeof(double));
+  L.result = take(2 * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+constexpr int kMaxBands = 1024;
+
+// Device bytes the band set-up needs for temporaries: the velocities (when
+// they come from the host) and the face velocities in double.
+size_t band_temp_need(size_t nc, int nx, int ny, bool host_fields) {
+  size_t need = host_fields ? 2 * align_up(nc * sizeof(double)) : 0;
+  return need + 2 * ((size_t)(nx + 1) * ny + (size_t)nx * (ny + 1)) * sizeof(double);
+}
+
+// Workspace of a grid of nb broad bands: state, per band and cell tables,
+// velocity data, geometry, force and the residual's partial sums.
+Layout make_band_layout(int nx, int ny, int nb, size_t rs) {
+  Layout L{};
+  size_t off = 0;
+  size_t nc = (size_t)nx * ny, nbc = (size_t)nb * nc;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+  for (int b = 0; b < 2; ++b)
+    for (int f = 0; f < 3; ++f) L.state[b][f] = take(nbc * rs);
+  // the set-up borrows the second state buffer, padded up to its need
+  const size_t span = off - L.state[1][0];
+  const size_t need = band_temp_need(nc, nx, ny, true);
+  if (span < need) take(need - span);
+  L.force = take(4 * nc * sizeof(double));
+  L.kabs = take(nbc * rs);
+  L.kflux = take(nbc * rs);
+  L.jsrc = take(nbc * rs);
+  L.grad = take(4 * nc * rs);
+  L.ufx = take((size_t)(nx + 1) * ny * rs);
+  L.ufy = take((size_t)nx * (ny + 1) * rs);
+  L.geo = take((size_t)(3 * (nx + 4) + 3 * nx + 3 * (ny + 4) + ny) * rs);
+  L.xe = take((nx + 1) * sizeof(double));
+  L.ye = take((ny + 1) * sizeof(double));
   L.partial = take(3 * kResBlocks * sizeof(double));
   L.result = take(2 * sizeof(double));
   L.total = off;
@@ -217,6 +256,7 @@ struct m1_handle {
   GridArgs<float> af[2];
   GridArgs<double> ad[2];
   bool broken = false;
+  bool band = false;          // a grid of broad bands (m1_band_init)
 };
 
 namespace {
@@ -275,6 +315,7 @@ void fill_args(m1_handle* h, GridArgs<R>* a) {
     g.force = (double*)(w + L.force);
     g.active = c.active_frac > 0.0 ? (const int32_t*)(w + L.active) : nullptr;
     g.substeps = c.substep_rule;
+    g.kabs = g.kflux = g.jsrc = nullptr;
     // e_floor = 4 pi J_floor / c, J_floor = 1e-15 erg cm^-2 s^-1 sr^-1, in
     // the scaled state units
     g.e_floor = ldexp(4.0 * kPi * 1.0e-15 / kC, h->e2);
@@ -496,6 +537,109 @@ int init_typed(m1_handle* h, const m1_fields* f, const std::vector<std::vector<d
   return M1_OK;
 }
 
+// Kernel arguments of a band grid: state, band tables, velocity data,
+// geometry and force; the line data stay null.
+template <typename R>
+void fill_band_args(m1_handle* h, GridArgs<R>* a) {
+  const m1_config& c = h->cfg;
+  const Layout& L = h->L;
+  char* w = h->ws;
+  const int nx = c.nx, ny = c.ny;
+  for (int dir = 0; dir < 2; ++dir) {
+    GridArgs<R> g{};
+    g.nx = nx; g.ny = ny; g.nb = h->nb; g.geom = c.geom;
+    for (int q = 0; q < 4; ++q) g.bc[q] = c.bc[q];
+    g.ctdt = (R)(c.c_tilde * h->dt);
+    g.ctdt_c = (R)(c.c_tilde * h->dt / kC);
+    const int in = dir, out = dir ^ 1;
+    g.E = (const R*)(w + L.state[in][0]);
+    g.fx = (const R*)(w + L.state[in][1]);
+    g.fy = (const R*)(w + L.state[in][2]);
+    g.Eo = (R*)(w + L.state[out][0]);
+    g.fxo = (R*)(w + L.state[out][1]);
+    g.fyo = (R*)(w + L.state[out][2]);
+    g.grad = (const R*)(w + L.grad);
+    g.ufx = (const R*)(w + L.ufx);
+    g.ufy = (const R*)(w + L.ufy);
+    const R* geo = (const R*)(w + L.geo);
+    g.xidl = geo;
+    g.xhm = geo + (nx + 4);
+    g.xhp = geo + 2 * (nx + 4);
+    g.cxm = geo + 3 * (nx + 4);
+    g.cxp = g.cxm + nx;
+    g.chp = g.cxp + nx;
+    g.yidl = g.chp + nx;
+    g.yhm = g.yidl + (ny + 4);
+    g.yhp = g.yhm + (ny + 4);
+    g.cy = g.yhp + (ny + 4);
+    g.force = (double*)(w + L.force);
+    g.kabs = (const R*)(w + L.kabs);
+    g.kflux = (const R*)(w + L.kflux);
+    g.jsrc = (const R*)(w + L.jsrc);
+    a[dir] = g;
+  }
+}
+
+// Band set-up: tables in the state precision (emission as 2^e2 L / c), face
+// velocities and gradients, geometry, zero state and force.  host: the
+// validated inputs (u_x, u_y, kappa_abs, kappa_flux, emis).
+template <typename R>
+int band_init_typed(m1_handle* h, const m1_band_fields* f,
+                    const std::vector<std::vector<double>>& host, double umax, double jmax) {
+  const m1_config& c = h->cfg;
+  hipStream_t s = h->stream;
+  char* w = h->ws;
+  const Layout& L = h->L;
+  const size_t nc = h->nc, nbc = (size_t)h->nb * nc;
+  const int nx = c.nx, ny = c.ny;
+  const double dx = (c.x1 - c.x0) / nx, dy = (c.y1 - c.y0) / ny;
+  h->dt = c.cfl * 0.5 * (std::min(dx, dy) / (c.c_tilde + umax));
+  const double ctdt = c.c_tilde * h->dt;
+  // internal scale: the brightest cell's first-step emission ~ 1 (a power
+  // of two, so results are scaled exactly)
+  const double v = ctdt * jmax / kC;
+  int e2 = 0;
+  if (v > 0 && isfinite(v)) e2 = -(int)floor(log2(v));
+  h->e2 = std::max(-900, std::min(900, e2));
+  std::vector<R> t(nbc);
+  const size_t off[3] = {L.kabs, L.kflux, L.jsrc};
+  for (int q = 0; q < 3; ++q) {
+    const std::vector<double>& src = host[2 + q];
+    for (size_t i = 0; i < nbc; ++i) t[i] = (R)(q == 2 ? ldexp(src[i], h->e2) / kC : src[i]);
+    HIPCHK(hipMemcpyAsync(w + off[q], t.data(), nbc * sizeof(R), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));          // t is reused
+  }
+  std::vector<double> xe, ye;
+  std::vector<R> geo = build_geometry<R>(c, ctdt, xe, ye);
+  HIPCHK(hipMemcpyAsync(w + L.geo, geo.data(), geo.size() * sizeof(R), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(w + L.xe, xe.data(), xe.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(w + L.ye, ye.data(), ye.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  // velocities: the caller's device arrays, or copies in the borrowed
+  // second state buffer; the face-velocity temporaries after them
+  char* tmp = w + L.state[1][0];
+  CellInputs in{};
+  if (f->on_device) {
+    in.ux = f->u_x;
+    in.uy = f->u_y;
+  } else {
+    double* ux = (double*)tmp;
+    double* uy = (double*)(tmp + align_up(nc * sizeof(double)));
+    HIPCHK(hipMemcpyAsync(ux, host[0].data(), nc * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(uy, host[1].data(), nc * sizeof(double), hipMemcpyHostToDevice, s));
+    in.ux = ux;
+    in.uy = uy;
+    tmp += 2 * align_up(nc * sizeof(double));
+  }
+  HIPCHK(launch_velocity<R>(in, nx, ny, c.geom, c.bc, (const double*)(w + L.xe),
+                            (const double*)(w + L.ye), (double*)tmp, (R*)(w + L.ufx),
+                            (R*)(w + L.ufy), (R*)(w + L.grad), s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int b = 0; b < 2; ++b)
+    for (int q = 0; q < 3; ++q) HIPCHK(hipMemsetAsync(w + L.state[b][q], 0, nbc * sizeof(R), s));
+  HIPCHK(hipMemsetAsync(w + L.force, 0, 4 * nc * sizeof(double), s));
+  HIPCHK(hipStreamSynchronize(s));
+  return M1_OK;
+}
 
 }  // namespace
 
@@ -656,6 +800,76 @@ int32_t m1_init(const m1_config* cfg, const m1_fields* f, void* d_ws, size_t ws_
   return M1_OK;
 }
 
+int32_t m1_band_workspace_bytes(const m1_config* cfg, int32_t n_band, size_t* bytes) {
+  if (!bytes) return fail(M1_EINVAL, "bytes is NULL");
+  int st = validate_config(cfg, nullptr);
+  if (st) return st;
+  if (n_band < 1 || n_band > kMaxBands) return fail(M1_EINVAL, "need 1 <= n_band <= %d", kMaxBands);
+  *bytes = make_band_layout(cfg->nx, cfg->ny, n_band, cfg->prec == M1_FP32 ? 4 : 8).total;
+  return M1_OK;
+}
+
+int32_t m1_band_init(const m1_config* cfg, int32_t n_band, const m1_band_fields* f, void* d_ws,
+                     size_t ws_bytes, void* stream, m1_handle** out) {
+  if (!out) return fail(M1_EINVAL, "out is NULL");
+  *out = nullptr;
+  int st = validate_config(cfg, nullptr);
+  if (st) return st;
+  if (cfg->active_frac != 0.0 || cfg->substep_rule)
+    return fail(M1_EUNSUPPORTED, "band grids take neither active bins nor the substep rule");
+  if (n_band < 1 || n_band > kMaxBands) return fail(M1_EINVAL, "need 1 <= n_band <= %d", kMaxBands);
+  if (!f) return fail(M1_EINVAL, "fields is NULL");
+  const double* p[5] = {f->u_x, f->u_y, f->kappa_abs, f->kappa_flux, f->emis};
+  const char* names[5] = {"u_x", "u_y", "kappa_abs", "kappa_flux", "emis"};
+  for (int q = 0; q < 5; ++q)
+    if (!p[q]) return fail(M1_EINVAL, "field %s is NULL", names[q]);
+  if (!d_ws) return fail(M1_EINVAL, "workspace is NULL");
+  if (((uintptr_t)d_ws) & 255) return fail(M1_EINVAL, "workspace must be 256-byte aligned");
+  const size_t nc = (size_t)cfg->nx * cfg->ny, nbc = (size_t)n_band * nc;
+  const size_t rs = cfg->prec == M1_FP32 ? 4 : 8;
+  Layout L = make_band_layout(cfg->nx, cfg->ny, n_band, rs);
+  if (ws_bytes < L.total)
+    return fail(M1_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, L.total);
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<std::vector<double>> host(5);
+  for (int q = 0; q < 5; ++q) {
+    const size_t n = q < 2 ? nc : nbc;
+    host[q].resize(n);
+    if (f->on_device)
+      HIPCHK(hipMemcpyAsync(host[q].data(), p[q], n * sizeof(double), hipMemcpyDeviceToHost, s));
+    else
+      memcpy(host[q].data(), p[q], n * sizeof(double));
+  }
+  if (f->on_device) HIPCHK(hipStreamSynchronize(s));
+  double umax = 0.0, jmax = 0.0;
+  for (int q = 0; q < 5; ++q) {
+    const std::vector<double>& v = host[q];
+    for (size_t i = 0; i < v.size(); ++i) {
+      if (!isfinite(v[i])) return fail(M1_EINVAL, "field %s has a non-finite value at %zu", names[q], i);
+      if (q >= 2 && v[i] < 0) return fail(M1_EINVAL, "field %s is negative at %zu", names[q], i);
+      if (q < 2 && fabs(v[i]) >= kC) return fail(M1_EINVAL, "field %s reaches c at cell %zu", names[q], i);
+      if (q == 4) jmax = std::max(jmax, v[i]);
+    }
+  }
+  for (size_t i = 0; i < nc; ++i) umax = std::max(umax, hypot(host[0][i], host[1][i]));
+  m1_handle* h = new m1_handle();
+  h->cfg = *cfg;
+  h->nb = n_band;
+  h->ncls = 0;
+  h->nc = nc;
+  h->stream = s;
+  h->ws = (char*)d_ws;
+  h->L = L;
+  h->band = true;
+  st = cfg->prec == M1_FP32 ? band_init_typed<float>(h, f, host, umax, jmax)
+                            : band_init_typed<double>(h, f, host, umax, jmax);
+  if (st) { delete h; return st; }
+  fill_band_args<float>(h, h->af);
+  fill_band_args<double>(h, h->ad);
+  *out = h;
+  return M1_OK;
+}
+
 int32_t m1_active_bins(m1_handle* h, int32_t* flags_host, int32_t* n_active) {
   if (!h) return fail(M1_EINVAL, "handle is NULL");
   std::vector<int32_t> f(h->nb, 1);
@@ -703,7 +917,10 @@ static hipError_t launch_selection(m1_handle* h, int dir, hipStream_t s) {
 
 static int enqueue_step(m1_handle* h, hipStream_t s) {
   hipError_t e = launch_selection(h, h->cur, s);
-  if (e == hipSuccess)
+  if (e == hipSuccess && h->band)
+    e = h->cfg.prec == M1_FP32 ? launch_band_step<float>(h->af[h->cur], s)
+                               : launch_band_step<double>(h->ad[h->cur], s);
+  else if (e == hipSuccess)
     e = h->cfg.prec == M1_FP32 ? launch_step<float>(h->af[h->cur], s)
                                : launch_step<double>(h->ad[h->cur], s);
   if (e != hipSuccess) {
@@ -738,11 +955,14 @@ int32_t m1_step_profiled(m1_handle* h, int32_t nsteps, double* ms) {
   HIPCHK(hipEventRecord(ev[0], h->stream));
   for (int n = 0; n < nsteps && !st; ++n) {
     hipError_t e = launch_selection(h, h->cur, h->stream);
-    if (e == hipSuccess)
+    if (e == hipSuccess && h->band)
+      e = h->cfg.prec == M1_FP32 ? launch_band_step<float>(h->af[h->cur], h->stream)
+                                 : launch_band_step<double>(h->ad[h->cur], h->stream);
+    else if (e == hipSuccess)
       e = h->cfg.prec == M1_FP32 ? launch_advect<float>(h->af[h->cur], h->stream)
                                  : launch_advect<double>(h->ad[h->cur], h->stream);
     if (e == hipSuccess) e = hipEventRecord(ev[2 * n + 1], h->stream);
-    if (e == hipSuccess)
+    if (e == hipSuccess && !h->band)
       e = h->cfg.prec == M1_FP32 ? launch_freq<float>(h->af[h->cur], h->stream)
                                  : launch_freq<double>(h->ad[h->cur], h->stream);
     if (e == hipSuccess) e = hipEventRecord(ev[2 * n + 2], h->stream);
@@ -816,6 +1036,8 @@ int check_members(m1_handle* const* hs, int n) {
     if (hs[q]->stream != hs[0]->stream) return fail(M1_EINVAL, "batch members must share a stream");
     if (hs[q]->cfg.substep_rule)
       return fail(M1_EUNSUPPORTED, "handle %d uses the substep rule: step it alone", q);
+    if (hs[q]->band)
+      return fail(M1_EUNSUPPORTED, "handle %d is a band grid: step it alone", q);
     for (int r = 0; r < q; ++r)
       if (hs[r] == hs[q]) return fail(M1_EINVAL, "handle %d appears twice", q);
   }

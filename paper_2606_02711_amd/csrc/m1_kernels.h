@@ -18,6 +18,10 @@ template <typename R>
 hipError_t launch_advect(const GridArgs<R>& a, hipStream_t s);
 template <typename R>
 hipError_t launch_freq(const GridArgs<R>& a, hipStream_t s);
+// Step of a grid of broad bands: advection + emission/absorption + force,
+// one block per tile walking every band.
+template <typename R>
+hipError_t launch_band_step(const GridArgs<R>& a, hipStream_t s);
 // ---- batched persistent launches (one launch per kernel and step for a
 //      set of grids); variant selects the bins-per-block run length, or the
 //      fused kernel (kBatchBK = -1: a block walks all bins of a tile)

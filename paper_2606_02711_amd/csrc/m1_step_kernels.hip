@@ -20,6 +20,10 @@
 //                   step 2; optional).
 //   bin_energy,   : the active-bin selection of Section 2.1 (optional):
 //   bin_select      per-bin energies in double, flags of the advected bins.
+//   band_step     : the advection + emission/absorption kernel for a grid
+//                   of broad bands (Section 2.5): per band and cell
+//                   opacities and emission, force summed over the bands,
+//                   no frequency step.
 //   residual      : deterministic FP64 norms ||E^{n+1} - E^n||, ||E^{n+1}||.
 #include "m1_kernels.h"
 
@@ -230,14 +234,56 @@ struct WriteSink {
   __device__ __forceinline__ void finish(const GridArgs<R>&, const bool*, const unsigned*) {}
 };
 
+// Sink of the band step (Section 2.5): stores the state like WriteSink and
+// sums the force sum_B kappa_F,B F**_B of its two cells over the bands (in
+// double), written once after the last band.  The band loop hands it
+// h = kappa_F of the cell and band.  There is no line share: force rows 2
+// and 3 are written 0.
+template <typename R>
+struct BandSink {
+  static constexpr bool kHeavy = true;
+  double fx[2], fy[2];
+  __device__ __forceinline__ void init(const GridArgs<R>&, const bool*, const unsigned*,
+                                       const int*) {
+    fx[0] = fx[1] = fy[0] = fy[1] = 0.0;
+  }
+  __device__ __forceinline__ void put(const GridArgs<R>& a, int m, int, size_t koff, unsigned c,
+                                      R h, R E, R X, R Y) {
+    R fxo, fyo;
+    reduced_flux<R>(E, X, Y, fxo, fyo);
+    __builtin_nontemporal_store(E, plane_at(a.Eo + koff, c));
+    __builtin_nontemporal_store(fxo, plane_at(a.fxo + koff, c));
+    __builtin_nontemporal_store(fyo, plane_at(a.fyo + koff, c));
+    fx[m] += (double)h * (double)X;
+    fy[m] += (double)h * (double)Y;
+  }
+  __device__ __forceinline__ void finish(const GridArgs<R>& a, const bool* own,
+                                         const unsigned* cidx) {
+    const size_t nc = (size_t)a.nx * a.ny;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      if (!own[m]) continue;
+      const size_t c = cidx[m];
+      a.force[c] = fx[m];
+      a.force[nc + c] = fy[m];
+      a.force[2 * nc + c] = 0.0;
+      a.force[3 * nc + c] = 0.0;
+    }
+  }
+};
+
 // One tile x run of bins (logical block L of grid a); BK = 0: all bins.
 // AB: the grid selects active bins (a.active); a separate instantiation, so
 // that grids advecting every bin keep the registers of the plain loop.
 // SUB: emission/absorption is left to the frequency kernel (substep rule);
 // the sink gets the post-transport state.
-template <typename R, int BK, bool AB, bool SUB, class Sink>
+// BAND: the grid holds broad bands (Section 2.5): opacities and emission
+// come per band and cell from a.kflux, a.kabs, a.jsrc instead of the
+// per-cell line data and the class profiles.
+template <typename R, int BK, bool AB, bool SUB, class Sink, bool BAND = false>
 __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigned L,
                                              AdvShared<R>& S, Sink& sink) {
+  static_assert(!(BAND && (AB || SUB)), "bands take neither active bins nor substeps");
   const int nx = a.nx, ny = a.ny, nb = a.nb;
   const size_t nc = (size_t)nx * ny;
   const int nbx = (nx + kTX - 1) / kTX, nby = (ny + kTY - 1) / kTY;
@@ -264,7 +310,11 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
       bool vac;
       if (ghost_source(x0 + ri - 1, y0 + rj - 1, nx, ny, a.bc, 1, si, sj, sgx, sgy, vac) && !vac) {
         const size_t c = (size_t)sj * nx + si;
-        ral[m] = a.alpha[c]; racF[m] = a.acF[c]; rcls[m] = a.cls[c];
+        if constexpr (BAND) {            // alpha_F = 1 * kappa_F + 0 below
+          ral[m] = R(1); racF[m] = R(0); rcls[m] = (int)c;
+        } else {
+          ral[m] = a.alpha[c]; racF[m] = a.acF[c]; rcls[m] = a.cls[c];
+        }
       }
     }
   }
@@ -313,10 +363,14 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
     own[m] = colok && gj < ny;
     cidx[m] = own[m] ? (unsigned)(gj * nx + gi) : 0u;
     const size_t c = cidx[m];
-    ccls[m] = own[m] ? a.cls[c] : 0;
-    acabs[m] = own[m] ? a.acabs[c] : R(0);
-    pda[m] = own[m] ? a.pda[c] : R(0);
-    em[m] = own[m] ? a.em[c] : R(0);
+    if constexpr (BAND) {
+      ccls[m] = 0; acabs[m] = R(0); pda[m] = R(0); em[m] = R(0);
+    } else {
+      ccls[m] = own[m] ? a.cls[c] : 0;
+      acabs[m] = own[m] ? a.acabs[c] : R(0);
+      pda[m] = own[m] ? a.pda[c] : R(0);
+      em[m] = own[m] ? a.em[c] : R(0);
+    }
     gxx[m] = own[m] ? a.grad[c] : R(0);
     gyy[m] = own[m] ? a.grad[nc + c] : R(0);
     gxy[m] = own[m] ? a.grad[2 * nc + c] : R(0);
@@ -384,13 +438,27 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
       xv[m] = Xk[q];
       yv[m] = Yk[q];
     }
+    R hcell[2], pcell[2], kcell[2];       // profiles of the owned cells for step (3)
+    if constexpr (BAND) {
+      // kappa_F of the ring, and kappa_F, L/c, kappa_abs of the owned cells
+      const R* KF = a.kflux + koff;
 #pragma unroll
-    for (int m = 0; m < kRingPerLane; ++m) hr[m] = hb[(size_t)rcls[m] * nb];
-    R hcell[2], pcell[2];                 // profiles of the owned cells for step (3)
+      for (int m = 0; m < kRingPerLane; ++m) hr[m] = *plane_at(KF, (unsigned)rcls[m]);
 #pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      hcell[m] = hb[(size_t)ccls[m] * nb];
-      pcell[m] = a.phi[(size_t)ccls[m] * nb + k];
+      for (int m = 0; m < 2; ++m) {
+        hcell[m] = *plane_at(KF, cidx[m]);
+        pcell[m] = *plane_at(a.jsrc + koff, cidx[m]);
+        kcell[m] = *plane_at(a.kabs + koff, cidx[m]);
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < kRingPerLane; ++m) hr[m] = hb[(size_t)rcls[m] * nb];
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        hcell[m] = hb[(size_t)ccls[m] * nb];
+        pcell[m] = a.phi[(size_t)ccls[m] * nb + k];
+        kcell[m] = R(0);
+      }
     }
 #pragma unroll
     for (int m = 0; m < kStagePerLane; ++m) {
@@ -451,8 +519,8 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
         sink.put(a, m, k, koff, cidx[m], hC, Es, Xs, Ys);
         continue;
       }
-      const R src = em[m] * pcell[m];
-      const R kE = acabs[m] + pda[m] * hC;
+      const R src = BAND ? pcell[m] : em[m] * pcell[m];
+      const R kE = BAND ? kcell[m] : acabs[m] + pda[m] * hC;
       const R dF = frcp(R(1) + ctdt * aFC);
       sink.put(a, m, k, koff, cidx[m], hC, (Es + ctdt * src) * frcp(R(1) + ctdt * kE), Xs * dF,
                Ys * dF);
@@ -473,6 +541,16 @@ void k_advect_source(GridArgs<R> a) {
   __shared__ AdvShared<R> S;
   WriteSink<R> sink;
   advect_block<R, BK, AB, SUB>(a, xcd_logical_block(), S, sink);
+}
+
+// The step of a grid of broad bands (Section 2.5): a block per tile walks
+// all bands, so its sink sums the force over them; no frequency step.
+template <typename R>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kAdvectWaves<R>)))
+void k_band_step(GridArgs<R> a) {
+  __shared__ AdvShared<R> S;
+  BandSink<R> sink;
+  advect_block<R, 0, false, false, BandSink<R>, true>(a, xcd_logical_block(), S, sink);
 }
 
 // Batched, persistent advection: blocks walk the work items (grid, tile x
@@ -1181,6 +1259,13 @@ hipError_t launch_advect(const GridArgs<R>& a, hipStream_t s) {
 }
 
 template <typename R>
+hipError_t launch_band_step(const GridArgs<R>& a, hipStream_t s) {
+  const unsigned nbx = (a.nx + kTX - 1) / kTX, nby = (a.ny + kTY - 1) / kTY;
+  hipLaunchKernelGGL((k_band_step<R>), dim3(nbx * nby), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_freq(const GridArgs<R>& a, hipStream_t s) {
   size_t nc = (size_t)a.nx * a.ny;
   const dim3 g((unsigned)((nc + 255) / 256));
@@ -1412,6 +1497,8 @@ template int batched_occupancy<float>(int, int);
 template int batched_occupancy<double>(int, int);
 template int freq_batched_occupancy<float>();
 template int freq_batched_occupancy<double>();
+template hipError_t launch_band_step<float>(const GridArgs<float>&, hipStream_t);
+template hipError_t launch_band_step<double>(const GridArgs<double>&, hipStream_t);
 template hipError_t launch_advect<float>(const GridArgs<float>&, hipStream_t);
 template hipError_t launch_advect<double>(const GridArgs<double>&, hipStream_t);
 template hipError_t launch_freq<float>(const GridArgs<float>&, hipStream_t);

@@ -49,6 +49,12 @@ class m1_fields(ctypes.Structure):
                [("on_device", ctypes.c_int32)]
 
 
+class m1_band_fields(ctypes.Structure):
+    _fields_ = [("u_x", ctypes.c_void_p), ("u_y", ctypes.c_void_p),
+                ("kappa_abs", ctypes.c_void_p), ("kappa_flux", ctypes.c_void_p),
+                ("emis", ctypes.c_void_p), ("on_device", ctypes.c_int32)]
+
+
 class m1_server_config(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("batched", ctypes.c_int32),
                 ("max_resident", ctypes.c_int32), ("check_every", ctypes.c_int32),
@@ -94,6 +100,9 @@ def lib():
         "m1_get_info": (I32, [VP, P(D), P(I32), P(I32), P(I64), P(I32)]),
         "m1_active_bins": (I32, [VP, VP, P(I32)]),
         "m1_dynamic_c_tilde": (I32, [P(m1_config), P(m1_fields), VP, D, VP, VP, P(D)]),
+        "m1_band_workspace_bytes": (I32, [P(m1_config), I32, P(ctypes.c_size_t)]),
+        "m1_band_init": (I32, [P(m1_config), I32, P(m1_band_fields), VP, ctypes.c_size_t, VP,
+                               P(VP)]),
         "m1_batch_workspace_bytes": (I32, [P(VP), I32, P(ctypes.c_size_t)]),
         "m1_batch_init": (I32, [P(VP), I32, VP, ctypes.c_size_t, I32, P(VP)]),
         "m1_batch_step": (I32, [VP, I32]),
@@ -128,7 +137,7 @@ def exported_symbols():
     return ["m1_default_config", "m1_num_bins", "m1_workspace_bytes",
             "m1_count_temperature_classes", "m1_init", "m1_step", "m1_force",
             "m1_solve_steady", "m1_residual", "m1_get_state", "m1_set_state", "m1_get_state_region", "m1_get_info",
-            "m1_active_bins", "m1_dynamic_c_tilde",
+            "m1_active_bins", "m1_dynamic_c_tilde", "m1_band_workspace_bytes", "m1_band_init",
             "m1_batch_workspace_bytes", "m1_batch_init", "m1_batch_step", "m1_batch_info",
             "m1_batch_free", "m1_batch_set_tile", "m1_batch_workspace_bound",
             "m1_server_create", "m1_server_submit", "m1_server_run", "m1_server_poll",
@@ -341,6 +350,76 @@ class M1Grid:
             self.free()
         except Exception:
             pass
+
+
+BAND_FIELDS = ("u_x", "u_y", "kappa_abs", "kappa_flux", "emis")
+
+
+def make_band_config(p, prec="fp64"):
+    """Config of a band problem (geometry keys, c_tilde, cfl; the frequency
+    grid fields keep their defaults)."""
+    c = m1_config()
+    check(lib().m1_default_config(ctypes.byref(c)))
+    c.geom = M1_CYL_RZ if p["geom"] == "cyl" else M1_CART2D
+    c.nx, c.ny = int(p["nx"]), int(p["ny"])
+    c.x0, c.x1, c.y0, c.y1 = float(p["x0"]), float(p["x1"]), float(p["y0"]), float(p["y1"])
+    for q in range(4):
+        c.bc[q] = BC[p["bc"][q]]
+    c.c_tilde, c.cfl = float(p["c_tilde"]), float(p["cfl"])
+    c.prec = M1_FP32 if prec == "fp32" else M1_FP64
+    return c
+
+
+def band_workspace_bytes(cfg, n_band):
+    b = ctypes.c_size_t()
+    check(lib().m1_band_workspace_bytes(ctypes.byref(cfg), int(n_band), ctypes.byref(b)))
+    return b.value
+
+
+class BandGrid(M1Grid):
+    """A grid of broad bands on the GPU (m1_band_init); stepping, state,
+    force and residual as for M1Grid, with bands in place of bins.
+
+    p: band problem dict (see inputs.band_random_small, inputs.band_hii_region)."""
+
+    def __init__(self, p, prec="fp64", stream=None, workspace=None):
+        torch = _torch()
+        self.p = p
+        self.prec = prec
+        self.cfg = make_band_config(p, prec)
+        self.nb = int(p["n_band"])
+        self.nx, self.ny = self.cfg.nx, self.cfg.ny
+        self.ncell = self.nx * self.ny
+        f = p["fields"]
+        host = [np.ascontiguousarray(f[n], dtype=np.float64).ravel() for n in BAND_FIELDS]
+        if host[0].size != self.ncell or host[1].size != self.ncell or \
+                any(h.size != self.nb * self.ncell for h in host[2:]):
+            raise ValueError("band fields must be (ny, nx) velocities and (n_band, ny, nx) tables")
+        self._host = host
+        self.ws_bytes = band_workspace_bytes(self.cfg, self.nb)
+        if workspace is None:
+            workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device="cuda")
+        self.ws = workspace
+        base = workspace.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        if self._ws_ptr + self.ws_bytes > base + workspace.numel():
+            raise ValueError("workspace tensor too small")
+        fl = m1_band_fields()
+        for n, a in zip(BAND_FIELDS, host):
+            setattr(fl, n, a.ctypes.data)
+        fl.on_device = 0
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        check(lib().m1_band_init(ctypes.byref(self.cfg), self.nb, ctypes.byref(fl), self._ws_ptr,
+                                 self.ws_bytes, self.stream.cuda_stream, ctypes.byref(h)))
+        self.h = h
+        dt, nnu, pr, nc, e2 = (ctypes.c_double(), ctypes.c_int32(), ctypes.c_int32(),
+                               ctypes.c_int64(), ctypes.c_int32())
+        check(lib().m1_get_info(h, ctypes.byref(dt), ctypes.byref(nnu), ctypes.byref(pr),
+                                ctypes.byref(nc), ctypes.byref(e2)))
+        self.dt, self.scale_exp2 = dt.value, e2.value
+        self.dtype = torch.float32 if prec == "fp32" else torch.float64
+        self.t = 0.0
 
 
 class M1Batch:

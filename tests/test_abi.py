@@ -218,3 +218,60 @@ def test_dynamic_c_tilde_argument_checks_without_device_work():
     fl.T = None
     assert L.m1_dynamic_c_tilde(ctypes.byref(cfg), ctypes.byref(fl), fake, 0.0, fake, None,
                                 ctypes.byref(out)) == m1.M1_EINVAL
+
+
+# ------------------------------------------------------------ band grids
+def _band_init_code(p, n_band=None, ws_ptr=256, ws_bytes=None, prec="fp64", cfg=None):
+    L = m1.lib()
+    c = cfg if cfg is not None else m1.make_band_config(p, prec)
+    nb = int(p["n_band"]) if n_band is None else n_band
+    f = p["fields"]
+    host = [np.ascontiguousarray(f[n], dtype=np.float64).ravel() for n in m1.BAND_FIELDS]
+    fl = m1.m1_band_fields()
+    for n, a in zip(m1.BAND_FIELDS, host):
+        setattr(fl, n, a.ctypes.data)
+    if ws_bytes is None:
+        ws_bytes = 1 << 40
+    h = ctypes.c_void_p()
+    return L.m1_band_init(ctypes.byref(c), nb, ctypes.byref(fl), ws_ptr, ws_bytes, None,
+                          ctypes.byref(h))
+
+
+def test_band_workspace_bytes():
+    p = inputs.band_random_small("cyl", 40, 24, seed=1, n_band=7)
+    c64, c32 = m1.make_band_config(p, "fp64"), m1.make_band_config(p, "fp32")
+    b64, b32 = m1.band_workspace_bytes(c64, 7), m1.band_workspace_bytes(c32, 7)
+    nbc = 7 * 40 * 24
+    assert b64 >= 9 * nbc * 8 and b32 >= 9 * nbc * 4 and b32 < b64   # state x2 + 3 tables
+    assert m1.band_workspace_bytes(c32, 14) > b32
+    L = m1.lib()
+    b = ctypes.c_size_t()
+    for n in (0, -1, 1025):
+        assert L.m1_band_workspace_bytes(ctypes.byref(c32), n, ctypes.byref(b)) == m1.M1_EINVAL
+
+
+@pytest.mark.parametrize("field,value", [("kappa_abs", -1.0), ("kappa_flux", float("nan")),
+                                         ("emis", float("inf")), ("u_x", 3.0e10),
+                                         ("emis", -1e-30)])
+def test_band_init_rejects_bad_fields_before_device_work(field, value):
+    p = inputs.band_random_small("cart", 12, 8, seed=2, n_band=3)
+    a = p["fields"][field]
+    a.flat[a.size // 2] = value
+    assert _band_init_code(p) == m1.M1_EINVAL
+    assert field in m1.lib().m1_last_error().decode()
+
+
+def test_band_init_rejects_runtime_controls_and_bad_sizes():
+    p = inputs.band_random_small("cart", 12, 8, seed=2, n_band=3)
+    c = m1.make_band_config(p)
+    c.active_frac = 1e-10
+    assert _band_init_code(p, cfg=c) == m1.M1_EUNSUPPORTED
+    c = m1.make_band_config(p)
+    c.substep_rule = 1
+    assert _band_init_code(p, cfg=c) == m1.M1_EUNSUPPORTED
+    assert _band_init_code(p, n_band=0) == m1.M1_EINVAL
+    assert _band_init_code(p, ws_ptr=256 + 8) == m1.M1_EINVAL            # misaligned
+    assert _band_init_code(p, ws_bytes=1024) == m1.M1_ENOMEM
+    c = m1.make_band_config(p)
+    c.cfl = 2.0
+    assert _band_init_code(p, cfg=c) == m1.M1_EINVAL

@@ -1,0 +1,110 @@
+"""GPU parity of the broad-band step (Section 2.5; Appendix E) against the FP64
+oracle, through the C ABI (m1_band_init, m1_step, m1_get_state, m1_force).
+
+Tolerances (relative L2 over all cells and bands, per result), as for the
+line step: FP64 1e-12 on E, F and the force; FP32 1e-5 on E and F, 1e-4 on
+the force.  Every case prints its name before touching the GPU.
+"""
+import numpy as np
+import pytest
+
+from oracle import m1_oracle as M
+from paper_2606_02711_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(a - b)) / nb if nb > 0 else float(np.linalg.norm(a))
+
+
+def random_state(p, seed):
+    """A causal random state with structure on every scale (E log-uniform
+    over 12 decades below the brightest cell's one-step emission, |f| up to
+    1), for parity from the first step on."""
+    rng = np.random.default_rng(seed)
+    sh = (p["n_band"], p["ny"], p["nx"])
+    e_ref = p["c_tilde"] * M.rt_time_step(p) * float(np.max(p["fields"]["emis"])) / M.C_LIGHT
+    E = e_ref * 10.0 ** rng.uniform(-12, 0, size=sh)
+    f = rng.uniform(0, 1, size=sh) ** 0.5
+    th = rng.uniform(0, 2 * np.pi, size=sh)
+    return E, E * f * np.cos(th), E * f * np.sin(th)
+
+
+def compare(p, steps, prec, tolE, tolF, state=None):
+    from paper_2606_02711_amd import m1
+    print(f"[gpu band] {p['geom']} {p['nx']}x{p['ny']}x{p['n_band']} steps={steps} prec={prec} "
+          f"state={'set' if state is not None else 'zero'}", flush=True)
+    g = m1.BandGrid(p, prec=prec)
+    o = M.BandOracle(p)
+    assert g.dt == pytest.approx(o.dt, rel=1e-14)
+    if state is not None:
+        g.set_state(*state)
+        o.set_state(*state)
+    g.step(steps)
+    o.step(steps)
+    E, Fx, Fy = [t.double().cpu().numpy() for t in g.state()]
+    f = g.force().cpu().numpy()
+    errs = dict(E=rel(E, o.E), Fx=rel(Fx, o.Fx), Fy=rel(Fy, o.Fy), force=rel(f, o.force))
+    print("   rel-L2", errs, flush=True)
+    assert errs["E"] <= tolE and errs["Fx"] <= tolE and errs["Fy"] <= tolE, errs
+    assert errs["force"] <= tolF, errs
+    assert np.all(np.isfinite(E)) and E.min() >= 0
+    assert np.all(np.isfinite(Fx)) and np.all(np.isfinite(Fy)) and np.all(np.isfinite(f))
+    assert np.all(f[2:] == 0)                      # no line share for bands
+    assert np.all(np.hypot(Fx, Fy) <= E * (1 + 1e-6))
+    g.free()
+    return errs
+
+
+# (geometry, nx, ny, seed, n_band): several tiles with ragged tails, the
+# smallest grid, one band and more bands than the seven of the paper
+CASES = [("cart", 70, 37, 1, 7), ("cyl", 45, 50, 2, 7), ("cyl", 4, 4, 3, 1),
+         ("cart", 33, 17, 4, 12), ("cyl", 97, 18, 5, 3)]
+
+
+@pytest.mark.parametrize("geom,nx,ny,seed,nb", CASES)
+def test_band_fp64_parity(geom, nx, ny, seed, nb):
+    p = inputs.band_random_small(geom, nx, ny, seed, n_band=nb)
+    compare(p, 8, "fp64", 1e-12, 1e-12)
+
+
+@pytest.mark.parametrize("geom,nx,ny,seed,nb", CASES)
+def test_band_fp32_parity(geom, nx, ny, seed, nb):
+    p = inputs.band_random_small(geom, nx, ny, seed, n_band=nb)
+    compare(p, 8, "fp32", 1e-5, 1e-4)
+
+
+@pytest.mark.parametrize("prec,tolE,tolF", [("fp64", 1e-12, 1e-12), ("fp32", 1e-5, 1e-4)])
+def test_band_parity_from_random_state(prec, tolE, tolF):
+    """Every term (closure at all |f|, blend at all depths, clamp) from step 1."""
+    p = inputs.band_random_small("cyl", 61, 40, 6, n_band=5)
+    compare(p, 4, prec, tolE, tolF, state=random_state(p, 6))
+
+
+def test_band_reflecting_box_and_static_gas():
+    p = inputs.band_random_small("cart", 40, 20, 7, n_band=4, with_velocity=False,
+                                 bc=("reflect",) * 4)
+    compare(p, 10, "fp64", 1e-12, 1e-12, state=random_state(p, 7))
+
+
+def test_band_hii_region_full_size_fp32():
+    """The seven-band H II-region workload at its full 512 x 1024 size, in the
+    launch the benchmark times: two steps from a random state against the
+    oracle over every cell and band."""
+    p = inputs.band_hii_region()
+    compare(p, 2, "fp32", 1e-5, 1e-4, state=random_state(p, 8))
+
+
+def test_band_grid_refused_by_batches():
+    import ctypes
+    from paper_2606_02711_amd import m1
+    print("[gpu band] batch refusal", flush=True)
+    g = m1.BandGrid(inputs.band_random_small("cart", 16, 16, 9, n_band=2), prec="fp32")
+    hs = (ctypes.c_void_p * 1)(g.h.value)
+    b = ctypes.c_size_t()
+    assert m1.lib().m1_batch_workspace_bytes(hs, 1, ctypes.byref(b)) == m1.M1_EUNSUPPORTED
+    flags = g.active_bins()
+    assert flags.tolist() == [1, 1]
+    g.free()
