@@ -260,9 +260,17 @@ def run_bands(steps, warmup):
         wall = time.perf_counter() - t0
         ms = a / steps
         alg = band_bytes(nc, nb, prec) / (ms * 1e-3) / 1e9
-        out[prec] = {"value": nc * nb * steps / wall, "ms_per_step": 1e3 * wall / steps,
-                     "kernel_ms": ms, "algorithmic_bytes": band_bytes(nc, nb, prec),
-                     "algorithmic_GBs": alg, "frac": alg / HBM_PEAK_GBS}
+        rec = {"value": nc * nb * steps / wall, "ms_per_step": 1e3 * wall / steps,
+               "kernel_ms": ms, "algorithmic_bytes": band_bytes(nc, nb, prec),
+               "algorithmic_GBs": alg, "frac": alg / HBM_PEAK_GBS}
+        t = measured_traffic("band_step", prec)
+        if t is not None:
+            rec.update(traffic_bytes=t, traffic_GBs=t / (ms * 1e-3) / 1e9)
+        v = measured_valu("band_step", prec)
+        if v is not None:
+            rec.update(valu_per_cell_band=v,
+                       valu_issue_frac=v * nc * nb / (ms * 1e-3) / VALU_PEAK)
+        out[prec] = rec
         g.free()
         torch.cuda.empty_cache()
     return out

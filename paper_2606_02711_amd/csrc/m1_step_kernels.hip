@@ -238,10 +238,11 @@ struct WriteSink {
 // sums the force sum_B kappa_F,B F**_B of its two cells over the bands (in
 // double), written once after the last band.  The band loop hands it
 // h = kappa_F of the cell and band.  There is no line share: force rows 2
-// and 3 are written 0.
+// and 3 are written 0.  Its sums cost the float kernel the registers of the
+// unrolled face runs (they would spill); double keeps its two-face unroll.
 template <typename R>
 struct BandSink {
-  static constexpr bool kHeavy = true;
+  static constexpr bool kHeavy = sizeof(R) == 4;
   double fx[2], fy[2];
   __device__ __forceinline__ void init(const GridArgs<R>&, const bool*, const unsigned*,
                                        const int*) {
