@@ -264,8 +264,8 @@ int32_t m1_band_workspace_bytes(const m1_config *cfg, int32_t n_band, size_t *by
 int32_t m1_band_init(const m1_config *cfg, int32_t n_band, const m1_band_fields *fields,
                      void *d_ws, size_t ws_bytes, void *stream, m1_handle **out);
 
-/* ---- batches: many grids advanced by one persistent launch per kernel and
- * step (a throughput addition with no counterpart in the paper).
+/* ---- batches: many grids advanced by one launch per kernel and step (a
+ * throughput addition with no counterpart in the paper).
  * A batch groups n handles of the same precision on the same stream.  Its
  * descriptor tables live in a caller workspace of m1_batch_workspace_bytes
  * bytes (256-byte aligned); the library allocates no device memory.  Every
@@ -316,7 +316,7 @@ int32_t m1_batch_workspace_bound(int32_t n, int32_t prec, size_t *bytes);
  *
  * m1_server_run performs rounds.  In a round every resident request takes
  * min(check_every, max_steps - steps) steps (in batched mode all requests
- * whose share is check_every advance together in one persistent batch;
+ * whose share is check_every advance together in one batch;
  * otherwise one request at a time, in order) and then its residual is
  * computed; a request whose residual is below rel_tol, or that reached
  * max_steps, is finished.  This is the schedule of m1_solve_steady, so each

@@ -1145,19 +1145,12 @@ int32_t m1_batch_init(m1_handle* const* hs, int32_t n, void* d_ws, size_t ws_byt
     totf += freq_blocks(hs[q]->cfg.nx, hs[q]->cfg.ny);
     offf[q + 1] = (int)totf;
   }
-  int dev = 0, ncu = 0;
-  (void)hipGetDevice(&dev);
-  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
-    ncu = 256;
   for (int q = 0; q < n; ++q)
     if (hs[q]->cfg.active_frac > 0.0) b->active = 1;
-  for (int v = 0; v < kNumBatchVariants; ++v) {
-    int occ = b->prec == M1_FP32 ? batched_occupancy<float>(v, b->active)
-                                 : batched_occupancy<double>(v, b->active);
-    b->blocks_adv[v] = (int)std::min<int64_t>(tot[v], (int64_t)ncu * occ);
-  }
-  int occf = b->prec == M1_FP32 ? freq_batched_occupancy<float>() : freq_batched_occupancy<double>();
-  b->blocks_freq = (int)std::min<int64_t>(totf, (int64_t)ncu * occf);
+  // a block per work item (capped; the kernels stride over any rest)
+  constexpr int64_t kMaxBlocks = int64_t(1) << 30;
+  for (int v = 0; v < kNumBatchVariants; ++v) b->blocks_adv[v] = (int)std::min(tot[v], kMaxBlocks);
+  b->blocks_freq = (int)std::min(totf, kMaxBlocks);
   b->par.resize(n);
   for (int q = 0; q < n; ++q) b->par[q] = hs[q]->cur;
   b->sp = 0;

@@ -36,10 +36,6 @@ hipError_t launch_advect_batched(int variant, const GridArgs<R>* args, const int
 template <typename R>
 hipError_t launch_freq_batched(const GridArgs<R>* args, const int* par, int n, int sp,
                                const int* off, int nblocks, int islands, hipStream_t s);
-template <typename R>
-int batched_occupancy(int variant, int active);
-template <typename R>
-int freq_batched_occupancy();
 
 // Active bins of a state E [nb][ny][nx]: per-bin energies with cell volumes
 // wx[i] wy[j] into part [nb][energy_chunks], then flags active[k].

@@ -554,11 +554,14 @@ void k_band_step(GridArgs<R> a) {
   advect_block<R, 0, false, false, BandSink<R>, true>(a, xcd_logical_block(), S, sink);
 }
 
-// Batched, persistent advection: blocks walk the work items (grid, tile x
-// run of bins) of every grid of a batch in a fixed order, strided by the grid
-// size from their XCD-ordered index, so that the blocks of one XCD work on
-// one contiguous range of tiles at a time and share its halo lines in their
-// L2.  off[g] is the
+// Batched advection: one launch covers the work items (grid, tile x run of
+// bins) of every grid of a batch.  A block takes the item of its XCD-ordered
+// index (and, when a batch has more items than the launch has blocks, every
+// grid-size stride after it), so that the blocks of one XCD work on one
+// contiguous range of tiles and share its halo lines in their L2.  The host
+// launches a block per item: the hardware then balances the blocks over the
+// CUs (a persistent grid of CUs x occupancy blocks was 9 % slower: its
+// blocks stay in step through the per-item set-up).  off[g] is the
 // first work item of grid g (off[n] = total); args holds both ping-pong
 // directions, [2][n]; grid g uses direction par[g] ^ sp.
 template <typename R, int BK, bool AB>
@@ -1012,7 +1015,8 @@ __global__ __launch_bounds__(256) void k_freq_sub(GridArgs<R> a) {
   }
 }
 
-// Batched, persistent frequency step: work item = 256 cells of one grid.
+// Batched frequency step: work item = 256 cells of one grid (a block per
+// item, as for the advection).
 template <typename R, int P>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFreqWaves<R, P>)))
 void k_freq_batched(const GridArgs<R>* __restrict__ args,
@@ -1134,7 +1138,7 @@ struct FusedSink {
   }
 };
 
-// Batched, persistent fused step: work item = one tile (all bins) of a grid.
+// Batched fused step: work item = one tile (all bins) of a grid.
 // Four waves per SIMD (128 registers).
 template <bool AB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
@@ -1411,32 +1415,6 @@ hipError_t launch_freq_batched(const GridArgs<R>* args, const int* par, int n, i
   return hipGetLastError();
 }
 
-template <typename R, bool AB>
-int batched_occupancy_ab(int variant) {
-  int nb = 0;
-  hipError_t e;
-  switch (variant) {
-    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_advect_batched<R, 7, AB>, 256, 0); break;
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_advect_batched<R, 14, AB>, 256, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_advect_batched<R, 28, AB>, 256, 0); break;
-    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_advect_batched<R, 49, AB>, 256, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_fused_batched<AB>, 256, 0); break;
-  }
-  return e == hipSuccess && nb > 0 ? nb : 1;
-}
-
-template <typename R>
-int batched_occupancy(int variant, int active) {
-  return active ? batched_occupancy_ab<R, true>(variant) : batched_occupancy_ab<R, false>(variant);
-}
-
-template <typename R>
-int freq_batched_occupancy() {
-  int nb = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_freq_batched<R, 0>, 256, 0);
-  return e == hipSuccess && nb > 0 ? nb : 1;
-}
-
 template <typename R>
 hipError_t launch_step(const GridArgs<R>& a, hipStream_t s) {
   hipError_t e = launch_advect(a, s);
@@ -1494,10 +1472,6 @@ template hipError_t launch_advect_batched<float>(int, const GridArgs<float>*, co
 template hipError_t launch_advect_batched<double>(int, const GridArgs<double>*, const int*, int, int, const int*, int, int, hipStream_t);
 template hipError_t launch_freq_batched<float>(const GridArgs<float>*, const int*, int, int, const int*, int, int, hipStream_t);
 template hipError_t launch_freq_batched<double>(const GridArgs<double>*, const int*, int, int, const int*, int, int, hipStream_t);
-template int batched_occupancy<float>(int, int);
-template int batched_occupancy<double>(int, int);
-template int freq_batched_occupancy<float>();
-template int freq_batched_occupancy<double>();
 template hipError_t launch_band_step<float>(const GridArgs<float>&, hipStream_t);
 template hipError_t launch_band_step<double>(const GridArgs<double>&, hipStream_t);
 template hipError_t launch_advect<float>(const GridArgs<float>&, hipStream_t);

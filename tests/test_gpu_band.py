@@ -108,3 +108,34 @@ def test_band_grid_refused_by_batches():
     flags = g.active_bins()
     assert flags.tolist() == [1, 1]
     g.free()
+
+
+@pytest.mark.parametrize("geom,prec,tol", [("cart", "fp64", 1e-10), ("cyl", "fp64", 1e-10),
+                                           ("cart", "fp32", 1e-5), ("cyl", "fp32", 1e-5)])
+def test_band_steady_state_of_closed_uniform_box(geom, prec, tol):
+    """m1_solve_steady on a band grid: a closed reflecting box of uniform
+    absorbing and emitting gas settles at E* = L/(c kappa_abs) in every band
+    (transport balances exactly for a uniform isotropic state), F = 0."""
+    from paper_2606_02711_amd import m1
+    print(f"[gpu band] steady box {geom} {prec}", flush=True)
+    nx, ny, dx = 40, 36, 1.0e16
+    y0 = -0.5 * ny * dx if geom == "cyl" else 0.0
+    p = inputs.band_base(inputs.base_problem(geom, nx, ny, 0.0, nx * dx, y0, y0 + ny * dx,
+                                             ("reflect",) * 4), 3)
+    ka = np.array([2.0e-17, 5.0e-17, 1.0e-16])
+    em = np.array([1.0e-21, 3.0e-23, 2.0e-22])
+    sh = (3, ny, nx)
+    p["fields"] = dict(u_x=np.zeros((ny, nx)), u_y=np.zeros((ny, nx)),
+                       kappa_abs=np.broadcast_to(ka[:, None, None], sh).copy(),
+                       kappa_flux=np.broadcast_to(3 * ka[:, None, None], sh).copy(),
+                       emis=np.broadcast_to(em[:, None, None], sh).copy())
+    g = m1.BandGrid(p, prec=prec)
+    ok, steps, r = g.solve_steady(rel_tol=1e-13 if prec == "fp64" else 1e-7, max_steps=20000,
+                                  check_every=50)
+    E, Fx, Fy = [t.cpu().numpy() for t in g.state()]
+    want = em / (M.C_LIGHT * ka)
+    print(f"   steps {steps} r {r:.2e}", flush=True)
+    for b in range(3):
+        assert np.max(np.abs(E[b] / want[b] - 1)) <= tol
+    assert np.max(np.hypot(Fx, Fy)) <= 1e-6 * E.max()
+    g.free()
