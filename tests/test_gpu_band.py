@@ -139,3 +139,39 @@ def test_band_steady_state_of_closed_uniform_box(geom, prec, tol):
         assert np.max(np.abs(E[b] / want[b] - 1)) <= tol
     assert np.max(np.hypot(Fx, Fy)) <= 1e-6 * E.max()
     g.free()
+
+
+def test_band_init_from_device_fields_matches_host_fields():
+    """m1_band_init with device-resident inputs (on_device = 1) gives the
+    grid a host-initialised one gets: same time step, scale and state bits
+    after several steps."""
+    import ctypes
+    import torch
+    from paper_2606_02711_amd import m1
+    print("[gpu band] device-resident fields", flush=True)
+    p = inputs.band_random_small("cyl", 37, 29, 11, n_band=5)
+    ref = m1.BandGrid(p, prec="fp32")
+    ref.step(5)
+    E0 = ref.state()[0].cpu().numpy()
+    cfg = m1.make_band_config(p, "fp32")
+    ws = torch.empty(ref.ws_bytes + 256, dtype=torch.uint8, device="cuda")
+    ptr = (ws.data_ptr() + 255) & ~255
+    dev = [torch.as_tensor(np.ascontiguousarray(p["fields"][n], dtype=np.float64).ravel(),
+                           device="cuda") for n in m1.BAND_FIELDS]
+    fl = m1.m1_band_fields()
+    for n, t in zip(m1.BAND_FIELDS, dev):
+        setattr(fl, n, t.data_ptr())
+    fl.on_device = 1
+    torch.cuda.current_stream().synchronize()
+    h = ctypes.c_void_p()
+    m1.check(m1.lib().m1_band_init(ctypes.byref(cfg), 5, ctypes.byref(fl), ptr, ref.ws_bytes,
+                                   torch.cuda.current_stream().cuda_stream, ctypes.byref(h)))
+    dt, e2 = ctypes.c_double(), ctypes.c_int32()
+    m1.check(m1.lib().m1_get_info(h, ctypes.byref(dt), None, None, None, ctypes.byref(e2)))
+    assert dt.value == ref.dt and e2.value == ref.scale_exp2
+    m1.check(m1.lib().m1_step(h, 5, None))
+    E = torch.empty((5, 29, 37), dtype=torch.float64, device="cuda")
+    m1.check(m1.lib().m1_get_state(h, E.data_ptr(), None, None))
+    assert np.array_equal(E.cpu().numpy(), E0)
+    m1.lib().m1_free(h)
+    ref.free()
