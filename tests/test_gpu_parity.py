@@ -291,3 +291,32 @@ def test_dust_only_destruction_and_full_speed_of_light():
     p["c_tilde"] = inputs.C_LIGHT
     compare(p, 7, "fp64", 1e-12, 1e-12)
     compare(p, 7, "fp32", 1e-5, 1e-4)
+
+
+def test_batch_workload_full_size_equals_alone_bitwise():
+    """The 64-grid workload the benchmark times as a batch (sides 64..512,
+    6.3e8 cell-bins), FP32, in the benchmark's launch configuration: the
+    15 tuning steps, a replayed step pair and an odd step, then every grid
+    against the same grid stepped alone (whose path the parity tests pin to
+    the oracle), bitwise, compared on the device."""
+    import torch
+    from paper_2606_02711_amd import m1
+    ps = inputs.config3()
+    print(f"[gpu] batch workload full size: {len(ps)} grids", flush=True)
+    s = torch.cuda.Stream()
+    gs = [m1.M1Grid(p, prec="fp32", stream=s) for p in ps]
+    b = m1.M1Batch(gs, use_graph=True)
+    b.step(15)
+    b.step(3)
+    s.synchronize()
+    for q, (p, g) in enumerate(zip(ps, gs)):
+        a = m1.M1Grid(p, prec="fp32")
+        a.step(18)
+        for x, y in zip(g.state(), a.state()):
+            assert torch.equal(x, y), q
+        assert torch.equal(g.force(), a.force()), q
+        a.free()
+    b.free()
+    for g in gs:
+        g.free()
+    torch.cuda.empty_cache()
