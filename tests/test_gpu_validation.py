@@ -7,6 +7,12 @@ the force multiplier against the thick-cloud relation M_F = 0.51 (a_v
 tau_cl)^(1/3) within 5 % at tau_cl = 1e7 and 1e8 (this implementation:
 8.51 vs 8.54 and 17.87 vs 18.41).
 
+Dusty static clouds (Test 5): at tau_cl = 1e8 the paper states that M_F
+falls roughly as 1/tau_c once (a_v tau_cl)^(1/3) tau_c >~ 1 (tau_c >~ 0.03
+here).  At tau_c = 0.25 and 1 (9 and 36 times that threshold), M_F tau_c
+must agree within 15 % and M_F must lie far below the dust-free value (this
+implementation: M_F = 2.963 and 0.803, M_F tau_c = 0.741 and 0.803).
+
 Anisotropic escape through a bipolar cone at 256^2 cells, FP32, run to half
 of the paper's t_max (the multipliers have converged to four digits by then:
 the full run gives the same values).  The paper's code reports M_F = 24.45 and
@@ -49,3 +55,21 @@ def test_static_sphere_follows_thick_asymptote(i):
     want = ref["M_F_coefficient"] * (ref["a_v_1e4K"] * tau) ** (1.0 / 3.0)
     assert r["M_F"] == pytest.approx(want, rel=0.05)
     assert r["M_F_radial"] == pytest.approx(r["M_F"], rel=0.01)     # spherical symmetry
+
+
+def test_dusty_sphere_force_multiplier_falls_as_one_over_tau_c():
+    from paper_2606_02711_amd import inputs, validation
+    ref = json.load(open(GOLDEN_T1))
+    tau = 1.0e8
+    dust_free = ref["M_F_coefficient"] * (ref["a_v_1e4K"] * tau) ** (1.0 / 3.0)
+    mf = {}
+    for tc in (0.25, 1.0):
+        print(f"[gpu] dusty sphere 64^2 fp32 tau_cl=1e8 tau_c={tc}", flush=True)
+        p = inputs.static_sphere(64, tau_cl=tau, tau_c=tc)
+        r = validation.run_cone(64, "fp32", problem=p, name="dusty sphere", checkpoints=2,
+                                log=lambda s: print(s, flush=True))
+        (_, _, m1_, _), (_, _, m2_, _) = r["history"]
+        assert abs(m2_ - m1_) < 0.01 * m2_                  # steady by t_max/2
+        mf[tc] = r["M_F"]
+    assert mf[1.0] * 1.0 == pytest.approx(mf[0.25] * 0.25, rel=0.15)
+    assert mf[1.0] < mf[0.25] < 0.25 * dust_free
