@@ -245,14 +245,16 @@ def cone_cloud(n=256, R_cl=PC, tau_cl=1.0e8, tau_cone=1.0e5, T=1.0e4, mu_cone=2 
     return p
 
 
-def static_sphere(n=64, R_cl=PC, tau_cl=1.0e6, T=1.0e4, tau_c=0.0):
-    """Static cloud of Section 4 (Tests 1, 4 and 5): a uniform sphere of
+def static_sphere(n=64, R_cl=PC, tau_cl=1.0e6, T=1.0e4, tau_c=0.0, v_exp=0.0):
+    """Uniform cloud of Section 4 (Tests 1, 2, 4 and 5): a uniform sphere of
     radius R_cl at T with line-centre depth tau_cl = n_HI sigma0(T) R_cl and
     uniform emission (1 erg/s in the box), vacuum outside; box
     [0, 1.1 R_cl]^2 in (R, Z) with reflecting axis and midplane, outflow at the
     outer edges; c_tilde = c; no recoil, no destruction.  tau_c: continuum
     (dust) absorption depth alpha_c R_cl inside the cloud, pure absorption
-    (albedo 0, so the flux opacity equals it); 0 for the dust-free Test 1."""
+    (albedo 0, so the flux opacity equals it); 0 for the dust-free Test 1.
+    v_exp: expansion rate dR_cl/dt [cm/s] of a Hubble-like flow
+    u = (v_exp / R_cl) r r_hat inside the cloud (Test 2); gas at rest outside."""
     half = 1.1 * R_cl
     p = base_problem("cyl", n, n, 0.0, half, 0.0, half,
                      ("reflect", "vacuum", "reflect", "vacuum"), c_tilde_frac=1.0)
@@ -264,6 +266,8 @@ def static_sphere(n=64, R_cl=PC, tau_cl=1.0e6, T=1.0e4, tau_c=0.0):
     f["n_HI"] = np.where(inside, tau_cl / (sig0 * R_cl), 0.0)
     f["alpha_abs"] = np.where(inside, tau_c / R_cl, 0.0)
     f["alpha_flux"] = f["alpha_abs"].copy()
+    f["u_x"] = np.where(inside, (v_exp / R_cl) * R[None, :], 0.0)
+    f["u_y"] = np.where(inside, (v_exp / R_cl) * Z[:, None], 0.0)
     src = inside.astype(float)
     f["emis"] = src / float(np.sum(src * cell_volumes(p)))
     p["fields"] = f

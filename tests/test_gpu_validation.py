@@ -13,6 +13,13 @@ here).  At tau_c = 0.25 and 1 (9 and 36 times that threshold), M_F tau_c
 must agree within 15 % and M_F must lie far below the dust-free value (this
 implementation: M_F = 2.963 and 0.803, M_F tau_c = 0.741 and 0.803).
 
+Expanding clouds (Test 2): a Hubble-like flow u = (dR/dt / R_cl) r r_hat
+suppresses M_F, more so the faster the expansion (the paper compares its
+curve with Monte Carlo and an analytic solution that it does not print).
+At tau_cl = 1e8 and 64^2 this implementation gives M_F = 17.87, 17.14,
+13.56, 6.48, 2.68 for 0, 10, 30, 100, 300 km/s; the test checks 30 and
+300 km/s against the dust-free relation and each other.
+
 Anisotropic escape through a bipolar cone at 256^2 cells, FP32, run to half
 of the paper's t_max (the multipliers have converged to four digits by then:
 the full run gives the same values).  The paper's code reports M_F = 24.45 and
@@ -73,3 +80,22 @@ def test_dusty_sphere_force_multiplier_falls_as_one_over_tau_c():
         mf[tc] = r["M_F"]
     assert mf[1.0] * 1.0 == pytest.approx(mf[0.25] * 0.25, rel=0.15)
     assert mf[1.0] < mf[0.25] < 0.25 * dust_free
+
+
+def test_expanding_sphere_suppresses_force_multiplier():
+    from paper_2606_02711_amd import inputs, validation
+    ref = json.load(open(GOLDEN_T1))
+    tau = 1.0e8
+    static = ref["M_F_coefficient"] * (ref["a_v_1e4K"] * tau) ** (1.0 / 3.0)
+    mf = {}
+    for v in (30.0, 300.0):
+        print(f"[gpu] expanding sphere 64^2 fp32 tau_cl=1e8 dR/dt={v} km/s", flush=True)
+        p = inputs.static_sphere(64, tau_cl=tau, v_exp=v * 1.0e5)
+        r = validation.run_cone(64, "fp32", problem=p, name="expanding sphere", checkpoints=2,
+                                log=lambda s: print(s, flush=True))
+        (_, _, m1_, _), (_, _, m2_, _) = r["history"]
+        assert abs(m2_ - m1_) < 0.01 * m2_                  # steady by t_max/2
+        assert r["M_F_radial"] == pytest.approx(r["M_F"], rel=0.01)
+        mf[v] = r["M_F"]
+    assert mf[30.0] < 0.9 * static
+    assert mf[300.0] < 0.5 * mf[30.0]
