@@ -138,6 +138,13 @@ int32_t m1_default_config(m1_config *cfg);
 /* Number of frequency bins of cfg's grid (194 with the defaults; Section 2.1). */
 int32_t m1_num_bins(const m1_config *cfg, int32_t *n_nu);
 
+/* The bins of cfg's grid (Section 2.1: widths Delta nu_D(T_min) q^m outwards
+ * from line centre, symmetric, the outermost clipped at the half-width):
+ * nu_centre[k] the absolute centre frequency [Hz] (arithmetic midpoint of
+ * the edges) and dnu[k] the width [Hz], k < m1_num_bins; host arrays, either
+ * may be NULL.  Host-only (no device work); M1_EINVAL for an invalid cfg. */
+int32_t m1_frequency_grid(const m1_config *cfg, double *nu_centre, double *dnu);
+
 /* Exact device workspace bytes for cfg when the temperature field holds
  * n_temp_classes distinct values (pass 0 for the worst case, one per cell).
  * m1_count_temperature_classes gives that number for a host T array. */

@@ -683,6 +683,17 @@ int32_t m1_num_bins(const m1_config* cfg, int32_t* n_nu) {
   return M1_OK;
 }
 
+int32_t m1_frequency_grid(const m1_config* cfg, double* nu_centre, double* dnu) {
+  int st = validate_config(cfg, nullptr);
+  if (st) return st;
+  FreqGrid g;
+  st = build_grid(*cfg, g);
+  if (st) return st;
+  if (nu_centre) memcpy(nu_centre, g.nuc.data(), g.nb * sizeof(double));
+  if (dnu) memcpy(dnu, g.dnu.data(), g.nb * sizeof(double));
+  return M1_OK;
+}
+
 int32_t m1_dynamic_c_tilde(const m1_config* cfg, const m1_fields* f, const double* d_cs,
                            double c_prev, void* d_work, void* stream, double* c_tilde) {
   int st = validate_config(cfg, nullptr);

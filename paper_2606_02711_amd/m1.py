@@ -87,6 +87,7 @@ def lib():
     sig = {
         "m1_default_config": (I32, [P(m1_config)]),
         "m1_num_bins": (I32, [P(m1_config), P(I32)]),
+        "m1_frequency_grid": (I32, [P(m1_config), VP, VP]),
         "m1_workspace_bytes": (I32, [P(m1_config), I64, P(ctypes.c_size_t)]),
         "m1_count_temperature_classes": (I32, [VP, I64, P(I64)]),
         "m1_init": (I32, [P(m1_config), P(m1_fields), VP, ctypes.c_size_t, VP, P(VP)]),
@@ -134,7 +135,7 @@ def lib():
 
 
 def exported_symbols():
-    return ["m1_default_config", "m1_num_bins", "m1_workspace_bytes",
+    return ["m1_default_config", "m1_num_bins", "m1_frequency_grid", "m1_workspace_bytes",
             "m1_count_temperature_classes", "m1_init", "m1_step", "m1_force",
             "m1_solve_steady", "m1_residual", "m1_get_state", "m1_set_state", "m1_get_state_region", "m1_get_info",
             "m1_active_bins", "m1_dynamic_c_tilde", "m1_band_workspace_bytes", "m1_band_init",
@@ -177,6 +178,15 @@ def num_bins(cfg):
     n = ctypes.c_int32()
     check(lib().m1_num_bins(ctypes.byref(cfg), ctypes.byref(n)))
     return n.value
+
+
+def frequency_grid(cfg):
+    """(nu_centre, dnu) [Hz] of cfg's bins (m1_frequency_grid), numpy arrays."""
+    n = num_bins(cfg)
+    nu = np.zeros(n)
+    dnu = np.zeros(n)
+    check(lib().m1_frequency_grid(ctypes.byref(cfg), nu.ctypes.data, dnu.ctypes.data))
+    return nu, dnu
 
 
 def workspace_bytes(cfg, n_classes=0):

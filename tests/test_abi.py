@@ -275,3 +275,20 @@ def test_band_init_rejects_runtime_controls_and_bad_sizes():
     c = m1.make_band_config(p)
     c.cfl = 2.0
     assert _band_init_code(p, cfg=c) == m1.M1_EINVAL
+
+
+@pytest.mark.parametrize("q,hw,T_min", [(1.1, 1.0e5, 30.0), (1.03, 1.0e5, 30.0), (1.1, 1.0e3, 100.0)])
+def test_frequency_grid_matches_oracle(q, hw, T_min):
+    """m1_frequency_grid (host-side, no GPU) against the oracle's own
+    construction of the Section 2.1 grid: same bins, centres and widths."""
+    from oracle import m1_oracle as M
+    c = m1.m1_config()
+    m1.check(m1.lib().m1_default_config(ctypes.byref(c)))
+    c.q, c.half_width, c.T_min = q, hw, T_min
+    nu, dnu = m1.frequency_grid(c)
+    g = M.frequency_grid(T_min, q, hw)
+    assert len(nu) == g["nb"]
+    np.testing.assert_allclose(nu, g["nu_c"], rtol=1e-15)
+    np.testing.assert_allclose(dnu, g["dnu"], rtol=1e-12)
+    c.q = 0.9
+    assert m1.lib().m1_frequency_grid(ctypes.byref(c), None, None) == m1.M1_EINVAL
