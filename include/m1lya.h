@@ -219,6 +219,17 @@ int32_t m1_set_state(m1_handle *h, const double *d_E, const double *d_Fx,
 int32_t m1_get_state_region(m1_handle *h, int32_t i0, int32_t i1, int32_t j0, int32_t j1,
                             double *d_E, double *d_Fx, double *d_Fy);
 
+/* Sets a grid's reduced speed of light to c_tilde (0 < c_tilde <= c), e.g.
+ * the value m1_dynamic_c_tilde chose for the current medium (Section 2.1,
+ * dynamic RSL), keeping the state: the time step becomes the CFL step of the
+ * new c_tilde (m1_get_info reports it) and the geometry factors scaled by
+ * c_tilde dt are rebuilt.  Line and band grids.  Waits for the handle's
+ * stream (work already enqueued finishes with the old value).  A batch that
+ * holds the handle uploads its new arguments at its next step.  M1_EINVAL
+ * for a NULL handle or a c_tilde outside (0, c]; M1_ESTATE after a device
+ * error. */
+int32_t m1_set_c_tilde(m1_handle *h, double c_tilde);
+
 /* Which bins the last step advected (Section 2.1, runtime controls):
  * flags_host[k] = 1 for an advected bin, 0 otherwise (N_nu int32 entries;
  * may be NULL), *n_active (may be NULL) their count.  With active_frac = 0

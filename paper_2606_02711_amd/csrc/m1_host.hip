@@ -257,6 +257,8 @@ struct m1_handle {
   GridArgs<double> ad[2];
   bool broken = false;
   bool band = false;          // a grid of broad bands (m1_band_init)
+  double umax = 0.0;          // largest gas speed (the CFL step's |u|)
+  int64_t gen = 0;            // bumped when the kernel arguments change
 };
 
 namespace {
@@ -457,6 +459,7 @@ int init_typed(m1_handle* h, const m1_fields* f, const std::vector<std::vector<d
   double dx = (c.x1 - c.x0) / c.nx, dy = (c.y1 - c.y0) / c.ny;
   double dmin = std::min(dx, dy);
   h->dt = c.cfl * 0.5 * (dmin / (c.c_tilde + umax));
+  h->umax = umax;
   double ctdt = c.c_tilde * h->dt;
   // internal scale: first-step line-centre energy density of the brightest
   // cell ~ 1 (exact power of two, so results are scaled exactly)
@@ -594,6 +597,7 @@ int band_init_typed(m1_handle* h, const m1_band_fields* f,
   const int nx = c.nx, ny = c.ny;
   const double dx = (c.x1 - c.x0) / nx, dy = (c.y1 - c.y0) / ny;
   h->dt = c.cfl * 0.5 * (std::min(dx, dy) / (c.c_tilde + umax));
+  h->umax = umax;
   const double ctdt = c.c_tilde * h->dt;
   // internal scale: the brightest cell's first-step emission ~ 1 (a power
   // of two, so results are scaled exactly)
@@ -896,6 +900,36 @@ int32_t m1_active_bins(m1_handle* h, int32_t* flags_host, int32_t* n_active) {
   return M1_OK;
 }
 
+extern "C++" {
+namespace {
+template <typename R>
+int set_geometry(m1_handle* h) {
+  std::vector<double> xe, ye;
+  std::vector<R> geo = build_geometry<R>(h->cfg, h->cfg.c_tilde * h->dt, xe, ye);
+  HIPCHK(hipMemcpyAsync(h->ws + h->L.geo, geo.data(), geo.size() * sizeof(R),
+                        hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return M1_OK;
+}
+}  // namespace
+}  // extern "C++"
+
+int32_t m1_set_c_tilde(m1_handle* h, double c_tilde) {
+  if (!h) return fail(M1_EINVAL, "handle is NULL");
+  if (h->broken) return fail(M1_ESTATE, "handle had a device error");
+  if (!(c_tilde > 0.0) || !(c_tilde <= kC)) return fail(M1_EINVAL, "need 0 < c_tilde <= c");
+  m1_config& c = h->cfg;
+  c.c_tilde = c_tilde;
+  const double dx = (c.x1 - c.x0) / c.nx, dy = (c.y1 - c.y0) / c.ny;
+  h->dt = c.cfl * 0.5 * (std::min(dx, dy) / (c_tilde + h->umax));
+  int st = c.prec == M1_FP32 ? set_geometry<float>(h) : set_geometry<double>(h);
+  if (st) { h->broken = true; return st; }
+  if (h->band) { fill_band_args<float>(h, h->af); fill_band_args<double>(h, h->ad); }
+  else { fill_args<float>(h, h->af); fill_args<double>(h, h->ad); }
+  h->gen += 1;
+  return M1_OK;
+}
+
 int32_t m1_get_info(const m1_handle* h, double* dt, int32_t* n_nu, int32_t* prec, int64_t* ncell,
                     int32_t* scale_exp2) {
   if (!h) return fail(M1_EINVAL, "handle is NULL");
@@ -1021,6 +1055,7 @@ struct m1_batch {
   bool use_graph = false;
   hipGraphExec_t exec = nullptr;
   int graph_sp = -1;                    // parity at which the graph starts
+  std::vector<int64_t> gen;             // members' argument generations uploaded
 };
 
 namespace {
@@ -1071,6 +1106,15 @@ int upload_args(m1_batch* b) {
 }
 
 int sync_parity(m1_batch* b) {
+  bool fresh = true;
+  for (int q = 0; q < b->n; ++q)
+    if (b->gen[q] != b->hs[q]->gen) fresh = false;
+  if (!fresh) {               // a member's c_tilde changed: new descriptor table
+    int st = b->prec == M1_FP32 ? upload_args<float>(b) : upload_args<double>(b);
+    if (st) return st;
+    for (int q = 0; q < b->n; ++q) b->gen[q] = b->hs[q]->gen;
+    if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; b->graph_sp = -1; }
+  }
   bool same = true;
   for (int q = 0; q < b->n; ++q)
     if ((b->par[q] ^ b->sp) != b->hs[q]->cur) same = false;
@@ -1174,6 +1218,8 @@ int32_t m1_batch_init(m1_handle* const* hs, int32_t n, void* d_ws, size_t ws_byt
     e = hipMemcpyAsync(b->ws + b->par_off, b->par.data(), n * sizeof(int), hipMemcpyHostToDevice,
                        b->stream);
   if (e != hipSuccess) { delete b; return fail(M1_EDEVICE, "batch upload: %s", hipGetErrorString(e)); }
+  b->gen.resize(n);
+  for (int q = 0; q < n; ++q) b->gen[q] = hs[q]->gen;
   st = b->prec == M1_FP32 ? upload_args<float>(b) : upload_args<double>(b);
   if (st) { delete b; return st; }
   *out = b;

@@ -100,6 +100,7 @@ def lib():
         "m1_get_state_region": (I32, [VP, I32, I32, I32, I32, VP, VP, VP]),
         "m1_get_info": (I32, [VP, P(D), P(I32), P(I32), P(I64), P(I32)]),
         "m1_active_bins": (I32, [VP, VP, P(I32)]),
+        "m1_set_c_tilde": (I32, [VP, D]),
         "m1_dynamic_c_tilde": (I32, [P(m1_config), P(m1_fields), VP, D, VP, VP, P(D)]),
         "m1_band_workspace_bytes": (I32, [P(m1_config), I32, P(ctypes.c_size_t)]),
         "m1_band_init": (I32, [P(m1_config), I32, P(m1_band_fields), VP, ctypes.c_size_t, VP,
@@ -138,7 +139,7 @@ def exported_symbols():
     return ["m1_default_config", "m1_num_bins", "m1_frequency_grid", "m1_workspace_bytes",
             "m1_count_temperature_classes", "m1_init", "m1_step", "m1_force",
             "m1_solve_steady", "m1_residual", "m1_get_state", "m1_set_state", "m1_get_state_region", "m1_get_info",
-            "m1_active_bins", "m1_dynamic_c_tilde", "m1_band_workspace_bytes", "m1_band_init",
+            "m1_active_bins", "m1_set_c_tilde", "m1_dynamic_c_tilde", "m1_band_workspace_bytes", "m1_band_init",
             "m1_batch_workspace_bytes", "m1_batch_init", "m1_batch_step", "m1_batch_info",
             "m1_batch_free", "m1_batch_set_tile", "m1_batch_workspace_bound",
             "m1_server_create", "m1_server_submit", "m1_server_run", "m1_server_poll",
@@ -332,6 +333,14 @@ class M1Grid:
         torch.cuda.current_stream().synchronize()     # inputs written on torch's stream
         check(lib().m1_set_state(self.h, *[t.data_ptr() for t in self._set]))
         self.sync()
+
+    def set_c_tilde(self, c_tilde):
+        """New reduced speed of light, state kept (m1_set_c_tilde); updates dt."""
+        check(lib().m1_set_c_tilde(self.h, float(c_tilde)))
+        dt = ctypes.c_double()
+        check(lib().m1_get_info(self.h, ctypes.byref(dt), None, None, None, None))
+        self.dt = dt.value
+        self.cfg.c_tilde = float(c_tilde)
 
     def active_bins(self):
         """Flags (int32 [N_nu]) of the bins the last step advected."""

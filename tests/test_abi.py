@@ -292,3 +292,8 @@ def test_frequency_grid_matches_oracle(q, hw, T_min):
     np.testing.assert_allclose(dnu, g["dnu"], rtol=1e-12)
     c.q = 0.9
     assert m1.lib().m1_frequency_grid(ctypes.byref(c), None, None) == m1.M1_EINVAL
+
+
+def test_set_c_tilde_argument_checks_without_device_work():
+    L = m1.lib()
+    assert L.m1_set_c_tilde(None, 1.0e9) == m1.M1_EINVAL

@@ -175,3 +175,26 @@ def test_band_init_from_device_fields_matches_host_fields():
     assert np.array_equal(E.cpu().numpy(), E0)
     m1.lib().m1_free(h)
     ref.free()
+
+
+def test_band_set_c_tilde_midway_matches_oracle():
+    from paper_2606_02711_amd import m1
+    print("[gpu band] set_c_tilde midway", flush=True)
+    p = inputs.band_random_small("cyl", 41, 26, 12, n_band=4)
+    g = m1.BandGrid(p, prec="fp64")
+    o = M.BandOracle(p)
+    g.step(3)
+    o.step(3)
+    c2 = 0.25 * p["c_tilde"]
+    g.set_c_tilde(c2)
+    dt2 = M.rt_time_step(dict(p, c_tilde=c2))
+    assert g.dt == pytest.approx(dt2, rel=1e-14)
+    o.dt = dt2
+    o.P.c_tilde, o.P.dt = c2, dt2
+    g.step(3)
+    o.step(3)
+    E, Fx, Fy = [t.double().cpu().numpy() for t in g.state()]
+    f = g.force().cpu().numpy()
+    for a, b in ((E, o.E), (Fx, o.Fx), (Fy, o.Fy), (f, o.force)):
+        assert rel(a, b) <= 1e-12
+    g.free()

@@ -38,3 +38,69 @@ def test_dynamic_c_tilde_reports_a_bad_temperature():
     print("[gpu] dynamic c_tilde with T = 0 in a cell", flush=True)
     with pytest.raises(m1.M1Error):
         m1.dynamic_c_tilde(p, np.full((9, 12), 1.0e5))
+
+
+def _rel(a, b):
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(a - b)) / nb if nb > 0 else float(np.linalg.norm(a))
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_set_c_tilde_midway_matches_oracle(prec, tol):
+    """m1_set_c_tilde between steps: the grid continues from its state with
+    the CFL step and geometry factors of the new c_tilde, as the oracle does
+    when its c_tilde and dt are changed between steps."""
+    from paper_2606_02711_amd import m1
+    print(f"[gpu] set_c_tilde midway {prec}", flush=True)
+    p = inputs.random_small("cyl", 45, 30, 7, half_width=1e3, log_nHI=(-4.0, 1.0))
+    g = m1.M1Grid(p, prec=prec)
+    o = M.Oracle(p)
+    g.step(4)
+    o.step(4)
+    c2 = 0.3 * p["c_tilde"]
+    g.set_c_tilde(c2)
+    dt2 = M.rt_time_step(dict(p, c_tilde=c2))
+    assert g.dt == pytest.approx(dt2, rel=1e-14)
+    o.s.dt = dt2
+    o.P.c_tilde, o.P.dt = c2, dt2
+    g.step(4)
+    o.step(4)
+    E, Fx, Fy = [t.double().cpu().numpy() for t in g.state()]
+    f = g.force().cpu().numpy()
+    errs = dict(E=_rel(E, o.E), Fx=_rel(Fx, o.Fx), Fy=_rel(Fy, o.Fy), force=_rel(f, o.force))
+    print("   rel-L2", errs, flush=True)
+    assert max(errs["E"], errs["Fx"], errs["Fy"]) <= tol
+    assert errs["force"] <= (tol if prec == "fp64" else 1e-4)
+    g.free()
+
+
+def test_batch_picks_up_set_c_tilde():
+    """A batch member whose c_tilde changes between batch steps: the batch
+    uploads its new arguments, and every member still equals itself stepped
+    alone through the same changes, bitwise."""
+    import torch
+    from paper_2606_02711_amd import m1
+    print("[gpu] batch with set_c_tilde", flush=True)
+    ps = [inputs.random_small(g, n, n + 5, s, half_width=1e3)
+          for g, n, s in (("cart", 20, 11), ("cyl", 37, 12), ("cart", 50, 13))]
+    ref = []
+    for p in ps:
+        a = m1.M1Grid(p, prec="fp32")
+        a.step(17)
+        if p is ps[1]:
+            a.set_c_tilde(0.5 * p["c_tilde"])
+        a.step(6)
+        ref.append([t.clone() for t in a.state()] + [a.force().clone()])
+        a.free()
+    s = torch.cuda.Stream()
+    gs = [m1.M1Grid(p, prec="fp32", stream=s) for p in ps]
+    b = m1.M1Batch(gs, use_graph=True)
+    b.step(17)
+    gs[1].set_c_tilde(0.5 * ps[1]["c_tilde"])
+    b.step(6)
+    for g, r in zip(gs, ref):
+        for x, y in zip(list(g.state()) + [g.force()], r):
+            assert torch.equal(x, y)
+    b.free()
+    for g in gs:
+        g.free()
