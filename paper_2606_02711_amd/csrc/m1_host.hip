@@ -1041,11 +1041,12 @@ struct m1_batch {
   int prec = 0;
   hipStream_t stream = nullptr;
   char* ws = nullptr;
-  size_t args_off = 0, par_off = 0, offa_off = 0, offf_off = 0;
+  size_t args_off = 0, par_off = 0, offa_off = 0, offf_off = 0, offr_off = 0;
   std::vector<int> par;                 // base parity per grid
   int sp = 0;                           // steps taken mod 2
   int blocks_adv[kNumBatchVariants] = {};
   int blocks_freq = 0;
+  int blocks_rates = 0;                 // rates items of the two-launch frequency step
   int islands = 0;                      // some member may have island cells
   int active = 0;                       // some member selects active bins
   bool fused_ok = false;                // the fused variant applies (float, no islands)
@@ -1062,7 +1063,7 @@ namespace {
 constexpr int kTrialSteps = 2;          // timed steps per variant while tuning
 
 size_t batch_layout(m1_handle* const* hs, int n, size_t* args_off, size_t* par_off,
-                    size_t* offa_off, size_t* offf_off) {
+                    size_t* offa_off, size_t* offf_off, size_t* offr_off) {
   size_t rs = hs[0]->cfg.prec == M1_FP32 ? sizeof(GridArgs<float>) : sizeof(GridArgs<double>);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
@@ -1070,6 +1071,7 @@ size_t batch_layout(m1_handle* const* hs, int n, size_t* args_off, size_t* par_o
   *par_off = take((size_t)n * sizeof(int));
   *offa_off = take((size_t)kNumBatchVariants * (n + 1) * sizeof(int));
   *offf_off = take((size_t)(n + 1) * sizeof(int));
+  *offr_off = take((size_t)(n + 1) * sizeof(int));
   return off;
 }
 
@@ -1133,6 +1135,7 @@ hipError_t batch_launch_step(m1_batch* b, int variant) {
   const int* par = (const int*)(b->ws + b->par_off);
   const int* offa = (const int*)(b->ws + b->offa_off) + (size_t)variant * (b->n + 1);
   const int* offf = (const int*)(b->ws + b->offf_off);
+  const int* offr = (const int*)(b->ws + b->offr_off);
   hipError_t e = hipSuccess;
   for (int q = 0; q < b->n && e == hipSuccess; ++q)
     e = launch_selection(b->hs[q], (b->par[q] ^ b->sp) & 1, b->stream);
@@ -1140,7 +1143,8 @@ hipError_t batch_launch_step(m1_batch* b, int variant) {
     e = launch_advect_batched<R>(variant, args, par, b->n, b->sp, offa, b->blocks_adv[variant],
                                  b->active, b->stream);
   if (e != hipSuccess || variant == kFusedVariant) return e;   // fused: no separate freq kernel
-  return launch_freq_batched<R>(args, par, b->n, b->sp, offf, b->blocks_freq, b->islands,
+  return launch_freq_batched<R>(args, par, b->n, b->sp, offf, b->blocks_freq, b->islands, offr,
+                                b->blocks_rates,
                                 b->stream);
 }
 
@@ -1161,7 +1165,8 @@ int32_t m1_batch_workspace_bytes(m1_handle* const* hs, int32_t n, size_t* bytes)
   int st = check_members(hs, n);
   if (st) return st;
   size_t a, p, oa, of;
-  *bytes = batch_layout(hs, n, &a, &p, &oa, &of);
+  size_t orr;
+  *bytes = batch_layout(hs, n, &a, &p, &oa, &of, &orr);
   return M1_OK;
 }
 
@@ -1178,14 +1183,15 @@ int32_t m1_batch_init(m1_handle* const* hs, int32_t n, void* d_ws, size_t ws_byt
   b->prec = hs[0]->cfg.prec;
   b->stream = hs[0]->stream;
   b->ws = (char*)d_ws;
-  size_t need = batch_layout(hs, n, &b->args_off, &b->par_off, &b->offa_off, &b->offf_off);
+  size_t need = batch_layout(hs, n, &b->args_off, &b->par_off, &b->offa_off, &b->offf_off,
+                             &b->offr_off);
   if (ws_bytes < need) { delete b; return fail(M1_ENOMEM, "batch workspace %zu < %zu", ws_bytes, need); }
   b->use_graph = use_graph != 0 && b->stream != nullptr;
   for (int q = 0; q < n; ++q)
     if (hs[q]->cfg.prec == M1_FP32 && hs[q]->cfg.fp64_tau < INFINITY) b->islands = 1;
   b->fused_ok = b->prec == M1_FP32 && !b->islands;
   // work lists: prefix sums of work items per grid, per tile variant
-  std::vector<int> offa((size_t)kNumBatchVariants * (n + 1)), offf(n + 1, 0);
+  std::vector<int> offa((size_t)kNumBatchVariants * (n + 1)), offf(n + 1, 0), offr(n + 1, 0);
   int64_t tot[kNumBatchVariants] = {};
   for (int v = 0; v < kNumBatchVariants; ++v) {
     offa[(size_t)v * (n + 1)] = 0;
@@ -1195,10 +1201,13 @@ int32_t m1_batch_init(m1_handle* const* hs, int32_t n, void* d_ws, size_t ws_byt
       offa[(size_t)v * (n + 1) + q + 1] = (int)tot[v];
     }
   }
-  int64_t totf = 0;
+  int64_t totf = 0, totr = 0;
   for (int q = 0; q < n; ++q) {
     totf += freq_blocks(hs[q]->cfg.nx, hs[q]->cfg.ny);
     offf[q + 1] = (int)totf;
+    totr += ((int64_t)(hs[q]->nb - 1) * (int64_t)hs[q]->nc + 255) / 256;
+    if (totr > INT32_MAX / 2) { delete b; return fail(M1_EUNSUPPORTED, "batch too large"); }
+    offr[q + 1] = (int)totr;
   }
   for (int q = 0; q < n; ++q)
     if (hs[q]->cfg.active_frac > 0.0) b->active = 1;
@@ -1206,11 +1215,15 @@ int32_t m1_batch_init(m1_handle* const* hs, int32_t n, void* d_ws, size_t ws_byt
   constexpr int64_t kMaxBlocks = int64_t(1) << 30;
   for (int v = 0; v < kNumBatchVariants; ++v) b->blocks_adv[v] = (int)std::min(tot[v], kMaxBlocks);
   b->blocks_freq = (int)std::min(totf, kMaxBlocks);
+  b->blocks_rates = (int)std::min(totr, kMaxBlocks);
   b->par.resize(n);
   for (int q = 0; q < n; ++q) b->par[q] = hs[q]->cur;
   b->sp = 0;
   hipError_t e = hipMemcpyAsync(b->ws + b->offa_off, offa.data(), offa.size() * sizeof(int),
                                 hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->ws + b->offr_off, offr.data(), offr.size() * sizeof(int),
+                       hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(b->ws + b->offf_off, offf.data(), offf.size() * sizeof(int),
                        hipMemcpyHostToDevice, b->stream);
@@ -1331,7 +1344,7 @@ int32_t m1_batch_workspace_bound(int32_t n, int32_t prec, size_t* bytes) {
   size_t rs = prec == M1_FP32 ? sizeof(GridArgs<float>) : sizeof(GridArgs<double>);
   *bytes = align_up(2 * (size_t)n * rs) + align_up((size_t)n * sizeof(int)) +
            align_up((size_t)kNumBatchVariants * (n + 1) * sizeof(int)) +
-           align_up((size_t)(n + 1) * sizeof(int));
+           2 * align_up((size_t)(n + 1) * sizeof(int));
   return M1_OK;
 }
 

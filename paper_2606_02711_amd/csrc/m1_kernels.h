@@ -33,9 +33,12 @@ int freq_blocks(int nx, int ny);
 template <typename R>
 hipError_t launch_advect_batched(int variant, const GridArgs<R>* args, const int* par, int n,
                                  int sp, const int* off, int nblocks, int active, hipStream_t s);
+// off/nblocks: 256-cell work items; offr/nrates: 256-interface work items of
+// the two-launch step a batch of few cells takes.
 template <typename R>
 hipError_t launch_freq_batched(const GridArgs<R>* args, const int* par, int n, int sp,
-                               const int* off, int nblocks, int islands, hipStream_t s);
+                               const int* off, int nblocks, int islands, const int* offr,
+                               int nrates, hipStream_t s);
 
 // Active bins of a state E [nb][ny][nx]: per-bin energies with cell volumes
 // wx[i] wy[j] into part [nb][energy_chunks], then flags active[k].

@@ -776,12 +776,11 @@ __device__ __forceinline__ void freq_backward(const GridArgs<R>& a, size_t c, si
 // d_k = y_k + a_{k-1} d_{k-1}/p_{k-1}, back substitution
 // y_k = d_k/p_k + (b_{k+1}/p_k) y_{k+1}.  No subtraction, so the relative
 // error stays O(N_nu eps) however stiff the cell is.
+// Per-cell constants of the frequency step of cell c of class cl.
 template <typename R, typename T>
-__device__ void freq_cell(const GridArgs<R>& a, size_t c) {
-  const size_t nc = (size_t)a.nx * a.ny;
-  const int cl = a.cls[c];
+__device__ __forceinline__ FreqCell<R, T> freq_cell_consts(const GridArgs<R>& a, size_t c,
+                                                           size_t nc, int cl, T al) {
   FreqCell<R, T> fc;
-  const T al = (T)a.alpha[c];
   fc.gxx = (T)a.grad[c];
   fc.gyy = (T)a.grad[nc + c];
   fc.gxy = (T)a.grad[2 * nc + c];
@@ -791,6 +790,15 @@ __device__ void freq_cell(const GridArgs<R>& a, size_t c) {
   fc.recoil = a.recoil != 0;
   fc.doppler = a.doppler != 0 &&
       ((fc.gxx != T(0)) || (fc.gyy != T(0)) || (fc.gxy != T(0)) || (fc.gpp != T(0)));
+  return fc;
+}
+
+template <typename R, typename T>
+__device__ void freq_cell(const GridArgs<R>& a, size_t c) {
+  const size_t nc = (size_t)a.nx * a.ny;
+  const int cl = a.cls[c];
+  const T al = (T)a.alpha[c];
+  const FreqCell<R, T> fc = freq_cell_consts<R, T>(a, c, nc, cl, al);
   double f4[4];
   freq_forward<R, T>(a, fc, c, nc, a.Eo, a.fxo, a.fyo, a.hbar + (size_t)cl * a.nb, a.zw,
                      al, (double)a.acF[c], f4);
@@ -826,6 +834,130 @@ void k_freq(GridArgs<R> a) {
   const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= (size_t)a.nx * a.ny) return;
   freq_dispatch<R, P>(a, c);
+}
+
+// ------------------------------------------- K3 for small grids
+// A grid of few cells leaves most of the GPU idle in k_freq, and each lane's
+// sweep over the bins is bound by the latency of its ~150 dependent
+// instructions per bin, mostly the exponential-scheme coefficients.  Small
+// grids therefore take the step in two launches with the same arithmetic:
+// k_freq_rates gives every (cell, interface k+1/2) a lane for the rates
+// gl, gr of Appendix A (stored in the elimination scratch slot k), then
+// k_freq_solve runs the light sequential part per cell (elimination in
+// double, force sum, back substitution), with its loads kSolveAhead bins
+// ahead.  Non-island cells (island cells of a float grid keep k_freq<R, 1>).
+// The rates launch evaluates every bin's coefficients twice at full-chip
+// cost, so its time grows with the cell count while k_freq's latency-bound
+// time does not, below a round of blocks.  Measured (uniform clouds, 194
+// bins, one grid): float 64^2 259 -> 118 us, 128^2 295 -> 174 us, 256^2
+// 307 -> 284 us, but a batch of 8 x 128^2 loses (0.64 -> 0.74 ms per step);
+// double 128^2 353 -> 233 us, 256^2 383 -> 442 us.  Hence the cut-overs
+// below (cells of the launch).
+constexpr int kSolveAhead = 4;
+template <typename R>
+constexpr size_t kTwoPhaseCells = sizeof(R) == 4 ? size_t(1) << 16 : size_t(1) << 15;
+
+// Rates of interface k+1/2 of cell c for t = k ncell + c < (N_nu - 1) ncell.
+template <typename R>
+__device__ __forceinline__ void freq_rates_at(const GridArgs<R>& a, size_t t) {
+  using T = R;                      // float grids: float coefficients (non-island cells)
+  const size_t nc = (size_t)a.nx * a.ny;
+  const int k = (int)(t / nc);
+  const size_t c = t - (size_t)k * nc;
+  if (sizeof(R) == 4 && a.island[c]) return;
+  const int cl = a.cls[c];
+  const T al = (T)a.alpha[c];
+  const FreqCell<R, T> fc = freq_cell_consts<R, T>(a, c, nc, cl, al);
+  const R* hb = a.hbar + (size_t)cl * a.nb;
+  T q0, C0, q1, C1;
+  fc.coeffs(a, k, hb[k], a.fxo[t], a.fyo[t], q0, C0);
+  fc.coeffs(a, k + 1, hb[k + 1], a.fxo[t + nc], a.fyo[t + nc], q1, C1);
+  T gl, gr;
+  if (q0 > T(0) && q1 > T(0)) {
+    interface_rates<T>(q0, C0, q1, C1, gl, gr);
+  } else {
+    gl = C0 < T(0) ? -C0 : T(0);       // K -> 0: first-order upwind
+    gr = C1 > T(0) ? C1 : T(0);
+  }
+  ZW<R> v;
+  v.z = gl;
+  v.w = gr;
+  a.zw[t] = v;
+}
+
+// Elimination, force and back substitution of cell c after freq_rates_at.
+template <typename R>
+__device__ __forceinline__ void freq_solve_cell(const GridArgs<R>& a, size_t c) {
+  using T = R;
+  const size_t nc = (size_t)a.nx * a.ny;
+  if (sizeof(R) == 4 && a.island[c]) return;
+  const int nb = a.nb;
+  const int cl = a.cls[c];
+  const T al = (T)a.alpha[c];
+  const double acF = (double)a.acF[c];
+  const R* hb = a.hbar + (size_t)cl * nb;
+  const double ctdt = (double)a.ctdt;
+  double fx = 0.0, fy = 0.0, gx = 0.0, gy = 0.0;
+  // ring: slot j holds bin k + j (state, profile, rates of interface k+j+1/2)
+  R re[kSolveAhead], rx[kSolveAhead], ry[kSolveAhead], rh[kSolveAhead];
+  ZW<R> rr[kSolveAhead];
+  auto load = [&](int kb, R& e, R& x, R& y, R& h, ZW<R>& r) {
+    e = x = y = h = R(0);
+    r.z = r.w = R(0);
+    if (kb < nb) {
+      const size_t i = (size_t)kb * nc + c;
+      e = a.Eo[i]; x = a.fxo[i]; y = a.fyo[i]; h = hb[kb];
+      if (kb + 1 < nb) r = a.zw[i];
+    }
+  };
+#pragma unroll
+  for (int j = 0; j < kSolveAhead; ++j) load(j, re[j], rx[j], ry[j], rh[j], rr[j]);
+  FreqRow row;
+  for (int k = 0; k < nb; ++k) {
+    const R e = re[0], x = rx[0], y = ry[0], h = rh[0];
+    const ZW<R> r = rr[0];
+#pragma unroll
+    for (int j = 0; j + 1 < kSolveAhead; ++j) {
+      re[j] = re[j + 1]; rx[j] = rx[j + 1]; ry[j] = ry[j + 1]; rh[j] = rh[j + 1];
+      rr[j] = rr[j + 1];
+    }
+    load(k + kSolveAhead, re[kSolveAhead - 1], rx[kSolveAhead - 1], ry[kSolveAhead - 1],
+         rh[kSolveAhead - 1], rr[kSolveAhead - 1]);
+    {
+      // force density, in bin order as in freq_forward
+      const double dn = a.dnu[k];
+      const double aH = (double)al * (double)h;
+      const double aF = aH + acF;
+      const double X = (double)x * (double)e, Y = (double)y * (double)e;
+      fx += dn * aF * X;
+      fy += dn * aF * Y;
+      gx += dn * aH * X;
+      gy += dn * aH * Y;
+    }
+    double a_k = 0.0, b_next = 0.0;
+    if (k + 1 < nb) {
+      a_k = ctdt * (double)r.z * a.inv_dnu[k];
+      b_next = ctdt * (double)r.w * a.inv_dnu[k + 1];
+    }
+    row.eliminate<R>(k, a.dnu[k] * (double)e, a_k, b_next, &a.zw[(size_t)k * nc + c]);
+  }
+  freq_backward<R>(a, c, nc, a.Eo, a.zw);
+  a.force[c] = fx;
+  a.force[nc + c] = fy;
+  a.force[2 * nc + c] = gx;
+  a.force[3 * nc + c] = gy;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_freq_rates(GridArgs<R> a) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < (size_t)(a.nb - 1) * a.nx * a.ny) freq_rates_at<R>(a, t);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_freq_solve(GridArgs<R> a) {
+  const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < (size_t)a.nx * a.ny) freq_solve_cell<R>(a, c);
 }
 
 // ------------------------------------------- K3 with the substep rule
@@ -1032,6 +1164,44 @@ void k_freq_batched(const GridArgs<R>* __restrict__ args,
     const GridArgs<R> a = global_args(args[((par[lo] ^ sp) & 1) * n + lo]);
     const size_t c = (size_t)(w - off[lo]) * 256 + threadIdx.x;
     if (c < (size_t)a.nx * a.ny) freq_dispatch<R, P>(a, c);
+  }
+}
+
+// The two launches of the small-grid frequency step for a batch: work item
+// = 256 interfaces (rates; off = offr) or 256 cells (solve; off = offf).
+template <typename R>
+__device__ __forceinline__ int batch_member(const int* __restrict__ off, int n, int w) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= w) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_freq_rates_batched(const GridArgs<R>* __restrict__ args,
+                                                            const int* __restrict__ par, int n,
+                                                            int sp, const int* __restrict__ off) {
+  const int total = off[n];
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int g = batch_member<R>(off, n, w);
+    const GridArgs<R> a = global_args(args[((par[g] ^ sp) & 1) * n + g]);
+    const size_t t = (size_t)(w - off[g]) * 256 + threadIdx.x;
+    if (t < (size_t)(a.nb - 1) * a.nx * a.ny) freq_rates_at<R>(a, t);
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_freq_solve_batched(const GridArgs<R>* __restrict__ args,
+                                                            const int* __restrict__ par, int n,
+                                                            int sp, const int* __restrict__ off) {
+  const int total = off[n];
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int g = batch_member<R>(off, n, w);
+    const GridArgs<R> a = global_args(args[((par[g] ^ sp) & 1) * n + g]);
+    const size_t c = (size_t)(w - off[g]) * 256 + threadIdx.x;
+    if (c < (size_t)a.nx * a.ny) freq_solve_cell<R>(a, c);
   }
 }
 
@@ -1248,11 +1418,27 @@ __global__ void k_force_out(const double* __restrict__ force, size_t nc, int e2,
 // ------------------------------------------------------------ launchers
 constexpr int kBK = 28;   // bins per advection block (7 runs for 194 bins)
 
+// Bin runs of the plain advection of one grid: 28 bins per block, or, on
+// grids whose 28-bin launch is under two rounds of blocks (1024 slots at
+// four waves per SIMD), 14 bins if that gives four rounds, else 7: at 64^2
+// the kernel takes 30 instead of 92 us.  The bits do not depend on the run
+// length.
+constexpr unsigned kRoundsBlocks = 4096;
+constexpr unsigned kFewBlocks = 2048;
+
 template <typename R>
 hipError_t launch_advect(const GridArgs<R>& a, hipStream_t s) {
   const unsigned nbx = (a.nx + kTX - 1) / kTX, nby = (a.ny + kTY - 1) / kTY;
   const unsigned nbz = (a.nb + kBK - 1) / kBK;
   const dim3 g(nbx * nby * nbz), b(256);
+  if (!a.substeps && !a.active && g.x < kFewBlocks) {
+    const unsigned n14 = nbx * nby * ((a.nb + 13) / 14), n7 = nbx * nby * ((a.nb + 6) / 7);
+    if (n14 >= kRoundsBlocks)
+      hipLaunchKernelGGL((k_advect_source<R, 14, false, false>), dim3(n14), b, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_advect_source<R, 7, false, false>), dim3(n7), b, 0, s, a);
+    return hipGetLastError();
+  }
   if (a.substeps) {
     if (a.active) hipLaunchKernelGGL((k_advect_source<R, kBK, true, true>), g, b, 0, s, a);
     else          hipLaunchKernelGGL((k_advect_source<R, kBK, false, true>), g, b, 0, s, a);
@@ -1279,7 +1465,13 @@ hipError_t launch_freq(const GridArgs<R>& a, hipStream_t s) {
     if (sizeof(R) == 4 && a.islands) hipLaunchKernelGGL((k_freq_sub<R, 1>), g, dim3(256), 0, s, a);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL((k_freq<R, 0>), g, dim3(256), 0, s, a);
+  if (nc < kTwoPhaseCells<R> && a.nb > 1) {
+    const size_t nt = (size_t)(a.nb - 1) * nc;
+    hipLaunchKernelGGL((k_freq_rates<R>), dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_freq_solve<R>), g, dim3(256), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_freq<R, 0>), g, dim3(256), 0, s, a);
+  }
   if (sizeof(R) == 4 && a.islands) hipLaunchKernelGGL((k_freq<R, 1>), g, dim3(256), 0, s, a);
   return hipGetLastError();
 }
@@ -1408,7 +1600,19 @@ hipError_t launch_advect_batched(int variant, const GridArgs<R>* args, const int
 
 template <typename R>
 hipError_t launch_freq_batched(const GridArgs<R>* args, const int* par, int n, int sp,
-                               const int* off, int nblocks, int islands, hipStream_t s) {
+                               const int* off, int nblocks, int islands, const int* offr,
+                               int nrates, hipStream_t s) {
+  if ((size_t)nblocks * 256 < kTwoPhaseCells<R>) {     // a batch of few cells
+    if (nrates > 0)
+      hipLaunchKernelGGL((k_freq_rates_batched<R>), dim3(nrates), dim3(256), 0, s, args, par, n,
+                         sp, offr);
+    hipLaunchKernelGGL((k_freq_solve_batched<R>), dim3(nblocks), dim3(256), 0, s, args, par, n,
+                       sp, off);
+    if (sizeof(R) == 4 && islands)
+      hipLaunchKernelGGL((k_freq_batched<R, 1>), dim3(nblocks), dim3(256), 0, s, args, par, n, sp,
+                         off);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL((k_freq_batched<R, 0>), dim3(nblocks), dim3(256), 0, s, args, par, n, sp, off);
   if (sizeof(R) == 4 && islands)
     hipLaunchKernelGGL((k_freq_batched<R, 1>), dim3(nblocks), dim3(256), 0, s, args, par, n, sp, off);
@@ -1470,8 +1674,8 @@ template hipError_t launch_step<float>(const GridArgs<float>&, hipStream_t);
 template hipError_t launch_step<double>(const GridArgs<double>&, hipStream_t);
 template hipError_t launch_advect_batched<float>(int, const GridArgs<float>*, const int*, int, int, const int*, int, int, hipStream_t);
 template hipError_t launch_advect_batched<double>(int, const GridArgs<double>*, const int*, int, int, const int*, int, int, hipStream_t);
-template hipError_t launch_freq_batched<float>(const GridArgs<float>*, const int*, int, int, const int*, int, int, hipStream_t);
-template hipError_t launch_freq_batched<double>(const GridArgs<double>*, const int*, int, int, const int*, int, int, hipStream_t);
+template hipError_t launch_freq_batched<float>(const GridArgs<float>*, const int*, int, int, const int*, int, int, const int*, int, hipStream_t);
+template hipError_t launch_freq_batched<double>(const GridArgs<double>*, const int*, int, int, const int*, int, int, const int*, int, hipStream_t);
 template hipError_t launch_band_step<float>(const GridArgs<float>&, hipStream_t);
 template hipError_t launch_band_step<double>(const GridArgs<double>&, hipStream_t);
 template hipError_t launch_advect<float>(const GridArgs<float>&, hipStream_t);
