@@ -201,6 +201,12 @@ int32_t m1_solve_steady(m1_handle *h, double rel_tol, int64_t max_steps,
 /* Residual r of the last step (as in m1_solve_steady).  Blocking. */
 int32_t m1_residual(m1_handle *h, double *resid);
 
+/* m1_residual of n handles into resid[0..n-1] (host array), with every
+ * reduction enqueued before the first wait: one synchronisation for handles
+ * that share a stream (a serving round's residents).  Same values as n calls
+ * of m1_residual.  Blocking.  M1_EINVAL for NULL arguments or n < 1. */
+int32_t m1_residuals(m1_handle *const *hs, int32_t n, double *resid);
+
 /* Copy the state out of / into caller device arrays of doubles
  * [N_nu][ny][nx] in physical units (E, F per Hz).  Internally the state is
  * E (scaled by 2^scale_exp2 in the FP32 path, see m1_get_info, so values far

@@ -1385,6 +1385,48 @@ int32_t m1_residual(m1_handle* h, double* resid) {
   return M1_OK;
 }
 
+int32_t m1_residuals(m1_handle* const* hs, int32_t n, double* resid) {
+  if (!hs || n < 1 || !resid) return fail(M1_EINVAL, "bad arguments");
+  for (int q = 0; q < n; ++q)
+    if (!hs[q]) return fail(M1_EINVAL, "handle %d is NULL", q);
+  // every reduction first, then the copies (the first waits for them all on
+  // a shared stream), then one wait per handle
+  std::vector<double> r2(2 * (size_t)n, 0.0);
+  for (int q = 0; q < n; ++q) {
+    m1_handle* h = hs[q];
+    if (h->steps == 0) continue;
+    const size_t cnt = (size_t)h->nb * h->nc;
+    const int nblk = (int)std::min<size_t>((cnt + 255) / 256, kResBlocks);
+    double* part = (double*)(h->ws + h->L.partial);
+    double* res = (double*)(h->ws + h->L.result);
+    const char* Eold = h->ws + h->L.state[h->cur ^ 1][0];
+    const char* Enew = h->ws + h->L.state[h->cur][0];
+    hipError_t e = h->cfg.prec == M1_FP32
+        ? launch_residual<float>((const float*)Eold, (const float*)Enew, cnt, part, nblk, res, h->stream)
+        : launch_residual<double>((const double*)Eold, (const double*)Enew, cnt, part, nblk, res, h->stream);
+    if (e != hipSuccess) return fail(M1_EDEVICE, "residual launch: %s", hipGetErrorString(e));
+  }
+  for (int q = 0; q < n; ++q) {
+    m1_handle* h = hs[q];
+    if (h->steps == 0) continue;
+    HIPCHK(hipMemcpyAsync(&r2[2 * (size_t)q], h->ws + h->L.result, 2 * sizeof(double),
+                          hipMemcpyDeviceToHost, h->stream));
+  }
+  for (int q = 0; q < n; ++q) {
+    hipError_t e = hipStreamSynchronize(hs[q]->stream);
+    if (e != hipSuccess) {
+      hs[q]->broken = true;
+      return fail(M1_EDEVICE, "stream error: %s", hipGetErrorString(e));
+    }
+  }
+  for (int q = 0; q < n; ++q) {
+    const double num = r2[2 * (size_t)q], den = r2[2 * (size_t)q + 1];
+    resid[q] = hs[q]->steps == 0 ? INFINITY
+                                 : (den > 0 ? sqrt(num / den) : (num == 0 ? 0.0 : INFINITY));
+  }
+  return M1_OK;
+}
+
 int32_t m1_solve_steady(m1_handle* h, double rel_tol, int64_t max_steps, int32_t check_every,
                         int64_t* steps_done, double* resid) {
   if (!h) return fail(M1_EINVAL, "handle is NULL");

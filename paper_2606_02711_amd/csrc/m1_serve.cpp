@@ -1,5 +1,5 @@
 // Continuous-batching engine for steady-state solves, built on the public
-// C ABI (m1_init, m1_step, m1_residual, m1_batch_*).
+// C ABI (m1_init, m1_step, m1_residual, m1_residuals, m1_batch_*).
 //
 // Device memory: one caller-owned arena.  The front of it holds the batch
 // descriptor tables for max_resident grids; the rest is handed out first-fit
@@ -255,9 +255,16 @@ int advance(m1_server* s) {
 
 void check_residuals(m1_server* s) {
   std::vector<Request*> still;
+  // every resident's residual with one wait; on an error, one by one, so
+  // that the request that failed is the one marked
+  std::vector<m1_handle*> hs;
+  for (Request* r : s->resident) hs.push_back(r->h);
+  std::vector<double> all(hs.size(), INFINITY);
+  const bool together = !hs.empty() && m1_residuals(hs.data(), (int32_t)hs.size(), all.data()) == M1_OK;
+  size_t q = 0;
   for (Request* r : s->resident) {
-    double res = INFINITY;
-    int st = m1_residual(r->h, &res);
+    double res = all[q++];
+    int st = together ? M1_OK : m1_residual(r->h, &res);
     r->resid = res;
     if (st != M1_OK) finish(s, r, M1_REQ_FAILED, st);
     else if (res < r->tol) finish(s, r, M1_REQ_CONVERGED, M1_OK);

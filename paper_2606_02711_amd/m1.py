@@ -95,6 +95,7 @@ def lib():
         "m1_force": (I32, [VP, VP, VP, VP, VP]),
         "m1_solve_steady": (I32, [VP, D, I64, I32, P(I64), P(D)]),
         "m1_residual": (I32, [VP, P(D)]),
+        "m1_residuals": (I32, [P(VP), I32, VP]),
         "m1_get_state": (I32, [VP, VP, VP, VP]),
         "m1_set_state": (I32, [VP, VP, VP, VP]),
         "m1_get_state_region": (I32, [VP, I32, I32, I32, I32, VP, VP, VP]),
@@ -138,7 +139,7 @@ def lib():
 def exported_symbols():
     return ["m1_default_config", "m1_num_bins", "m1_frequency_grid", "m1_workspace_bytes",
             "m1_count_temperature_classes", "m1_init", "m1_step", "m1_force",
-            "m1_solve_steady", "m1_residual", "m1_get_state", "m1_set_state", "m1_get_state_region", "m1_get_info",
+            "m1_solve_steady", "m1_residual", "m1_residuals", "m1_get_state", "m1_set_state", "m1_get_state_region", "m1_get_info",
             "m1_active_bins", "m1_set_c_tilde", "m1_dynamic_c_tilde", "m1_band_workspace_bytes", "m1_band_init",
             "m1_batch_workspace_bytes", "m1_batch_init", "m1_batch_step", "m1_batch_info",
             "m1_batch_free", "m1_batch_set_tile", "m1_batch_workspace_bound",

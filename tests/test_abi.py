@@ -297,3 +297,12 @@ def test_frequency_grid_matches_oracle(q, hw, T_min):
 def test_set_c_tilde_argument_checks_without_device_work():
     L = m1.lib()
     assert L.m1_set_c_tilde(None, 1.0e9) == m1.M1_EINVAL
+
+
+def test_residuals_argument_checks_without_device_work():
+    L = m1.lib()
+    out = (ctypes.c_double * 2)()
+    hs = (ctypes.c_void_p * 2)(None, None)
+    assert L.m1_residuals(None, 1, out) == m1.M1_EINVAL
+    assert L.m1_residuals(hs, 0, out) == m1.M1_EINVAL
+    assert L.m1_residuals(hs, 2, out) == m1.M1_EINVAL          # NULL handles

@@ -320,3 +320,26 @@ def test_batch_workload_full_size_equals_alone_bitwise():
     for g in gs:
         g.free()
     torch.cuda.empty_cache()
+
+
+def test_residuals_of_many_grids_equal_one_by_one():
+    """m1_residuals (one wait for all) gives m1_residual's values, including
+    +inf for a grid that has not stepped."""
+    import ctypes
+    import torch
+    from paper_2606_02711_amd import m1
+    print("[gpu] m1_residuals", flush=True)
+    s = torch.cuda.Stream()
+    ps = [inputs.random_small(g, n, n + 2, q, half_width=1e3)
+          for g, n, q in (("cart", 12, 21), ("cyl", 30, 22), ("cart", 45, 23))]
+    gs = [m1.M1Grid(p, prec=pr, stream=s) for p, pr in zip(ps, ("fp32", "fp64", "fp32"))]
+    gs[0].step(5)
+    gs[1].step(7)
+    hs = (ctypes.c_void_p * 3)(*[g.h.value for g in gs])
+    out = (ctypes.c_double * 3)()
+    m1.check(m1.lib().m1_residuals(hs, 3, out))
+    assert list(out)[:2] == [gs[0].residual(), gs[1].residual()]
+    assert out[2] == float("inf") and gs[2].residual() == float("inf")
+    assert 0 < out[0] < float("inf") and 0 < out[1] < float("inf")
+    for g in gs:
+        g.free()
