@@ -434,7 +434,7 @@ def main():
     achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
     traffic = measured_traffic(dom, "fp32")
     out = {
-        "metric": "M1 Lya cell-updates/s (FP32 batched vs FP64 plain), %HBM roofline, p99 solve latency",
+        "metric": "M1 Ly\u03b1 cell-updates/s (FP32 batched vs FP64 plain), %HBM roofline, p99 solve latency",
         "value": r32["rate"],
         "unit": "cell-bin updates/s",
         "n_gpus": 1,
