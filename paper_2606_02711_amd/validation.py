@@ -53,3 +53,36 @@ def run_cone(n=256, prec="fp32", t_max=None, log=None, checkpoints=4, problem=No
     g.free()
     return dict(n=n, prec=prec, steps=steps, dt=g.dt, seconds=wall, M_F=hist[-1][2],
                 M_F_radial=hist[-1][3], history=hist)
+
+
+def energy_budget(p, g):
+    """Steady-state energy budget of a grid g of problem p (Section 4, the
+    escape-fraction test), over the emitted luminosity: (absorbed, escaped
+    lower, escaped upper).  Absorbed: c alpha_abs int E dnu over the volume
+    (alpha_abs the continuum absorption coefficient; no destruction).
+    Escaped: the outflow through the vacuum faces x = x1 and y = y1 (the
+    other sides must be reflecting), bracketed from the boundary cells'
+    values: below by c F.n, above by the corrected GLF outflow with an empty
+    ghost and no opacity, c (F.n + E)/2, at the cell centre (where E exceeds
+    its face value).  An energy-conserving step has absorbed + escaped = 1
+    inside the bracket."""
+    nu, dnu = m1.frequency_grid(g.cfg)
+    E, Fx, Fy = [t.cpu().numpy() for t in g.state()]
+    Eint = np.tensordot(dnu, E, axes=(0, 0))
+    Fxi = np.tensordot(dnu, Fx, axes=(0, 0))
+    Fyi = np.tensordot(dnu, Fy, axes=(0, 0))
+    vol = inputs.cell_volumes(p)
+    L = float(np.sum(p["fields"]["emis"] * vol))
+    c = inputs.C_LIGHT
+    absorbed = c * float(np.sum(p["fields"]["alpha_abs"] * Eint * vol))
+    xe, ye = inputs.edges(p)
+    dz = np.diff(ye)
+    if p["geom"] == "cyl":
+        a_x = 2.0 * np.pi * xe[-1] * dz                      # outer cylinder, per row
+        a_y = np.pi * (xe[1:] ** 2 - xe[:-1] ** 2)           # top annuli, per column
+    else:
+        a_x = dz
+        a_y = np.diff(xe)
+    fn = float(np.sum(Fxi[:, -1] * a_x)) + float(np.sum(Fyi[-1, :] * a_y))
+    en = float(np.sum(Eint[:, -1] * a_x)) + float(np.sum(Eint[-1, :] * a_y))
+    return absorbed / L, c * fn / L, 0.5 * c * (fn + en) / L
