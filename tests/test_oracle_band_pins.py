@@ -176,3 +176,40 @@ def test_band_refuses_runtime_controls():
     o.P.substep_rule = 1
     with pytest.raises(ValueError):
         o.step(1)
+
+
+@pytest.mark.parametrize("geom,factor", [("cart", 8.0 / 3.0), ("cyl", 4.0)])
+def test_isotropic_field_in_hubble_flow_cools_adiabatically(geom, factor):
+    """Uniform isotropic radiation (F = 0) in a Hubble flow u = H r: the
+    energy advected out of a cell, c dt E div(u)/c, plus the radiation
+    pressure work, c dt (D : grad u / c) E with D = I/3, give one step's
+    change E -> E (1 - k H c dt / c), k = 2 + 2/3 in the slab (div u = 2H)
+    and 3 + 1 in (R, z) (div u = 3H, with the azimuthal u_R/R = H term) --
+    radiation's adiabatic cooling dE/dt = -(4/3) E div u.  Cells away from
+    the boundaries, no opacity or emission.  In (R, z) the face velocity,
+    the mean of the two cells' centroid velocities, differs from H R_face
+    by O((dR / R)^2), so there the factor approaches 4 outwards."""
+    dx, nx, ny = 1.0e16, 16, 16
+    p = band_problem(geom, nx, ny, dx, ("reflect", "vacuum", "vacuum", "vacuum") if geom == "cyl"
+                     else ("vacuum",) * 4, [0.0], [0.0], [0.0], c_frac=0.01)
+    xe, ye = inputs.edges(p)
+    H = 3.0e-10                                   # 1/s: |u| <= 5e7 cm/s here
+    xc = 0.5 * (xe[1:] + xe[:-1])
+    if geom == "cyl":
+        xc = (2.0 / 3.0) * (xe[1:] ** 3 - xe[:-1] ** 3) / (xe[1:] ** 2 - xe[:-1] ** 2)
+    yc = 0.5 * (ye[1:] + ye[:-1])
+    p["fields"]["u_x"] = np.broadcast_to(H * xc[None, :], (ny, nx)).copy()
+    p["fields"]["u_y"] = np.broadcast_to(H * yc[:, None], (ny, nx)).copy()
+    o = M.BandOracle(p)
+    E0 = 1.0e-9
+    o.set_state(np.full((1, ny, nx), E0), np.zeros((1, ny, nx)), np.zeros((1, ny, nx)))
+    o.step(1)
+    k1 = H * p["c_tilde"] * o.dt / C
+    assert k1 > 1e-6                               # the effect is resolved
+    fac = (1.0 - o.E[0][3:ny - 3, 3:nx - 3] / E0) / k1
+    if geom == "cart":
+        np.testing.assert_allclose(fac, factor, rtol=1e-9)
+    else:
+        err = np.abs(fac - factor)
+        assert err.max() <= 1e-3 * factor
+        assert np.all(np.diff(err[0]) < 0)          # converging outwards
