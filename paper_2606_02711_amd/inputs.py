@@ -494,5 +494,44 @@ def band_hii_region(nx=512, ny=1024, L_star=1.0e39, steps=1000):
     return p
 
 
+def filled_state(p, nb, E_peak, seed=0):
+    """A developed radiation field to start a run from (instead of E = F = 0),
+    physical units: E [N_nu, ny, nx] and F_x, F_y, with
+
+      * a smooth spectrum in the bin index, a core over the central bins and
+        exponential wings, spanning ~7 decades over the grid;
+      * a smooth spatial envelope exp(-r / 0.3 L) (r from the centre of the
+        source plane: the axis mid-height in (R, z), the box centre in the
+        slab; L the box diagonal) with a gentle seeded modulation, spanning
+        about one more decade; the peak value is E_peak;
+      * a reduced flux whose magnitude grows with r and towards the wings,
+        |f| = min(1, (r / r_max) (0.4 + 1.2 |u_k|)), so it spans [0, 1] and is
+        exactly 1 over the outer far-wing cell-bins, pointing away from the
+        centre, turned by a bin-dependent angle.
+
+    Only an input recipe (no part of the transfer method)."""
+    rng = np.random.default_rng(np.random.SeedSequence([SEED_BASE, 77, seed]))
+    xc, yc = cell_centres(p)
+    if p["geom"] == "cyl":
+        cx, cy = p["x0"], 0.5 * (p["y0"] + p["y1"])
+    else:
+        cx, cy = 0.5 * (p["x0"] + p["x1"]), 0.5 * (p["y0"] + p["y1"])
+    L = math.hypot(p["x1"] - p["x0"], p["y1"] - p["y0"])
+    X, Y = xc[None, :] - cx, yc[:, None] - cy
+    r = np.hypot(X, Y)
+    ph = rng.uniform(0.0, 2.0 * math.pi, size=2)
+    env = np.exp(-r / (0.3 * L)) * (1.0 + 0.3 * np.sin(3.0 * X / L * 2.0 * math.pi + ph[0])
+                                    * np.cos(2.0 * Y / L * 2.0 * math.pi + ph[1]))
+    env *= 1.0 / float(env.max())
+    u = (np.arange(nb) - 0.5 * (nb - 1)) / max(0.5 * nb, 1.0)
+    spec = np.exp(-0.5 * (u / 0.08) ** 2) + 1.0e-3 * np.exp(-np.abs(u) / 0.1)
+    spec *= 1.0 / float(spec.max())
+    E = E_peak * spec[:, None, None] * env[None, :, :]
+    rmax = float(r.max())
+    fmag = np.minimum(1.0, (r[None, :, :] / rmax) * (0.4 + 1.2 * np.abs(u))[:, None, None])
+    ang = np.arctan2(Y, X)[None, :, :] + 0.6 * np.sin(5.0 * u)[:, None, None]
+    return E, E * fmag * np.cos(ang), E * fmag * np.sin(ang)
+
+
 def get_config(cid: int, **kw):
     return {1: config1, 2: config2, 5: config5}[cid](**kw)

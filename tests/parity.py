@@ -1,0 +1,128 @@
+"""Element-wise comparison of a GPU result with the FP64 oracle.
+
+Per result (E, F as a vector, the force as a vector) the checks are:
+  l2     relative L2 over all cells and bins, ||x - x_ref|| / ||x_ref||;
+  linf   normalised L-infinity, max |x - x_ref| / max |x_ref|;
+  bin    per-bin normalised L-infinity: for every bin k whose reference holds
+         more than 1e-30 of the largest value, max_cells |x_k - x_ref,k| /
+         max_cells |x_ref,k|, the worst over the bins (a far-wing bin is
+         judged against its own scale, not the line core's);
+  cell   per-cell relative error where E_ref > 1e-6 max E_ref:
+         |E - E_ref| / E_ref, and |F - F_ref| / E_ref for the flux (the error
+         of the reduced flux f = F/E, which stays meaningful where F ~ 0);
+         for the force, |f - f_ref| / |f_ref| where |f_ref| > 1e-6 max |f_ref|.
+The bounds per precision are stated in BOUNDS; a test may pass its own.
+Every comparison prints its figures (and appends them to the file named by
+the environment variable PARITY_LOG, if set).
+"""
+import json
+import os
+
+import numpy as np
+
+# Bounds per precision and check, about ten times the worst value measured
+# over the parity workloads (MI355X; 27 FP64 and 46 FP32 comparisons, the
+# full-size developed 512 x 1024 state included), never looser than the
+# stated targets: relative L2 1e-12 (FP64) and 1e-5 on E and F, 1e-4 on the
+# force (FP32).  Worst measured, FP64 / FP32: linf 3.2e-14 / 1.3e-5, linf of
+# the force 8.9e-13 / 3.0e-6, per bin 4.6e-13 / 1.9e-5, per cell 1.1e-12 /
+# 1.7e-4 (the band grid from a random state spanning 12 decades; line grids
+# 2.4e-5), per-cell force 2.4e-10 / 2.7e-3 (the developed 512 x 1024 state,
+# whose bin-dependent flux directions make a cell's force a cancelling sum).
+BOUNDS = {
+    "fp64": {"l2": 1e-12, "l2_force": 1e-12, "linf": 1e-12, "linf_force": 1e-11,
+             "bin": 1e-11, "cell": 1e-11, "cell_force": 1e-9},
+    "fp32": {"l2": 1e-5, "l2_force": 1e-4, "linf": 1e-4, "linf_force": 3e-5,
+             "bin": 2e-4, "cell": 1e-3, "cell_force": 1e-2},
+}
+
+BIN_FLOOR = 1e-30        # bins below this share of the largest value are skipped
+CELL_FLOOR = 1e-6        # cell-bins below this share of max E are skipped
+
+
+def _rel_l2(a, b):
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(a - b)) / nb if nb > 0 else float(np.linalg.norm(a))
+
+
+def _linf(a, b):
+    m = float(np.max(np.abs(b))) if b.size else 0.0
+    d = float(np.max(np.abs(a - b))) if b.size else 0.0
+    return d / m if m > 0 else d
+
+
+def metrics(E, Fx, Fy, force, rE, rFx, rFy, rforce):
+    """All checks for one comparison.  State arrays [N_nu, ...cells...]
+    (any trailing shape); force arrays [n_comp, ...cells...] whose first two
+    components form the vector (more components, e.g. the line share, are
+    compared as a second vector)."""
+    E, Fx, Fy, rE, rFx, rFy = [np.asarray(x, dtype=np.float64) for x in (E, Fx, Fy, rE, rFx, rFy)]
+    force, rforce = np.asarray(force, dtype=np.float64), np.asarray(rforce, dtype=np.float64)
+    nb = E.shape[0]
+    Em, Ftm = float(np.max(np.abs(rE))), float(np.max(np.hypot(rFx, rFy)))
+    dF = np.hypot(Fx - rFx, Fy - rFy)
+    out = {
+        "l2_E": _rel_l2(E, rE), "l2_Fx": _rel_l2(Fx, rFx), "l2_Fy": _rel_l2(Fy, rFy),
+        "l2_force": _rel_l2(force, rforce),
+        "linf_E": _linf(E, rE),
+        "linf_F": float(dF.max()) / Ftm if Ftm > 0 else float(dF.max()),
+    }
+    # per-bin normalised L-infinity
+    worstE = worstF = 0.0
+    for k in range(nb):
+        mk = float(np.max(np.abs(rE[k])))
+        if mk > BIN_FLOOR * Em:
+            worstE = max(worstE, float(np.max(np.abs(E[k] - rE[k]))) / mk)
+        fk = float(np.max(np.hypot(rFx[k], rFy[k])))
+        if fk > BIN_FLOOR * Ftm and Ftm > 0:
+            worstF = max(worstF, float(np.max(dF[k])) / fk)
+    out["bin_E"], out["bin_F"] = worstE, worstF
+    # per-cell relative error where E is not negligible
+    m = rE > CELL_FLOOR * Em
+    out["cell_E"] = float(np.max(np.abs(E[m] - rE[m]) / rE[m])) if m.any() else 0.0
+    out["cell_F"] = float(np.max(dF[m] / rE[m])) if m.any() else 0.0
+    out["cells_compared"] = int(m.sum())
+    # force: vectors of the first two components and, if present, of the next two
+    fl, fc = 0.0, 0.0
+    for c0 in range(0, force.shape[0] - 1, 2):
+        a = np.hypot(force[c0] - rforce[c0], force[c0 + 1] - rforce[c0 + 1])
+        r = np.hypot(rforce[c0], rforce[c0 + 1])
+        rm = float(r.max())
+        if rm > 0:
+            fl = max(fl, float(a.max()) / rm)
+            mm = r > CELL_FLOOR * rm
+            fc = max(fc, float(np.max(a[mm] / r[mm])))
+        else:
+            fl = max(fl, float(a.max()))
+    out["linf_force"], out["cell_force"] = fl, fc
+    return out
+
+
+def check(name, prec, got, ref, bounds=None, **override):
+    """Compares got = (E, Fx, Fy, force) with ref (same layout) and asserts
+    the bounds of `prec` (or `bounds`, with single entries overridden by
+    keyword).  Returns the metrics."""
+    b = dict(BOUNDS[prec] if bounds is None else bounds)
+    b.update(override)
+    m = metrics(*got, *ref)
+    line = {"case": name, "prec": prec, **m}
+    print("   parity", json.dumps(line), flush=True)
+    path = os.environ.get("PARITY_LOG")
+    if path:
+        with open(path, "a") as fh:
+            fh.write(json.dumps(line) + "\n")
+    fails = []
+    for key in ("l2_E", "l2_Fx", "l2_Fy"):
+        if m[key] > b["l2"]:
+            fails.append((key, m[key], b["l2"]))
+    pairs = (("l2_force", "l2_force"), ("linf_E", "linf"), ("linf_F", "linf"),
+             ("linf_force", "linf_force"), ("bin_E", "bin"), ("bin_F", "bin"),
+             ("cell_E", "cell"), ("cell_F", "cell"), ("cell_force", "cell_force"))
+    for key, bk in pairs:
+        if m[key] > b[bk]:
+            fails.append((key, m[key], b[bk]))
+    assert not fails, f"{name} ({prec}): {fails}"
+    for x in got:
+        assert np.all(np.isfinite(x)), name
+    assert float(np.min(got[0])) >= 0.0, name
+    return m

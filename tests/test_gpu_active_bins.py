@@ -6,21 +6,18 @@ transport step.  The oracle takes the same selection in FP64.  Each case's
 threshold keeps every nonzero share at least a factor e^0.005 away from it on
 every step (checked on the oracle's state), so the FP32 state, ~1e-6 from the
 oracle, cannot flip a bin: the advected sets are compared exactly, step by
-step, and the states to the parity tolerances (FP64 1e-12, FP32 1e-5 on E
-and F, 1e-4 on the force).
+step, and the states to the parity tolerances (relative L2 FP64 1e-12, FP32
+1e-5 on E and F and 1e-4 on the force, with the element-wise bounds of
+parity.py).
 """
 import numpy as np
 import pytest
 
+import parity
 from oracle import m1_oracle as M
 from paper_2606_02711_amd import inputs
 
 pytestmark = pytest.mark.gpu
-
-
-def rel(a, b):
-    nb = float(np.linalg.norm(b))
-    return float(np.linalg.norm(a - b)) / nb if nb > 0 else float(np.linalg.norm(a))
 
 
 def _volumes(o):
@@ -68,9 +65,8 @@ def test_active_bins_parity(geom, nx, ny, seed, thr, prec, tolE, tolF):
     assert partial >= steps - 1                           # the selection is not vacuous
     E, Fx, Fy = [t.double().cpu().numpy() for t in g.state()]
     f = g.force().cpu().numpy()
-    errs = dict(E=rel(E, o.E), Fx=rel(Fx, o.Fx), Fy=rel(Fy, o.Fy), force=rel(f, o.force))
-    print("   rel-L2", errs, flush=True)
-    assert max(errs["E"], errs["Fx"], errs["Fy"]) <= tolE and errs["force"] <= tolF, errs
+    parity.check(f"active bins {geom} {nx}x{ny} thr={thr}", prec, (E, Fx, Fy, f),
+                 (o.E, o.Fx, o.Fy, o.force), l2=tolE, l2_force=tolF)
     g.free()
 
 

@@ -1,13 +1,14 @@
 """GPU parity of the broad-band step (Section 2.5; Appendix E) against the FP64
 oracle, through the C ABI (m1_band_init, m1_step, m1_get_state, m1_force).
 
-Tolerances (relative L2 over all cells and bands, per result), as for the
-line step: FP64 1e-12 on E, F and the force; FP32 1e-5 on E and F, 1e-4 on
-the force.  Every case prints its name before touching the GPU.
+Tolerances per result, as for the line step: relative L2 FP64 1e-12 on E,
+F and the force, FP32 1e-5 on E and F and 1e-4 on the force, and the
+element-wise bounds of parity.py.  Every case prints its name before touching the GPU.
 """
 import numpy as np
 import pytest
 
+import parity
 from oracle import m1_oracle as M
 from paper_2606_02711_amd import inputs
 
@@ -46,12 +47,10 @@ def compare(p, steps, prec, tolE, tolF, state=None):
     o.step(steps)
     E, Fx, Fy = [t.double().cpu().numpy() for t in g.state()]
     f = g.force().cpu().numpy()
-    errs = dict(E=rel(E, o.E), Fx=rel(Fx, o.Fx), Fy=rel(Fy, o.Fy), force=rel(f, o.force))
-    print("   rel-L2", errs, flush=True)
-    assert errs["E"] <= tolE and errs["Fx"] <= tolE and errs["Fy"] <= tolE, errs
-    assert errs["force"] <= tolF, errs
-    assert np.all(np.isfinite(E)) and E.min() >= 0
-    assert np.all(np.isfinite(Fx)) and np.all(np.isfinite(Fy)) and np.all(np.isfinite(f))
+    name = (f"band {p['geom']} {p['nx']}x{p['ny']}x{p['n_band']} steps={steps} "
+            f"state={'set' if state is not None else 'zero'}")
+    errs = parity.check(name, prec, (E, Fx, Fy, f), (o.E, o.Fx, o.Fy, o.force),
+                        l2=tolE, l2_force=tolF)
     assert np.all(f[2:] == 0)                      # no line share for bands
     assert np.all(np.hypot(Fx, Fy) <= E * (1 + 1e-6))
     g.free()

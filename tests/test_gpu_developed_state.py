@@ -1,0 +1,63 @@
+"""GPU parity at the full 512 x 1024 size of the cylindrical workload (ionised
+bubble in a log-normal neutral shell, outflow, dust, p_d = 1e-6) from a
+developed state instead of E = F = 0.
+
+Every cell and bin starts filled (inputs.filled_state: a smooth spectrum over
+~7 decades, a spatial envelope, |f| spanning [0, 1] and exactly 1 in the
+outer far wings), set into the oracle and the GPU alike, so ten steps reach
+the whole grid: the neutral shell, whose cells have line-centre depths
+tau_cell,0 ~ 1e6-1e7, the outflow's Doppler term everywhere, the dust, and
+the one-pass frequency kernel the benchmark times (grids of at least 2^16
+cells).  FP64 against the oracle at 1e-12 (relative L2), FP32 at 1e-5 on E
+and F and 1e-4 on the force, with the element-wise bounds of parity.py, with
+float frequency-step coefficients everywhere (fp64_tau = inf) and with the
+double ones in cells of depth above 1e6 (fp64_tau = 1e6).
+"""
+import numpy as np
+import pytest
+
+import parity
+from oracle import m1_oracle as M
+from paper_2606_02711_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+STEPS = 10
+
+
+def e_peak(p, dt):
+    """A peak energy density of the order of the first step's emission,
+    c_tilde dt max(l) / (c 1e11 Hz), so the FP32 path's internal scale (taken
+    from the first step's emission) suits the state."""
+    return p["c_tilde"] * dt * float(np.max(p["fields"]["emis"])) / (M.C_LIGHT * 1.0e11)
+
+
+@pytest.fixture(scope="module")
+def developed():
+    p = inputs.config2()
+    o = M.Oracle(p)
+    state = inputs.filled_state(p, o.s.nb, e_peak(p, o.dt), seed=2)
+    o.set_state(*state)
+    print(f"[oracle] config 2 from a filled state, {STEPS} steps", flush=True)
+    o.step(STEPS)
+    tau0 = o.s.alpha.reshape(p["ny"], p["nx"]) * (p["x1"] - p["x0"]) / p["nx"]
+    return p, state, o, tau0
+
+
+@pytest.mark.parametrize("prec,fp64_tau", [("fp64", float("inf")), ("fp32", float("inf")),
+                                           ("fp32", 1.0e6)])
+def test_config2_full_size_from_developed_state(developed, prec, fp64_tau):
+    from paper_2606_02711_amd import m1
+    p, state, o, tau0 = developed
+    if fp64_tau < float("inf"):
+        assert int((tau0 >= fp64_tau).sum()) > 100000        # the shell takes the island path
+    print(f"[gpu] config 2 developed state {prec} fp64_tau={fp64_tau}", flush=True)
+    g = m1.M1Grid(p, prec=prec, fp64_tau=fp64_tau)
+    assert g.dt == pytest.approx(o.dt, rel=1e-14)
+    g.set_state(*state)
+    g.step(STEPS)
+    E, Fx, Fy = [t.double().cpu().numpy() for t in g.state()]
+    f = g.force().cpu().numpy()
+    g.free()
+    parity.check(f"config2 developed {STEPS} steps fp64_tau={fp64_tau}", prec,
+                 (E, Fx, Fy, f), (o.E, o.Fx, o.Fy, o.force))

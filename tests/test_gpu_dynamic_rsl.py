@@ -40,11 +40,6 @@ def test_dynamic_c_tilde_reports_a_bad_temperature():
         m1.dynamic_c_tilde(p, np.full((9, 12), 1.0e5))
 
 
-def _rel(a, b):
-    nb = float(np.linalg.norm(b))
-    return float(np.linalg.norm(a - b)) / nb if nb > 0 else float(np.linalg.norm(a))
-
-
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
 def test_set_c_tilde_midway_matches_oracle(prec, tol):
     """m1_set_c_tilde between steps: the grid continues from its state with
@@ -67,10 +62,9 @@ def test_set_c_tilde_midway_matches_oracle(prec, tol):
     o.step(4)
     E, Fx, Fy = [t.double().cpu().numpy() for t in g.state()]
     f = g.force().cpu().numpy()
-    errs = dict(E=_rel(E, o.E), Fx=_rel(Fx, o.Fx), Fy=_rel(Fy, o.Fy), force=_rel(f, o.force))
-    print("   rel-L2", errs, flush=True)
-    assert max(errs["E"], errs["Fx"], errs["Fy"]) <= tol
-    assert errs["force"] <= (tol if prec == "fp64" else 1e-4)
+    import parity
+    parity.check(f"set_c_tilde midway {prec}", prec, (E, Fx, Fy, f), (o.E, o.Fx, o.Fy, o.force),
+                 l2=tol, l2_force=tol if prec == "fp64" else 1e-4)
     g.free()
 
 

@@ -1,15 +1,17 @@
 """GPU parity: the HIP library (through the C ABI) against the FP64 oracle.
 
-Tolerances (relative L2 over all cells and bins, per result):
-  FP64 path : 1e-12 on E, F and the force (rounding-order differences only);
-  FP32 path : 1e-5 on E and F, 1e-4 on the force (the stated target).
+Tolerances per result (E, F, force), element by element (parity.py):
+  FP64 path : relative L2 1e-12 on E, F and the force (rounding-order
+              differences only), with the normalised L-infinity, per-bin
+              and per-cell bounds of parity.BOUNDS;
+  FP32 path : relative L2 1e-5 on E and F, 1e-4 on the force (the stated
+              target), with the FP32 element-wise bounds.
 Every case prints its name before touching the GPU.
 """
-import sys
-
 import numpy as np
 import pytest
 
+import parity
 from oracle import m1_oracle as M
 from paper_2606_02711_amd import inputs
 
@@ -32,16 +34,14 @@ def run_gpu(p, steps, prec, fp64_tau=float("inf")):
     return g, E, Fx, Fy, f
 
 
-def compare(p, steps, prec, tolE, tolF, oracle=None, fp64_tau=float("inf")):
+def compare(p, steps, prec, tolE, tolF, oracle=None, fp64_tau=float("inf"), name=None,
+            **bounds):
     g, E, Fx, Fy, f = run_gpu(p, steps, prec, fp64_tau)
     o = oracle if oracle is not None else M.run(p, steps=steps)
     assert g.dt == pytest.approx(o.dt, rel=1e-14)
-    errs = dict(E=rel(E, o.E), Fx=rel(Fx, o.Fx), Fy=rel(Fy, o.Fy), force=rel(f, o.force))
-    print("   rel-L2", errs, flush=True)
-    assert errs["E"] <= tolE and errs["Fx"] <= tolE and errs["Fy"] <= tolE, errs
-    assert errs["force"] <= tolF, errs
-    assert np.all(np.isfinite(E)) and E.min() >= 0
-    assert np.all(np.isfinite(Fx)) and np.all(np.isfinite(Fy)) and np.all(np.isfinite(f))
+    name = name or f"{p['geom']} {p['nx']}x{p['ny']} steps={steps} fp64_tau={fp64_tau}"
+    errs = parity.check(name, prec, (E, Fx, Fy, f), (o.E, o.Fx, o.Fy, o.force),
+                        l2=tolE, l2_force=tolF, **bounds)
     return g, errs
 
 
@@ -159,6 +159,33 @@ def test_batched_equals_alone_bitwise(prec):
     assert (ms[4] == float("inf")) == (prec == "fp64")      # fused: FP32 only
     b.step(7)
     _assert_same(gs, ref)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_members_match_oracle(prec):
+    """A batch of four grids of different sizes, geometries and media stepped
+    together (the tuning steps over every tile variant, then graph replays of
+    step pairs and an odd step): every member against the oracle run of its
+    own problem, at the parity bounds of its precision."""
+    from paper_2606_02711_amd import m1
+    import torch
+    ps = _mixed_problems()
+    steps = 5 * 3 + 5
+    print(f"[gpu] batch vs oracle {prec}", flush=True)
+    s = torch.cuda.Stream()
+    gs = [m1.M1Grid(p, prec=prec, stream=s) for p in ps]
+    b = m1.M1Batch(gs, use_graph=True)
+    b.step(steps)
+    s.synchronize()
+    for q, (p, g) in enumerate(zip(ps, gs)):
+        o = M.run(p, steps=steps)
+        assert g.dt == pytest.approx(o.dt, rel=1e-14)
+        E, Fx, Fy = [t.double().cpu().numpy() for t in g.state()]
+        parity.check(f"batch member {q} {p['geom']} {p['nx']}x{p['ny']}", prec,
+                     (E, Fx, Fy, g.force().cpu().numpy()), (o.E, o.Fx, o.Fy, o.force))
+    b.free()
+    for g in gs:
+        g.free()
 
 
 def test_fused_kernel_equals_two_kernel_path_bitwise():

@@ -14,17 +14,13 @@ taken within it.
 import numpy as np
 import pytest
 
+import parity
 from oracle import m1_oracle as M
 from paper_2606_02711_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
 E_FLOOR = 4.0 * np.pi * 1.0e-15 / M.C_LIGHT
-
-
-def rel(a, b):
-    nb = float(np.linalg.norm(b))
-    return float(np.linalg.norm(a - b)) / nb if nb > 0 else float(np.linalg.norm(a))
 
 
 def _problem(geom, nx, ny, seed, scale):
@@ -51,9 +47,7 @@ def test_substeps_fp64_parity():
     g.step(steps)
     E, Fx, Fy = [t.cpu().numpy() for t in g.state()]
     f = g.force().cpu().numpy()
-    errs = dict(E=rel(E, o.E), Fx=rel(Fx, o.Fx), Fy=rel(Fy, o.Fy), force=rel(f, o.force))
-    print("   rel-L2", errs, flush=True)
-    assert max(errs.values()) <= 1e-12, errs
+    parity.check("substeps fp64 cyl 24x20", "fp64", (E, Fx, Fy, f), (o.E, o.Fx, o.Fy, o.force))
     g.free()
 
 
@@ -75,10 +69,9 @@ def test_substeps_fp32_one_step_from_shared_state(geom, nx, ny, seed):
     g.step(1)
     E, Fx, Fy = [t.double().cpu().numpy() for t in g.state()]
     f = g.force().cpu().numpy()
-    errs = dict(E=rel(E[:, ok], o.E[:, ok]), Fx=rel(Fx[:, ok], o.Fx[:, ok]),
-                Fy=rel(Fy[:, ok], o.Fy[:, ok]), force=rel(f[:, ok], o.force[:, ok]))
-    print("   rel-L2 on safe cells", errs, flush=True)
-    assert max(errs["E"], errs["Fx"], errs["Fy"]) <= 1e-5 and errs["force"] <= 1e-4, errs
+    parity.check(f"substeps fp32 {geom} {nx}x{ny} safe cells", "fp32",
+                 (E[:, ok], Fx[:, ok], Fy[:, ok], f[:, ok]),
+                 (o.E[:, ok], o.Fx[:, ok], o.Fy[:, ok], o.force[:, ok]))
     assert np.all(np.isfinite(E)) and E.min() >= 0 and np.all(np.isfinite(f))
     g.free()
 
