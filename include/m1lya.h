@@ -166,6 +166,22 @@ int32_t m1_count_temperature_classes(const double *T_host, int64_t n, int64_t *n
 int32_t m1_dynamic_c_tilde(const m1_config *cfg, const m1_fields *fields, const double *d_cs,
                            double c_prev, void *d_work, void *stream, double *c_tilde);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, the tight loop of a hydrodynamics driver, harnesses that forbid
+ * allocation): m1_dynamic_c_tilde without d_work.  Its block maxima and their
+ * maximum go to a static device array of the library, 8448 bytes on every GPU
+ * the library runs on, held until the process ends; the call allocates
+ * nothing (no device or host allocator).  It works on the current device
+ * (stream, NULL = default, must belong to it) and returns the same value as
+ * m1_dynamic_c_tilde, bitwise.  Every grid size fits the array (the kernel
+ * strides over the cells).  Calls that overlap on one GPU (from other
+ * threads, or on other streams) race on the array.  Argument checks and
+ * errors as for m1_dynamic_c_tilde, plus M1_EDEVICE if the array's device
+ * address cannot be obtained.  Waits for the stream. */
+int32_t m1_dynamic_c_tilde_noalloc(const m1_config *cfg, const m1_fields *fields,
+                                   const double *d_cs, double c_prev, void *stream,
+                                   double *c_tilde);
+
 /* Validates cfg and fields, lays out the caller-owned workspace d_ws of
  * ws_bytes (>= m1_workspace_bytes for the field's class count, 256-byte
  * aligned), runs the set-up kernels (frequency grid, bin-averaged Voigt

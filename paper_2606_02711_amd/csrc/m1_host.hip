@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -655,6 +656,67 @@ int record_error(int code, const char* msg) {
 }
 }  // namespace m1
 
+// ---- scratch of the entry point without allocation.  A file-scope device
+// array (one copy per GPU, alive until the process ends): the block maxima
+// of the dynamic reduced speed of light and, after them, their maximum.  In
+// host code `scratch` names a host-side stand-in, never a device address:
+// kernels and copies use the per-device address from hipGetSymbolAddress.
+constexpr int kScratchDoubles = kDynRslBlocks + 32;           // 8448 bytes
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+// Arguments of the dynamic reduced speed of light, checked before any
+// device work: cell inputs, cell count and the larger cell side.
+int dyn_rsl_args(const m1_config* cfg, const m1_fields* f, const double* d_cs, double c_prev,
+                 double* c_tilde, CellInputs* in, size_t* nc, double* dmax) {
+  int st = validate_config(cfg, nullptr);
+  if (st) return st;
+  if (!f || !d_cs || !c_tilde) return fail(M1_EINVAL, "NULL argument");
+  if (!f->on_device) return fail(M1_EINVAL, "fields must be device arrays (on_device = 1)");
+  if (!f->n_HI || !f->T || !f->u_x || !f->u_y || !f->alpha_abs || !f->p_d)
+    return fail(M1_EINVAL, "a field array is NULL");
+  if (!(c_prev >= 0.0) || !isfinite(c_prev)) return fail(M1_EINVAL, "c_prev must be finite and >= 0");
+  *nc = (size_t)cfg->nx * cfg->ny;
+  *dmax = std::max((cfg->x1 - cfg->x0) / cfg->nx, (cfg->y1 - cfg->y0) / cfg->ny);
+  *in = CellInputs{f->n_HI, f->T, f->u_x, f->u_y, f->alpha_abs, f->alpha_flux, f->p_d, f->emis};
+  return M1_OK;
+}
+
+// c_tilde = min(max(c_min, eps_RSL m), c), rate-limited against c_prev > 0.
+int dyn_rsl_finish(double m, double c_prev, double* c_tilde) {
+  if (m != m) return fail(M1_EINVAL, "non-finite trapping term (check T > 0 and the opacities)");
+  double c = std::min(std::max(kCTildeMin, kEpsRsl * m), kC);
+  if (c_prev > 0.0) c = std::min(std::max(c, 0.75 * c_prev), 4.0 * c_prev);
+  *c_tilde = c;
+  return M1_OK;
+}
+
+// Devices whose scratch address is kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the current device's scratch, looked up once per device
+// (the first call on that device, with the device current).
+int scratch_address(double** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(M1_EDEVICE, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(M1_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_dev[dev] = (double*)p;
+  }
+  *out = g_scratch_dev[dev];
+  return M1_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* m1_last_error(void) { return g_err.c_str(); }
@@ -698,19 +760,16 @@ int32_t m1_frequency_grid(const m1_config* cfg, double* nu_centre, double* dnu) 
   return M1_OK;
 }
 
+
 int32_t m1_dynamic_c_tilde(const m1_config* cfg, const m1_fields* f, const double* d_cs,
                            double c_prev, void* d_work, void* stream, double* c_tilde) {
-  int st = validate_config(cfg, nullptr);
+  CellInputs in;
+  size_t nc = 0;
+  double dmax = 0.0;
+  int st = dyn_rsl_args(cfg, f, d_cs, c_prev, c_tilde, &in, &nc, &dmax);
   if (st) return st;
-  if (!f || !d_cs || !d_work || !c_tilde) return fail(M1_EINVAL, "NULL argument");
-  if (!f->on_device) return fail(M1_EINVAL, "fields must be device arrays (on_device = 1)");
-  if (!f->n_HI || !f->T || !f->u_x || !f->u_y || !f->alpha_abs || !f->p_d)
-    return fail(M1_EINVAL, "a field array is NULL");
+  if (!d_work) return fail(M1_EINVAL, "NULL argument");
   if (((uintptr_t)d_work) & 7) return fail(M1_EINVAL, "d_work not 8-byte aligned");
-  if (!(c_prev >= 0.0) || !isfinite(c_prev)) return fail(M1_EINVAL, "c_prev must be finite and >= 0");
-  const size_t nc = (size_t)cfg->nx * cfg->ny;
-  const double dmax = std::max((cfg->x1 - cfg->x0) / cfg->nx, (cfg->y1 - cfg->y0) / cfg->ny);
-  CellInputs in{f->n_HI, f->T, f->u_x, f->u_y, f->alpha_abs, f->alpha_flux, f->p_d, f->emis};
   hipStream_t s = (hipStream_t)stream;
   const int nblk = (int)std::min<size_t>((nc + 255) / 256, kDynRslBlocks);
   HIPCHK(launch_dyn_rsl(in, d_cs, nc, dmax, (double*)d_work, nblk, s));
@@ -719,13 +778,35 @@ int32_t m1_dynamic_c_tilde(const m1_config* cfg, const m1_fields* f, const doubl
   HIPCHK(hipStreamSynchronize(s));
   double m = 0.0;
   for (double v : part) {
-    if (v != v) return fail(M1_EINVAL, "non-finite trapping term (check T > 0 and the opacities)");
+    if (v != v) return dyn_rsl_finish(v, c_prev, c_tilde);
     m = std::max(m, v);
   }
-  double c = std::min(std::max(kCTildeMin, kEpsRsl * m), kC);
-  if (c_prev > 0.0) c = std::min(std::max(c, 0.75 * c_prev), 4.0 * c_prev);
-  *c_tilde = c;
-  return M1_OK;
+  return dyn_rsl_finish(m, c_prev, c_tilde);
+}
+
+int32_t m1_dynamic_c_tilde_noalloc(const m1_config* cfg, const m1_fields* f,
+                                   const double* d_cs, double c_prev, void* stream,
+                                   double* c_tilde) {
+  CellInputs in;
+  size_t nc = 0;
+  double dmax = 0.0;
+  int st = dyn_rsl_args(cfg, f, d_cs, c_prev, c_tilde, &in, &nc, &dmax);
+  if (st) return st;
+  double* work = nullptr;
+  st = scratch_address(&work);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  // every grid size fits: the kernel strides over the cells, so the block
+  // maxima never outnumber kDynRslBlocks; the check states the bound
+  const int nblk = (int)std::min<size_t>((nc + 255) / 256, kDynRslBlocks);
+  if (nblk + 1 > kScratchDoubles)
+    return fail(M1_EINVAL, "%d block maxima exceed the %d-double scratch", nblk, kScratchDoubles);
+  HIPCHK(launch_dyn_rsl(in, d_cs, nc, dmax, work, nblk, s));
+  HIPCHK(launch_max_of(work, nblk, work + kDynRslBlocks, s));
+  double m = 0.0;
+  HIPCHK(hipMemcpyAsync(&m, work + kDynRslBlocks, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return dyn_rsl_finish(m, c_prev, c_tilde);
 }
 
 int32_t m1_count_temperature_classes(const double* T, int64_t n, int64_t* n_classes) {

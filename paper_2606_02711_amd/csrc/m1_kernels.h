@@ -92,6 +92,8 @@ hipError_t launch_velocity(const CellInputs& in, int nx, int ny, int geom, const
 // Block maxima of the dynamic reduced-speed-of-light term (cs: sound speed).
 hipError_t launch_dyn_rsl(const CellInputs& in, const double* cs, size_t nc, double dmax,
                           double* partial, int nblk, hipStream_t s);
+// Maximum of n doubles on the device (NaN if any is NaN) into *out.
+hipError_t launch_max_of(const double* partial, int n, double* out, hipStream_t s);
 
 // Block partials of max |u|, max emis, min T (for dt and the state scale).
 hipError_t launch_init_reduce(const CellInputs& in, size_t nc, double* partial, int nblk,

@@ -253,6 +253,26 @@ hipError_t launch_dyn_rsl(const CellInputs& in, const double* cs, size_t nc, dou
   return hipGetLastError();
 }
 
+// The maximum of n block maxima (NaN if any is NaN) into *out, one block.
+__global__ __launch_bounds__(256) void k_max_of(const double* __restrict__ partial, int n,
+                                                double* __restrict__ out) {
+  __shared__ double sm[256];
+  double best = 0.0;
+  for (int b = threadIdx.x; b < n; b += 256) best = nan_max(best, partial[b]);
+  sm[threadIdx.x] = best;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sm[threadIdx.x] = nan_max(sm[threadIdx.x], sm[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sm[0];
+}
+
+hipError_t launch_max_of(const double* partial, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_max_of, dim3(1), dim3(256), 0, s, partial, n, out);
+  return hipGetLastError();
+}
+
 template hipError_t launch_class_profiles<float>(const double*, const double*, int64_t,
                                                  const double*, const double*, int,
                                                  const double*, double*, float*, float*,

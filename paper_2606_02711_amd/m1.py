@@ -103,6 +103,7 @@ def lib():
         "m1_active_bins": (I32, [VP, VP, P(I32)]),
         "m1_set_c_tilde": (I32, [VP, D]),
         "m1_dynamic_c_tilde": (I32, [P(m1_config), P(m1_fields), VP, D, VP, VP, P(D)]),
+        "m1_dynamic_c_tilde_noalloc": (I32, [P(m1_config), P(m1_fields), VP, D, VP, P(D)]),
         "m1_band_workspace_bytes": (I32, [P(m1_config), I32, P(ctypes.c_size_t)]),
         "m1_band_init": (I32, [P(m1_config), I32, P(m1_band_fields), VP, ctypes.c_size_t, VP,
                                P(VP)]),
@@ -140,7 +141,8 @@ def exported_symbols():
     return ["m1_default_config", "m1_num_bins", "m1_frequency_grid", "m1_workspace_bytes",
             "m1_count_temperature_classes", "m1_init", "m1_step", "m1_force",
             "m1_solve_steady", "m1_residual", "m1_residuals", "m1_get_state", "m1_set_state", "m1_get_state_region", "m1_get_info",
-            "m1_active_bins", "m1_set_c_tilde", "m1_dynamic_c_tilde", "m1_band_workspace_bytes", "m1_band_init",
+            "m1_active_bins", "m1_set_c_tilde", "m1_dynamic_c_tilde",
+            "m1_dynamic_c_tilde_noalloc", "m1_band_workspace_bytes", "m1_band_init",
             "m1_batch_workspace_bytes", "m1_batch_init", "m1_batch_step", "m1_batch_info",
             "m1_batch_free", "m1_batch_set_tile", "m1_batch_workspace_bound",
             "m1_server_create", "m1_server_submit", "m1_server_run", "m1_server_poll",
@@ -207,9 +209,10 @@ def count_temperature_classes(T):
 FIELD_ORDER = ("n_HI", "T", "u_x", "u_y", "alpha_abs", "alpha_flux", "p_d", "emis")
 
 
-def dynamic_c_tilde(p, cs, c_prev=0.0):
+def dynamic_c_tilde(p, cs, c_prev=0.0, noalloc=False):
     """The reduced speed of light the paper chooses for the medium of p with
-    sound speeds cs [cm/s] (m1_dynamic_c_tilde), the fields copied to the GPU."""
+    sound speeds cs [cm/s] (m1_dynamic_c_tilde, or with noalloc
+    m1_dynamic_c_tilde_noalloc), the fields copied to the GPU."""
     torch = _torch()
     cfg = make_config(p)
     f = p["fields"]
@@ -223,8 +226,13 @@ def dynamic_c_tilde(p, cs, c_prev=0.0):
     fl.on_device = 1
     torch.cuda.current_stream().synchronize()      # inputs written on torch's stream
     out = ctypes.c_double()
-    check(lib().m1_dynamic_c_tilde(ctypes.byref(cfg), ctypes.byref(fl), d_cs.data_ptr(),
-                                   float(c_prev), work.data_ptr(), None, ctypes.byref(out)))
+    if noalloc:
+        check(lib().m1_dynamic_c_tilde_noalloc(ctypes.byref(cfg), ctypes.byref(fl),
+                                               d_cs.data_ptr(), float(c_prev), None,
+                                               ctypes.byref(out)))
+    else:
+        check(lib().m1_dynamic_c_tilde(ctypes.byref(cfg), ctypes.byref(fl), d_cs.data_ptr(),
+                                       float(c_prev), work.data_ptr(), None, ctypes.byref(out)))
     return out.value
 
 

@@ -220,6 +220,30 @@ def test_dynamic_c_tilde_argument_checks_without_device_work():
                                 ctypes.byref(out)) == m1.M1_EINVAL
 
 
+def test_dynamic_c_tilde_noalloc_argument_checks_without_device_work():
+    """The entry point without allocation refuses what m1_dynamic_c_tilde
+    refuses, before any device call (and before it looks up its array)."""
+    import ctypes
+    L = m1.lib()
+    p = inputs.config1()
+    cfg = m1.make_config(p)
+    fl = m1.m1_fields()
+    out = ctypes.c_double()
+    fake = 1 << 40                         # never dereferenced
+    for n in m1.FIELD_ORDER:
+        setattr(fl, n, fake)
+    fl.on_device = 0
+    f = L.m1_dynamic_c_tilde_noalloc
+    assert f(ctypes.byref(cfg), ctypes.byref(fl), fake, 0.0, None, ctypes.byref(out)) == m1.M1_EINVAL
+    fl.on_device = 1
+    assert f(ctypes.byref(cfg), ctypes.byref(fl), None, 0.0, None, ctypes.byref(out)) == m1.M1_EINVAL
+    assert f(ctypes.byref(cfg), ctypes.byref(fl), fake, float("nan"), None,
+             ctypes.byref(out)) == m1.M1_EINVAL
+    assert f(ctypes.byref(cfg), ctypes.byref(fl), fake, 0.0, None, None) == m1.M1_EINVAL
+    fl.T = None
+    assert f(ctypes.byref(cfg), ctypes.byref(fl), fake, 0.0, None, ctypes.byref(out)) == m1.M1_EINVAL
+
+
 # ------------------------------------------------------------ band grids
 def _band_init_code(p, n_band=None, ws_ptr=256, ws_bytes=None, prec="fp64", cfg=None):
     L = m1.lib()
