@@ -2,16 +2,26 @@
 
 Workload: the 512 x 1024 cylindrical (R, z) cloud (ionised bubble in a
 log-normal neutral shell, radial outflow, dust, p_d = 1e-6, point source on
-the axis), 194 frequency bins, synthetic seeded fields.  A step is one full
-pass of the hot path: advection + emission/absorption, force density, and the
-implicit frequency step, for every cell and bin.
+the axis), 194 frequency bins, synthetic seeded fields, stepped from a
+developed radiation field (every cell and bin filled: inputs.filled_state).
+A step is one full pass of the hot path: advection + emission/absorption,
+force density, and the implicit frequency step, for every cell and bin.
 
-value      : FP32-path cell-bin updates per second (N_cells x N_nu x steps / s),
-             state resident in HBM before the timed region starts.
-fp64_value : the FP64 plain path on the same workload.
-roofline   : the dominant kernel's algorithmic bytes (read + write of E, F_x,
-             F_y once per cell-bin: 24 B FP32) over its HIP-event duration.
-cpu_baseline : the FP64 oracle on the host cores, on a bounded sample.
+value      : FP32-path cell-bin updates per second (N_cells x N_nu x steps / s)
+             from the developed state, state resident in HBM before the timed
+             region starts; from_empty gives the same path from E = F = 0
+             (steps warmup..warmup+steps and near step 1000).
+fp64_value : the FP64 plain path on the same workload and state.
+errors     : FP32 and FP64 GPU paths against the FP64 oracle (and FP32
+             against FP64) after 10 steps from the developed state: relative
+             L2 and normalised L-infinity of E, F and the force.
+roofline   : the dominant kernel (advection) is bound by vector-instruction
+             issue: VALU lane-instructions per second (committed counters x
+             cell-bins / HIP-event duration) against the issue peak, with its
+             HBM figures (algorithmic bytes: E, F_x, F_y read and written once
+             per cell-bin, 24 B FP32) beside them.
+cpu_baseline : the FP64 oracle on the host cores (all threads and one), on a
+             bounded sample: 10 (1) steps from the same developed state.
 """
 import argparse
 import hashlib
@@ -100,15 +110,19 @@ def copy_bandwidth():
     return 2.0 * (1 << 30) / (best * 1e-3) / 1e9
 
 
-def run_path(p, prec, steps, warmup, fp64_tau=float("inf")):
+def e_peak(p, dt):
+    """Peak energy density of the developed state: of the order of the first
+    step's emission, c_tilde dt max(l) / (c 1e11 Hz)."""
+    import numpy as np
+    return p["c_tilde"] * dt * float(np.max(p["fields"]["emis"])) / (2.99792458e10 * 1.0e11)
+
+
+def _timed(g, steps):
+    """Times `steps` steps of grid g (wall clock, and HIP events around each
+    kernel on the grid's stream)."""
     import torch
-    from paper_2606_02711_amd import m1
-    log(f"[bench] init {prec} fp64_tau={fp64_tau}")
-    g = m1.M1Grid(p, prec=prec, fp64_tau=fp64_tau)
-    g.step(warmup)
     g.sync()
     torch.cuda.synchronize()
-    log(f"[bench] timing {steps} steps {prec}")
     t0 = time.perf_counter()
     ms = [0.0, 0.0]
     left = steps
@@ -121,8 +135,28 @@ def run_path(p, prec, steps, warmup, fp64_tau=float("inf")):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     cell_bins = g.ncell * g.nb
-    res = dict(wall=wall, ms_advect=ms[0], ms_freq=ms[1], cell_bins=cell_bins, nb=g.nb,
-               ncell=g.ncell, rate=cell_bins * steps / wall)
+    return dict(wall=wall, ms_advect=ms[0], ms_freq=ms[1], cell_bins=cell_bins, nb=g.nb,
+                ncell=g.ncell, rate=cell_bins * steps / wall,
+                ms_per_step=1e3 * wall / steps)
+
+
+def run_path(p, prec, steps, warmup, fp64_tau=float("inf"), state=None, late=0):
+    """Times `steps` steps after `warmup` untimed ones, from `state` (physical
+    E, F_x, F_y) or from E = F = 0; with late > 0 also `steps` steps starting
+    at step `late`."""
+    import torch
+    from paper_2606_02711_amd import m1
+    log(f"[bench] init {prec} fp64_tau={fp64_tau} start={'developed' if state else 'empty'}")
+    g = m1.M1Grid(p, prec=prec, fp64_tau=fp64_tau)
+    if state is not None:
+        g.set_state(*state)
+    g.step(warmup)
+    log(f"[bench] timing {steps} steps {prec}")
+    res = _timed(g, steps)
+    res["dt"] = g.dt
+    if late > warmup + steps:
+        g.step(late - warmup - steps)
+        res["late"] = dict(_timed(g, steps), first_step=late)
     del g
     torch.cuda.empty_cache()
     return res
@@ -317,6 +351,16 @@ def run_large(steps, warmup):
     return out
 
 
+def arena_bytes(gb):
+    """The serving arena: gb GiB, or with gb <= 0 the device's free HBM less
+    4 GiB (so admission is bounded by the memory the GPU really has)."""
+    import torch
+    if gb > 0:
+        return int(gb) << 30
+    free, _ = torch.cuda.mem_get_info()
+    return int(free - (4 << 30)) & ~255
+
+
 def run_serving(args):
     """Poisson stream of steady-state solves (uniform clouds, log N_HI 19..23,
     T 100..1e4 K, dust 0..0.01 solar) through the continuous-batching engine
@@ -325,12 +369,17 @@ def run_serving(args):
     reqs = inputs.config4_requests(rate=args.serve_rate, duration=args.serve_seconds,
                                    lo=args.serve_lo, hi=args.serve_hi)
     out = {"workload": f"Poisson {args.serve_rate} req/s for {args.serve_seconds} s, sides "
-                       f"log-uniform {args.serve_lo}..{args.serve_hi}, rel_tol 1e-6",
+                       f"log-uniform {args.serve_lo}..{args.serve_hi}, uniform clouds log N_HI "
+                       f"19..23, T 100..1e4 K, dust 0..0.01 solar; steady solve to relative "
+                       f"residual 1e-6, at most {args.serve_max_steps} steps per request",
            "requests": len(reqs)}
     for name, prec, batched, slots in (("fp32_batched", "fp32", True, args.serve_slots),
                                        ("fp64_plain", "fp64", False, 1)):
-        log(f"[bench] serving {name}: {len(reqs)} requests")
-        r = serve.run_stream(reqs, prec=prec, batched=batched, arena_bytes=args.serve_arena_gb << 30,
+        import torch
+        torch.cuda.empty_cache()               # the previous run's arena back to the device
+        arena = arena_bytes(args.serve_arena_gb)
+        log(f"[bench] serving {name}: {len(reqs)} requests, arena {arena / 2**30:.1f} GiB")
+        r = serve.run_stream(reqs, prec=prec, batched=batched, arena_bytes=arena,
                              max_resident=slots, check_every=32, rel_tol=1e-6,
                              max_steps=args.serve_max_steps, duration=args.serve_seconds,
                              drain=args.serve_drain, log=log)
@@ -338,18 +387,82 @@ def run_serving(args):
     return out
 
 
-def cpu_baseline(p, steps=10):
+def cpu_model():
+    """Host CPU model and logical CPU count (from /proc/cpuinfo)."""
+    model, n = "unknown", 0
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    n += 1
+                    if model == "unknown":
+                        model = line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return model, n
+
+
+def gpu_after(p, prec, state, steps):
+    """E, F_x, F_y and the force of the GPU path after `steps` steps from
+    `state`, as host arrays."""
+    import torch
+    from paper_2606_02711_amd import m1
+    g = m1.M1Grid(p, prec=prec)
+    g.set_state(*state)
+    g.step(steps)
+    out = [t.cpu().numpy() for t in g.state()] + [g.force().cpu().numpy()]
+    g.free()
+    del g
+    torch.cuda.empty_cache()
+    return out
+
+
+def error_figures(a, b):
+    """Relative L2 and normalised L-infinity of E, F (vector) and the force
+    (total, vector) of result a against reference b."""
+    import numpy as np
+    def pair(x, y):
+        d = float(np.sqrt(sum(np.sum((u - v) ** 2) for u, v in zip(x, y))))
+        n = float(np.sqrt(sum(np.sum(v ** 2) for v in y)))
+        dm = float(np.max(np.sqrt(sum((u - v) ** 2 for u, v in zip(x, y)))))
+        nm = float(np.max(np.sqrt(sum(v ** 2 for v in y))))
+        return {"rel_l2": d / n if n > 0 else d, "linf": dm / nm if nm > 0 else dm}
+    return {"E": pair([a[0]], [b[0]]), "F": pair(a[1:3], b[1:3]),
+            "force": pair([a[3][0], a[3][1]], [b[3][0], b[3][1]])}
+
+
+def cpu_baseline(p, state, steps=10, steps_1t=1):
+    """The FP64 oracle on the host: `steps` steps from `state` with every
+    thread (the reference of the error figures) and `steps_1t` with one."""
     from oracle import m1_oracle
     log(f"[bench] oracle sample: {steps} steps of the full workload on the host")
     o = m1_oracle.Oracle(p)
+    o.set_state(*state)
     t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
+    ref = [o.E.copy(), o.Fx.copy(), o.Fy.copy(), o.force.copy()]
     n = o.s.nx * o.s.ny * o.s.nb * steps
-    return {"value": n / dt, "unit": "cell-bin updates/s", "cores": m1_oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{steps} steps of the 512x1024 cylindrical workload from E=F=0, all "
-                      f"{o.s.nb} bins ({n:.3e} cell-bin updates, {dt:.1f} s)"}
+    threads = m1_oracle.num_threads()
+    log(f"[bench] oracle sample: {steps_1t} step(s) on one thread")
+    o.set_state(*state)
+    m1_oracle.set_num_threads(1)
+    t1 = time.perf_counter()
+    o.step(steps_1t)
+    dt1 = time.perf_counter() - t1
+    m1_oracle.set_num_threads(threads)
+    n1 = o.s.nx * o.s.ny * o.s.nb * steps_1t
+    model, ncpu = cpu_model()
+    out = {"value": n / dt, "unit": "cell-bin updates/s", "cores": threads, "kind": "oracle",
+           "sample": f"{steps} steps of the 512x1024 cylindrical workload from the developed "
+                     f"state, all {o.s.nb} bins ({n:.3e} cell-bin updates, {dt:.1f} s, "
+                     f"{threads} threads); one thread: {steps_1t} step ({n1:.3e}, {dt1:.1f} s)",
+           "value_1_thread": n1 / dt1,
+           "ns_per_cell_bin_per_core": 1e9 * dt1 / n1,
+           "cpu_model": model, "host_logical_cpus": ncpu,
+           "build": "gcc -O3, no fast-math, no FMA contraction"}
+    del o
+    return out, ref
 
 
 def main():
@@ -373,15 +486,19 @@ def main():
                     help="only the seven-band workload")
     ap.add_argument("--serve-seconds", type=float, default=30.0,
                     help="length of the request stream (0 skips the serving workload)")
-    ap.add_argument("--serve-rate", type=float, default=0.5, help="requests per second")
-    ap.add_argument("--serve-lo", type=int, default=64)
-    ap.add_argument("--serve-hi", type=int, default=128)
+    ap.add_argument("--serve-rate", type=float, default=0.3, help="requests per second")
+    ap.add_argument("--serve-lo", type=int, default=128)
+    ap.add_argument("--serve-hi", type=int, default=160)
     ap.add_argument("--serve-slots", type=int, default=32, help="resident requests at most")
-    ap.add_argument("--serve-arena-gb", type=int, default=64)
+    ap.add_argument("--serve-arena-gb", type=int, default=0,
+                    help="serving arena in GiB (0: the device's free HBM less 4 GiB)")
     ap.add_argument("--serve-max-steps", type=int, default=200000)
     ap.add_argument("--serve-drain", type=float, default=30.0,
                     help="seconds after the stream ends before the backlog is counted")
     ap.add_argument("--serve-only", action="store_true")
+    ap.add_argument("--serve-config4", action="store_true",
+                    help="only the serving workload as specified: 50 req/s for 120 s, sides "
+                         "128..2048 (far beyond one GPU's capacity; reports the backlog)")
     ap.add_argument("--active-only", action="store_true",
                     help="run only the active-bin workload")
     ap.add_argument("--batch-only", action="store_true",
@@ -409,6 +526,10 @@ def main():
         torch.cuda.synchronize()
         log("[bench] copy calibration: 3 copies of 1 GiB")
         del src, dst
+    if args.serve_config4:
+        args.serve_rate, args.serve_seconds, args.serve_lo, args.serve_hi = 50.0, 120.0, 128, 2048
+        print(json.dumps({"serving_config4": run_serving(args)}), flush=True)
+        return
     if args.serve_only:
         print(json.dumps({"serving": run_serving(args)}), flush=True)
         return
@@ -426,13 +547,30 @@ def main():
     copy_gbs = copy_bandwidth()
     log(f"[bench] device copy: {copy_gbs:.0f} GB/s")
     p = inputs.config2()
-    r32 = run_path(p, "fp32", args.steps, args.warmup, args.fp64_tau)
-    r64 = None if args.no_fp64 else run_path(p, "fp64", args.steps, args.warmup)
+    # FP32 from E = F = 0: the steps after the warm-up, and near step 1000
+    r32e = run_path(p, "fp32", args.steps, args.warmup, args.fp64_tau, late=1000)
+    # the developed state every timed and compared run below starts from
+    state = inputs.filled_state(p, r32e["nb"], e_peak(p, r32e["dt"]), seed=2)
+    r32 = run_path(p, "fp32", args.steps, args.warmup, args.fp64_tau, state=state)
+    r64 = None if args.no_fp64 else run_path(p, "fp64", args.steps, args.warmup, state=state)
     dom = "advect_source" if r32["ms_advect"] >= r32["ms_freq"] else "freq_step"
     dom_ms = (r32["ms_advect"] if dom == "advect_source" else r32["ms_freq"]) / args.steps
     alg_bytes = 24.0 * r32["cell_bins"]                    # per launch, FP32
     achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
     traffic = measured_traffic(dom, "fp32")
+    valu = measured_valu(dom, "fp32")
+    if valu is not None:
+        rate = valu * r32["cell_bins"] / (dom_ms * 1e-3)
+        roof = {"bound": "alu", "kernel": dom, "achieved": rate, "peak": VALU_PEAK,
+                "unit": "VALU lane-instr/s", "frac": rate / VALU_PEAK,
+                "valu_per_cell_bin": valu, "traffic": traffic,
+                "hbm_achieved": achieved, "hbm_peak": HBM_PEAK_GBS, "hbm_unit": "GB/s",
+                "hbm_frac": achieved / HBM_PEAK_GBS, "copy_GBs": copy_gbs,
+                "hbm_frac_of_copy": achieved / copy_gbs}
+    else:                       # no counters for this source: the HBM figures alone
+        roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs}
     out = {
         "metric": "M1 Ly\u03b1 cell-updates/s (FP32 batched vs FP64 plain), %HBM roofline, p99 solve latency",
         "value": r32["rate"],
@@ -448,14 +586,24 @@ def main():
         "data": "synthetic",
         "config": {"workload": "cylindrical 512x1024 (R,z) bubble + log-normal k^-2 shell, "
                                "radial outflow 30 km/s, dust 0.01 solar, p_d 1e-6, axis point "
-                               "source; 194 frequency bins; FP32 path",
+                               "source; 194 frequency bins; FP32 path; stepped from a developed "
+                               "radiation field (every cell and bin filled)",
                    "nx": 512, "ny": 1024, "n_nu": r32["nb"],
                    "spatial_cell_updates_per_s": r32["rate"] / r32["nb"]},
         "kernel_ms_per_step": {"advect_source": r32["ms_advect"] / args.steps,
                                "freq_step": r32["ms_freq"] / args.steps},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
+        "roofline": roof,
+        "from_empty": {
+            "first_timed_step": args.warmup, "value": r32e["rate"],
+            "ms_per_step": r32e["ms_per_step"],
+            "kernel_ms_per_step": {"advect_source": r32e["ms_advect"] / args.steps,
+                                   "freq_step": r32e["ms_freq"] / args.steps},
+            "near_step_1000": {"first_timed_step": r32e["late"]["first_step"],
+                               "value": r32e["late"]["rate"],
+                               "ms_per_step": r32e["late"]["ms_per_step"],
+                               "kernel_ms_per_step": {
+                                   "advect_source": r32e["late"]["ms_advect"] / args.steps,
+                                   "freq_step": r32e["late"]["ms_freq"] / args.steps}}},
     }
     # both kernels: algorithmic and (when the committed counters match the
     # source) measured HBM rates, against the nominal peak and the device copy
@@ -475,17 +623,22 @@ def main():
                        valu_issue_frac=v * r32["cell_bins"] / (ms * 1e-3) / VALU_PEAK)
         kern[name] = rec
     out["kernels_fp32"] = kern
-    valu = measured_valu(dom, "fp32")
-    if valu is not None:
-        rate = valu * r32["cell_bins"] / (dom_ms * 1e-3)
-        out["roofline_valu"] = {"bound": "alu", "kernel": dom, "achieved": rate, "peak": VALU_PEAK,
-                                "unit": "VALU lane-instr/s", "frac": rate / VALU_PEAK,
-                                "valu_per_cell_bin": valu}
     if r64 is not None:
         out["fp64_value"] = r64["rate"]
         out["fp64_ms_per_step"] = 1e3 * r64["wall"] / args.steps
         out["fp64_kernel_ms_per_step"] = {"advect_source": r64["ms_advect"] / args.steps,
                                           "freq_step": r64["ms_freq"] / args.steps}
+    # errors after 10 steps from the developed state, and the oracle's timing
+    log("[bench] error figures: FP32 and FP64 paths, 10 steps from the developed state")
+    g32 = gpu_after(p, "fp32", state, 10)
+    g64 = gpu_after(p, "fp64", state, 10)
+    out["errors"] = {"steps": 10, "start": "developed state", "fp32_vs_fp64": error_figures(g32, g64)}
+    if not args.no_cpu:
+        out["cpu_baseline"], ref = cpu_baseline(p, state, 10, 1)
+        out["errors"]["fp32_vs_oracle"] = error_figures(g32, ref)
+        out["errors"]["fp64_vs_oracle"] = error_figures(g64, ref)
+        del ref
+    del g32, g64, state
     if args.batch_steps > 0:
         rb = run_batch(inputs.config3(), args.batch_steps, args.warmup)
         out["batch_64_grids"] = {
@@ -506,8 +659,6 @@ def main():
         out["bands"] = run_bands(args.band_steps, args.warmup)
     if args.serve_seconds > 0:
         out["serving"] = run_serving(args)
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)
 
 

@@ -209,12 +209,14 @@ class _Prob(ctypes.Structure):
 
 
 def build(force=False):
-    """Compile the C core with gcc (no fast-math, no FMA contraction)."""
+    """Compile the C core with gcc -O3 for the generic x86-64 target (the library
+    built here also runs on other hosts, so no -march=native), without
+    fast-math or FMA contraction."""
     if not force and os.path.exists(LIB_PATH) and \
             os.path.getmtime(LIB_PATH) >= os.path.getmtime(SRC_PATH):
         return LIB_PATH
     tmp = LIB_PATH + ".tmp%d" % os.getpid()
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+    subprocess.check_call(["gcc", "-O3", "-std=c11", "-fopenmp", "-fPIC", "-shared",
                            "-ffp-contract=off", "-fno-fast-math", "-o", tmp, SRC_PATH, "-lm"])
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -233,6 +235,7 @@ def lib():
         L.oracle_eddington.argtypes = [ctypes.c_double] * 3 + [ctypes.c_void_p]
         L.oracle_interface_rates.argtypes = [ctypes.c_double] * 6 + [ctypes.c_void_p]
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -400,6 +403,11 @@ def run(p, steps=None, dt=None):
 
 def num_threads():
     return lib().oracle_num_threads()
+
+
+def set_num_threads(n):
+    """OpenMP threads of later steps (the arithmetic does not depend on it)."""
+    lib().oracle_set_num_threads(int(n))
 
 
 if __name__ == "__main__":

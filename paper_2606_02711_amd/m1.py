@@ -621,6 +621,10 @@ class M1Server:
         if getattr(self, "h", None) is not None and self.h.value:
             lib().m1_server_free(self.h)
             self.h = ctypes.c_void_p()
+        # the callback refers back to this object (a cycle): drop it and the
+        # arena, so the arena's memory returns without waiting for the collector
+        self._cb = None
+        self.arena = None
 
     def __del__(self):
         try:
