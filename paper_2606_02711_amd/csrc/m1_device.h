@@ -133,11 +133,37 @@ struct Eddington {
 
 // Reciprocal, square root and reciprocal square root.  Float: the hardware's
 // 1-ulp instructions, used only on arguments that are normal numbers by
-// construction; double: IEEE operations.
+// construction.  Double reciprocal and square root: the hardware's
+// approximations refined by two Newton steps (quadratic convergence, so the
+// result is within about an ulp, though not correctly rounded), half the
+// instructions of the IEEE sequences, which also handle scaling and special
+// values that cannot occur here: the reciprocals are taken of normal numbers
+// (quantities >= 0.2, or energies above recip_floor) and the square root of
+// 4 - 3 f^2 in [1, 4].  The double reciprocal square root (rare branches
+// only) stays IEEE.
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ double frcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+// sqrt(a) = a / sqrt(a): Newton steps on g ~ sqrt(a) and h ~ 1 / (2 sqrt(a))
+// from the hardware's 1/sqrt(a), then a last correction of g by its residual.
+__device__ __forceinline__ double fsqrt(double a) {
+  const double y = __builtin_amdgcn_rsq(a);
+  double g = a * y, h = 0.5 * y;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  const double d = fma(-g, g, a);
+  return fma(d, h, g);
+}
 __device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double frsq(double x) { return 1.0 / sqrt(x); }
 

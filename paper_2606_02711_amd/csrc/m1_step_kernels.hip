@@ -667,7 +667,7 @@ struct FreqRow {
                                             ZW<R>* __restrict__ out) {
     const double s = (k == 0) ? 1.0 : 1.0 + b * r1;
     const double d = (k == 0) ? y : y + r2;
-    const double ip = 1.0 / (s + a_k);
+    const double ip = frcp(s + a_k);       // s + a_k >= 1
     const double z = d * ip;
     __builtin_nontemporal_store((R)z, &out->z);
     __builtin_nontemporal_store((R)(b_next * ip), &out->w);
