@@ -68,6 +68,20 @@ typedef enum { M1_BC_VACUUM = 0, M1_BC_REFLECT = 1 } m1_bc;
  * the level of the float storage. */
 typedef enum { M1_FP64 = 0, M1_FP32 = 1 } m1_prec;
 
+/* Interface flux of the advection step (Section 2.1).  M1_FLUX_GLF: the
+ * corrected GLF flux the paper adopts (HLL with signal speeds -c_tilde and
+ * +c_tilde, blended with the diffusion flux by eps(tau)).  M1_FLUX_HLL_EIG:
+ * the HLL flux the paper reports having tried (footnote to its choice of the
+ * GLF solver), with the extreme eigenvalues of the M1 system's flux Jacobian
+ * along the face normal as signal speeds (Davis estimates over the two face
+ * states; the paper gives no speeds, they are computed here from the
+ * Levermore closure) and the same eps blend: the HLL dissipation of the F
+ * flux scaled by eps, the whole E flux by eps plus (1 - eps) times the
+ * diffusion flux.  A comparison variant: single-grid stepping only, without
+ * active bins or substeps; batches, band grids and batched servers refuse it
+ * (M1_EUNSUPPORTED). */
+typedef enum { M1_FLUX_GLF = 0, M1_FLUX_HLL_EIG = 1 } m1_flux;
+
 typedef struct {
   int32_t geom;            /* m1_geom.  Cylindrical requires x0 == 0 with a
                               reflecting x- (axis) boundary. */
@@ -112,6 +126,7 @@ typedef struct {
                               over the step.  0 (the default): one substep.
                               Single-grid stepping only (batches refuse such
                               handles with M1_EUNSUPPORTED). */
+  int32_t flux;            /* an m1_flux value; M1_FLUX_GLF is the default */
 } m1_config;
 
 /* Per-cell physical inputs, FP64, [ny][nx].  Host pointers when on_device is
@@ -132,7 +147,8 @@ typedef struct {
 typedef struct m1_handle m1_handle;
 
 /* Fills *cfg with the paper's defaults (T_min 30 K, q 1.1, half-width 1e5,
- * CFL 0.4, recoil and Doppler on, FP64, fp64_tau +inf, vacuum boundaries). */
+ * CFL 0.4, recoil and Doppler on, FP64, fp64_tau +inf, vacuum boundaries,
+ * the GLF flux). */
 int32_t m1_default_config(m1_config *cfg);
 
 /* Number of frequency bins of cfg's grid (194 with the defaults; Section 2.1). */
@@ -229,7 +245,10 @@ int32_t m1_residuals(m1_handle *const *hs, int32_t n, double *resid);
  * below FLT_MIN are kept) and the reduced flux f = F/E in the state
  * precision: get forms F = f E in double (NULL outputs are skipped); set
  * stores f = F/E and drops the flux where E <= 0.  get is blocking; set is
- * asynchronous. */
+ * asynchronous.  FP32 handles store E times 2^scale_exp2, a scale fixed at
+ * init so that the first step's emission is of order one: a state set far
+ * below that scale (below ~1e-30 of it) falls into float subnormals and
+ * loses precision. */
 int32_t m1_get_state(m1_handle *h, double *d_E, double *d_Fx, double *d_Fy);
 int32_t m1_set_state(m1_handle *h, const double *d_E, const double *d_Fx,
                      const double *d_Fy);

@@ -147,6 +147,9 @@ def voigt_bin_average(grid, T):
 
 # --------------------------------------------------------------- the setup
 BC_CODE = {"vacuum": 0, "reflect": 1}
+# interface flux: the corrected GLF flux (the paper's), or HLL with the M1
+# signal speeds (the alternative the paper reports having tried)
+FLUX_CODE = {"glf": 0, "hll_eig": 1}
 
 
 def rt_time_step(p):
@@ -190,6 +193,7 @@ class OracleSetup:
         self.doppler = int(p.get("doppler", 1))
         self.active_frac = float(p.get("active_frac", 0.0))
         self.substep_rule = int(p.get("substep_rule", 0))
+        self.flux = FLUX_CODE[p.get("flux", "glf")]
 
 
 # ------------------------------------------------------------- the C core
@@ -205,7 +209,8 @@ class _Prob(ctypes.Structure):
                    ("substep_rule", ctypes.c_int), ("substeps", ctypes.c_void_p),
                    ("sub_margin", ctypes.c_void_p),
                    ("band", ctypes.c_int), ("kabs", ctypes.c_void_p),
-                   ("kflux", ctypes.c_void_p), ("jband", ctypes.c_void_p)])
+                   ("kflux", ctypes.c_void_p), ("jband", ctypes.c_void_p),
+                   ("flux", ctypes.c_int)])
 
 
 def build(force=False):
@@ -234,6 +239,8 @@ def lib():
         L.oracle_step.argtypes = [ctypes.POINTER(_Prob)] + [ctypes.c_void_p] * 7
         L.oracle_eddington.argtypes = [ctypes.c_double] * 3 + [ctypes.c_void_p]
         L.oracle_interface_rates.argtypes = [ctypes.c_double] * 6 + [ctypes.c_void_p]
+        L.oracle_signal_speeds.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                           ctypes.c_void_p]
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -279,6 +286,7 @@ class Oracle:
         self.active = np.ones(s.nb, dtype=np.int32)   # bins advected by the last step
         P.active = self.active.ctypes.data
         P.substep_rule = s.substep_rule
+        P.flux = s.flux
         self.substeps = np.ones((s.ny, s.nx), dtype=np.int32)   # accepted substeps per cell
         P.substeps = self.substeps.ctypes.data
         self.sub_margin = np.full((s.ny, s.nx), np.inf)        # closest call to the 10 % rule
@@ -386,6 +394,14 @@ class BandOracle:
 def eddington(E, Fx, Fy):
     out = np.zeros(4)
     lib().oracle_eddington(E, Fx, Fy, _ptr(out))
+    return out
+
+
+def signal_speeds(fx, fy, n):
+    """(lambda_min, lambda_max) of the M1 system across a face of normal n
+    (0: x, 1: y) for the reduced flux (fx, fy), in units of c_tilde."""
+    out = np.zeros(2)
+    lib().oracle_signal_speeds(float(fx), float(fy), int(n), _ptr(out))
     return out
 
 

@@ -88,6 +88,13 @@ typedef struct {
    * there is no frequency step (no frequency-derivative terms). */
   int band;
   const double *kabs, *kflux, *jband;
+  /* Interface flux: 0 the corrected GLF flux the paper adopts (HLL with
+   * signal speeds -c_tilde, +c_tilde); 1 the HLL flux with the extreme
+   * eigenvalues of the M1 system as signal speeds, which the paper reports
+   * having tried (Section 2.1, footnote on the GLF solver), with the same
+   * eps blend: eps times its dissipation in the F flux, eps times the whole
+   * flux plus (1 - eps) times the diffusion flux for E. */
+  int flux;
 } OracleProblem;
 
 /* ------------------------------------------------------------------------ */
@@ -111,6 +118,67 @@ static void eddington_tensor(double E, double Fx, double Fy,
   *Dyy = iso + dir * hy * hy;
   *Dxy = dir * hx * hy;
   *Dpp = iso;
+}
+
+/* Signal speeds of the M1 system across a face with normal n (0: x, 1: y),
+ * in units of the transport speed: the smallest and largest eigenvalues of
+ * the Jacobian of the face flux (F_n, P_nx, P_ny) with respect to
+ * (E, F_x, F_y), where P = D(f) E with the Levermore closure of reduced flux
+ * f = (fx, fy), |f| <= 1.  Write D = a(q) I + w(q) f (x) f with q = f^2,
+ * a = (1 - chi)/2 and w = (3 chi - 1)/(2 q) = 3 / (2 + sqrt(4 - 3 q)) (the
+ * second form follows from chi and stays finite at q = 0).  P is homogeneous
+ * of degree one in (E, F), so dP_nm/dE = D_nm - f . grad_f D_nm and
+ * dP_nm/dF_k = dD_nm/df_k.  The eigenvalues are the roots of the
+ * characteristic cubic (trace, principal minors, determinant), all real for
+ * this hyperbolic system, found in long double by the trigonometric method.
+ * Where |f| -> 1 the three roots merge at f . n and the cubic's roots lose
+ * accuracy like the cube root of the rounding. */
+static void signal_speeds(double fx_d, double fy_d, int n, double *lmin, double *lmax) {
+  long double f[2] = {fx_d, fy_d};
+  long double q = f[0] * f[0] + f[1] * f[1];
+  if (q > 1.0L) q = 1.0L;
+  long double s = sqrtl(4.0L - 3.0L * q);
+  long double chi = (3.0L + 4.0L * q) / (5.0L + 2.0L * s);
+  long double dchi = (4.0L * (5.0L + 2.0L * s) + 3.0L * (3.0L + 4.0L * q) / s) /
+                     ((5.0L + 2.0L * s) * (5.0L + 2.0L * s));       /* d chi / d q */
+  long double a = 0.5L * (1.0L - chi), da = -0.5L * dchi;
+  long double w = 3.0L / (2.0L + s), dw = 9.0L / (2.0L * s * (2.0L + s) * (2.0L + s));
+  long double J[3][3];
+  J[0][0] = 0.0L; J[0][1] = (n == 0); J[0][2] = (n == 1);
+  for (int m = 0; m < 2; ++m) {
+    long double Dnm = (n == m ? a : 0.0L) + w * f[n] * f[m];
+    long double dD[2];
+    for (int k = 0; k < 2; ++k)
+      dD[k] = 2.0L * f[k] * ((n == m ? da : 0.0L) + dw * f[n] * f[m]) +
+              w * ((n == k ? f[m] : 0.0L) + (m == k ? f[n] : 0.0L));
+    J[1 + m][0] = Dnm - f[0] * dD[0] - f[1] * dD[1];
+    J[1 + m][1] = dD[0];
+    J[1 + m][2] = dD[1];
+  }
+  /* lambda^3 + A lambda^2 + B lambda + C = 0 */
+  long double tr = J[0][0] + J[1][1] + J[2][2];
+  long double mi = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) +
+                   (J[0][0] * J[2][2] - J[0][2] * J[2][0]) +
+                   (J[1][1] * J[2][2] - J[1][2] * J[2][1]);
+  long double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                    J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                    J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+  long double A = -tr, B = mi, C = -det;
+  long double p = B - A * A / 3.0L;
+  long double r = 2.0L * A * A * A / 27.0L - A * B / 3.0L + C;
+  long double shift = -A / 3.0L;
+  if (p >= 0.0L) {                   /* a triple root (p = 0 up to rounding) */
+    *lmin = *lmax = (double)shift;
+    return;
+  }
+  long double m2 = 2.0L * sqrtl(-p / 3.0L);
+  long double arg = 3.0L * r / (p * m2);        /* cos(3 theta) */
+  if (arg > 1.0L) arg = 1.0L;
+  if (arg < -1.0L) arg = -1.0L;
+  long double th = acosl(arg) / 3.0L;
+  const long double two_pi_3 = 2.0943951023931954923084289221863353L;
+  *lmax = (double)(shift + m2 * cosl(th));
+  *lmin = (double)(shift + m2 * cosl(th - 2.0L * two_pi_3));
 }
 
 /* MinMod of two slopes (sign comparison, so products never underflow). */
@@ -303,7 +371,7 @@ typedef struct { double e, fx, fy; } Flux3;
 
 static Flux3 face_flux(const PadBin *B, const double *xcent, double xf,
                        size_t qLL, size_t qL, size_t qR, size_t qRR,
-                       int iL, int iR, int n, double u_n) {
+                       int iL, int iR, int n, double u_n, int flux) {
   /* centroid coordinates along the normal: xcent indexed by padded index */
   double xLL = xcent[iL - 1], xL = xcent[iL], xR = xcent[iR], xRR = xcent[iR + 1];
   const double *q[3] = {B->E, B->fx, B->fy};
@@ -339,9 +407,36 @@ static Flux3 face_flux(const PadBin *B, const double *xcent, double xf,
   double dcoef = tau / (3.0 * (0.2 + tau + tau * tau));
   double FnL = (n == 0) ? FxL : FyL, FnR = (n == 0) ? FxR : FyR;
   Flux3 r;
-  r.e = eps * (0.5 * (FnL + FnR) - 0.5 * (ER - EL)) - dcoef * (B->E[qR] - B->E[qL]);
-  r.fx = 0.5 * (PnxL + PnxR) - eps * 0.5 * (FxR - FxL);
-  r.fy = 0.5 * (PnyL + PnyR) - eps * 0.5 * (FyR - FyL);
+  if (flux == 1) {
+    /* HLL with the M1 signal speeds: the central part
+     * (sR G_L - sL G_R)/(sR - sL) and the dissipation sL sR (U_R - U_L)/(sR - sL),
+     * sL = min(0, lambda_min of both states), sR = max(0, lambda_max of both) */
+    double lminL, lmaxL, lminR, lmaxR;
+    signal_speeds(fxL, fyL, n, &lminL, &lmaxL);
+    signal_speeds(fxR, fyR, n, &lminR, &lmaxR);
+    double sL = lminL < lminR ? lminL : lminR, sR = lmaxL > lmaxR ? lmaxL : lmaxR;
+    if (sL > 0.0) sL = 0.0;
+    if (sR < 0.0) sR = 0.0;
+    double GL[3] = {FnL, PnxL, PnyL}, GR[3] = {FnR, PnxR, PnyR};
+    double UL[3] = {EL, FxL, FyL}, UR[3] = {ER, FxR, FyR};
+    double cen[3], dis[3];
+    for (int v = 0; v < 3; ++v) {
+      if (sR - sL > 0.0) {
+        cen[v] = (sR * GL[v] - sL * GR[v]) / (sR - sL);
+        dis[v] = sL * sR * (UR[v] - UL[v]) / (sR - sL);
+      } else {                     /* both speeds zero: no wave crosses the face */
+        cen[v] = 0.5 * (GL[v] + GR[v]);
+        dis[v] = 0.0;
+      }
+    }
+    r.e = eps * (cen[0] + dis[0]) - dcoef * (B->E[qR] - B->E[qL]);
+    r.fx = cen[1] + eps * dis[1];
+    r.fy = cen[2] + eps * dis[2];
+  } else {
+    r.e = eps * (0.5 * (FnL + FnR) - 0.5 * (ER - EL)) - dcoef * (B->E[qR] - B->E[qL]);
+    r.fx = 0.5 * (PnxL + PnxR) - eps * 0.5 * (FxR - FxL);
+    r.fy = 0.5 * (PnyL + PnyR) - eps * 0.5 * (FyR - FyL);
+  }
   /* upwind velocity advection with the reconstructed upstream state */
   double b = u_n / C_LIGHT;
   if (u_n > 0.0) { r.e += b * EL; r.fx += b * FxL; r.fy += b * FyL; }
@@ -422,7 +517,7 @@ static void advect_source_bin(const OracleProblem *P, const Geometry *G,
       size_t qL = (size_t)jp * px + iL, qR = qL + 1;
       double un = V->unx[(size_t)j * (nx + 1) + f];
       fxf[(size_t)j * (nx + 1) + f] =
-          face_flux(B, G->xcp, P->xe[f], qL - 1, qL, qR, qR + 1, iL, iR, 0, un);
+          face_flux(B, G->xcp, P->xe[f], qL - 1, qL, qR, qR + 1, iL, iR, 0, un, P->flux);
     }
   /* y-faces: jface = 0..ny between cells jface-1 and jface */
   for (int f = 0; f <= ny; ++f)
@@ -431,7 +526,7 @@ static void advect_source_bin(const OracleProblem *P, const Geometry *G,
       size_t qL = (size_t)jL * px + ip, qR = (size_t)jR * px + ip;
       double un = V->uny[(size_t)f * nx + i];
       fyf[(size_t)f * nx + i] =
-          face_flux(B, G->ycp, P->ye[f], qL - px, qL, qR, qR + px, jL, jR, 1, un);
+          face_flux(B, G->ycp, P->ye[f], qL - px, qL, qR, qR + px, jL, jR, 1, un, P->flux);
     }
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
@@ -755,6 +850,9 @@ int oracle_step(const OracleProblem *P, double *E, double *Fx, double *Fy,
 }
 
 /* Pieces exported for the oracle's own pin tests. */
+void oracle_signal_speeds(double fx, double fy, int n, double *out2) {
+  signal_speeds(fx, fy, n, &out2[0], &out2[1]);
+}
 void oracle_eddington(double E, double Fx, double Fy, double *out4) {
   eddington_tensor(E, Fx, Fy, &out4[0], &out4[1], &out4[2], &out4[3]);
 }

@@ -62,6 +62,9 @@ struct GridArgs {
   // energy-density floor of the rule in state units
   int substeps;
   double e_floor;
+  // interface flux: 0 corrected GLF (signal speeds -+c_tilde), 1 HLL with the
+  // M1 system's eigenvalue signal speeds
+  int flux;
   // broad bands (a grid of bands instead of line bins): per band and cell
   // [nb][ncell], absorption and flux opacities and the emission term L/c
   // (state units); nullptr for line grids

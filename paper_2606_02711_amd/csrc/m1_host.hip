@@ -230,6 +230,9 @@ int validate_config(const m1_config* c, int* nb_out) {
   if (!(c->active_frac >= 0.0) || !isfinite(c->active_frac))
     return fail(M1_EINVAL, "active_frac must be finite and >= 0");
   if (c->substep_rule != 0 && c->substep_rule != 1) return fail(M1_EINVAL, "substep_rule must be 0/1");
+  if (c->flux != M1_FLUX_GLF && c->flux != M1_FLUX_HLL_EIG) return fail(M1_EINVAL, "bad flux %d", c->flux);
+  if (c->flux == M1_FLUX_HLL_EIG && (c->active_frac != 0.0 || c->substep_rule))
+    return fail(M1_EUNSUPPORTED, "the eigenvalue HLL flux takes neither active bins nor substeps");
   FreqGrid g;
   int st = build_grid(*c, g);
   if (st) return st;
@@ -318,6 +321,7 @@ void fill_args(m1_handle* h, GridArgs<R>* a) {
     g.force = (double*)(w + L.force);
     g.active = c.active_frac > 0.0 ? (const int32_t*)(w + L.active) : nullptr;
     g.substeps = c.substep_rule;
+    g.flux = c.flux;
     g.kabs = g.kflux = g.jsrc = nullptr;
     // e_floor = 4 pi J_floor / c, J_floor = 1e-15 erg cm^-2 s^-1 sr^-1, in
     // the scaled state units
@@ -911,8 +915,9 @@ int32_t m1_band_init(const m1_config* cfg, int32_t n_band, const m1_band_fields*
   *out = nullptr;
   int st = validate_config(cfg, nullptr);
   if (st) return st;
-  if (cfg->active_frac != 0.0 || cfg->substep_rule)
-    return fail(M1_EUNSUPPORTED, "band grids take neither active bins nor the substep rule");
+  if (cfg->active_frac != 0.0 || cfg->substep_rule || cfg->flux != M1_FLUX_GLF)
+    return fail(M1_EUNSUPPORTED,
+                "band grids take neither active bins, the substep rule nor the eigenvalue HLL flux");
   if (n_band < 1 || n_band > kMaxBands) return fail(M1_EINVAL, "need 1 <= n_band <= %d", kMaxBands);
   if (!f) return fail(M1_EINVAL, "fields is NULL");
   const double* p[5] = {f->u_x, f->u_y, f->kappa_abs, f->kappa_flux, f->emis};
@@ -1165,6 +1170,8 @@ int check_members(m1_handle* const* hs, int n) {
     if (hs[q]->stream != hs[0]->stream) return fail(M1_EINVAL, "batch members must share a stream");
     if (hs[q]->cfg.substep_rule)
       return fail(M1_EUNSUPPORTED, "handle %d uses the substep rule: step it alone", q);
+    if (hs[q]->cfg.flux != M1_FLUX_GLF)
+      return fail(M1_EUNSUPPORTED, "handle %d uses the eigenvalue HLL flux: step it alone", q);
     if (hs[q]->band)
       return fail(M1_EUNSUPPORTED, "handle %d is a band grid: step it alone", q);
     for (int r = 0; r < q; ++r)

@@ -311,6 +311,8 @@ int32_t m1_server_submit(m1_server* s, const m1_config* cfg, int64_t n_temp_clas
   c.prec = s->c.prec;
   if (s->c.batched && c.substep_rule)
     return err(M1_EUNSUPPORTED, "the substep rule needs single-grid stepping (batched server)");
+  if (s->c.batched && c.flux != M1_FLUX_GLF)
+    return err(M1_EUNSUPPORTED, "the eigenvalue HLL flux needs single-grid stepping (batched server)");
   size_t ws = 0;
   int st = m1_workspace_bytes(&c, n_temp_classes, &ws);
   if (st) return st;

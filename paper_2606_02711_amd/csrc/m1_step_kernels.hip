@@ -34,12 +34,66 @@ struct Flux3 {
   R e, x, y;
 };
 
+// Signal speeds of the M1 system across a face, in units of c_tilde: the
+// smallest and largest eigenvalues of the Jacobian of the face flux
+// (F_n, P_nn, P_nt) with respect to (E, F_n, F_t), for the reduced flux of
+// normal and tangential components (fn, ft), |f| <= 1 (the eigenvalues do not
+// depend on the order of the flux components, so local face coordinates
+// serve both directions).  With D = iso I + g f (x) f (the Levermore closure
+// in the form of closure_f; q = f^2, s = sqrt(4 - 3 q), iso = (s - 1)/3,
+// g = 3/(2 + s), d iso/dq = -1/(2 s), dg/dq = 9/(2 s (2 + s)^2)) and P = D E
+// homogeneous of degree one, the Jacobian is
+//   [ 0    1    0  ]
+//   [ a1   b1   c1 ]   b1 = dD_nn/df_n, c1 = dD_nn/df_t, a1 = D_nn - fn b1 - ft c1,
+//   [ a2   b2   c2 ]   b2 = dD_nt/df_n, c2 = dD_nt/df_t, a2 = D_nt - fn b2 - ft c2,
+// whose characteristic polynomial is
+//   lambda^3 - (b1 + c2) lambda^2 + (b1 c2 - b2 c1 - a1) lambda + (a1 c2 - a2 c1).
+// Its three real roots (the system is hyperbolic) come from the
+// trigonometric solution of the depressed cubic, in double for either
+// storage precision.  As |f| -> 1 they merge at fn, and computed roots then
+// carry errors up to the cube root of the rounding.
+__device__ __forceinline__ void m1_signal_speeds(double fn, double ft, double& lo, double& hi) {
+  double q = fn * fn + ft * ft;
+  q = q < 1.0 ? q : 1.0;
+  const double s = fsqrt(4.0 - 3.0 * q);            // in [1, 2]
+  const double is = frcp(s), ip = frcp(2.0 + s);
+  const double iso = (s - 1.0) * (1.0 / 3.0), g = 3.0 * ip;
+  const double diso = -0.5 * is, dg = 4.5 * is * ip * ip;
+  const double fn2 = fn * fn, ft2 = ft * ft;
+  const double b1 = 2.0 * fn * (diso + dg * fn2 + g);
+  const double c1 = 2.0 * ft * (diso + dg * fn2);
+  const double b2 = ft * (2.0 * dg * fn2 + g);
+  const double c2 = fn * (2.0 * dg * ft2 + g);
+  const double a1 = (iso + g * fn2) - fn * b1 - ft * c1;
+  const double a2 = g * fn * ft - fn * b2 - ft * c2;
+  // lambda^3 + A lambda^2 + B lambda + C
+  const double A = -(b1 + c2), B = b1 * c2 - b2 * c1 - a1, C = a1 * c2 - a2 * c1;
+  const double p = B - A * A * (1.0 / 3.0);
+  const double r = A * A * A * (2.0 / 27.0) - A * B * (1.0 / 3.0) + C;
+  const double shift = -A * (1.0 / 3.0);
+  if (p >= 0.0) {                // a triple root (p = 0 up to rounding)
+    lo = hi = shift;
+    return;
+  }
+  const double m2 = 2.0 * sqrt(-p * (1.0 / 3.0));
+  double arg = 3.0 * r / (p * m2);                    // cos(3 theta)
+  arg = arg > 1.0 ? 1.0 : (arg < -1.0 ? -1.0 : arg);
+  const double th = acos(arg) * (1.0 / 3.0);
+  hi = shift + m2 * cos(th);
+  lo = shift + m2 * cos(th - 4.1887902047863909846);   // theta - 4 pi / 3
+}
+
 // Flux of (E, F_x, F_y) through one face with normal n (0: x, 1: y), from
 // the reconstructed states on its two sides (EL, fxL, fyL | ER, fxR, fyR),
 // the cell values eL, eR (diffusion term), the centroid distances
 // hL = x_f - c_L > 0 and hR = x_f - c_R < 0, the flux opacities of the two
 // cells and the face-normal velocity over c.
-template <typename R, int N>
+// EIG: HLL with the M1 signal speeds (m1_signal_speeds, Davis estimates over
+// the two states, clipped at zero) in place of -1, +1: the central part
+// (sR G_L - sL G_R)/(sR - sL) and the dissipation sL sR (U_R - U_L)/(sR - sL),
+// blended with eps as the GLF flux is; where both speeds are zero no wave
+// crosses the face and the flux is the mean of the two states' fluxes.
+template <typename R, int N, bool EIG = false>
 __device__ __forceinline__ Flux3<R> face_flux(R EL, R fxL, R fyL, R ER, R fxR, R fyR, R eL,
                                               R eR, R hL, R hR, R aFL, R aFR, R un_c) {
   // causality at the interface: |f| > 1 is scaled back to 1
@@ -60,9 +114,26 @@ __device__ __forceinline__ Flux3<R> face_flux(R EL, R fxL, R fyL, R ER, R fxR, R
   R dco = tau * inv * R(1.0 / 3.0);     // (1 - eps) / (3 tau)
   R FnL = (N == 0) ? FxL : FyL, FnR = (N == 0) ? FxR : FyR;
   Flux3<R> r;
-  r.e = eps * (R(0.5) * (FnL + FnR) - R(0.5) * (ER - EL)) - dco * (eR - eL);
-  r.x = R(0.5) * (PxL + PxR) - eps * R(0.5) * (FxR - FxL);
-  r.y = R(0.5) * (PyL + PyR) - eps * R(0.5) * (FyR - FyL);
+  if constexpr (EIG) {
+    double loL, hiL, loR, hiR;
+    m1_signal_speeds(N == 0 ? fxL : fyL, N == 0 ? fyL : fxL, loL, hiL);
+    m1_signal_speeds(N == 0 ? fxR : fyR, N == 0 ? fyR : fxR, loR, hiR);
+    double sl = fmin(fmin(loL, loR), 0.0), sr = fmax(fmax(hiL, hiR), 0.0);
+    R wl, wr, wd;                      // central weights and dissipation factor
+    if (sr - sl > 0.0) {
+      const double id = 1.0 / (sr - sl);
+      wl = (R)(sr * id); wr = (R)(-sl * id); wd = (R)(sl * sr * id);
+    } else {
+      wl = R(0.5); wr = R(0.5); wd = R(0);
+    }
+    r.e = eps * (wl * FnL + wr * FnR + wd * (ER - EL)) - dco * (eR - eL);
+    r.x = wl * PxL + wr * PxR + eps * wd * (FxR - FxL);
+    r.y = wl * PyL + wr * PyR + eps * wd * (FyR - FyL);
+  } else {
+    r.e = eps * (R(0.5) * (FnL + FnR) - R(0.5) * (ER - EL)) - dco * (eR - eL);
+    r.x = R(0.5) * (PxL + PxR) - eps * R(0.5) * (FxR - FxL);
+    r.y = R(0.5) * (PyL + PyR) - eps * R(0.5) * (FyR - FyL);
+  }
   // upwind advection by the face velocity with the upstream reconstruction
   const bool up = un_c > R(0);
   r.e += un_c * (up ? EL : ER);
@@ -162,7 +233,7 @@ constexpr int kFaceUnroll = EXTRA ? 1 : (sizeof(R) == 8 ? 2 : kRun);
 // columns c+1 and c+2; N = 1: tile column, faces between padded rows c+1 and
 // c+2).  MinMod slopes on centroid distances: each cell's slope and each
 // difference between neighbours is formed once and carried along the run.
-template <typename R, int N, int U>
+template <typename R, int N, int U, bool EIG = false>
 __device__ __forceinline__ void face_run(AdvShared<R>& S, int line, int c0, int c1) {
   auto ld = [&](int p, R& e, R& x, R& y) {
     if (N == 0) { e = S.E[line + 2][p]; x = S.fx[line + 2][p]; y = S.fy[line + 2][p]; }
@@ -193,7 +264,7 @@ __device__ __forceinline__ void face_run(AdvShared<R>& S, int line, int c0, int 
     int f;
     if (N == 0) { aFL = S.aF[line + 1][c]; aFR = S.aF[line + 1][c + 1]; f = line * (kTX + 1) + c; }
     else        { aFL = S.aF[c][line + 1]; aFR = S.aF[c + 1][line + 1]; f = kNXF + c * kTX + line; }
-    const Flux3<R> r = face_flux<R, N>(e1 + sE * hL, x1 + sX * hL, y1 + sY * hL,
+    const Flux3<R> r = face_flux<R, N, EIG>(e1 + sE * hL, x1 + sX * hL, y1 + sY * hL,
                                        e2 + tE * hR, x2 + tX * hR, y2 + tY * hR,
                                        e1, e2, hL, hR, aFL, aFR, S.un[f]);
     S.fle[f] = r.e; S.flx[f] = r.x; S.fly[f] = r.y;
@@ -281,7 +352,9 @@ struct BandSink {
 // BAND: the grid holds broad bands (Section 2.5): opacities and emission
 // come per band and cell from a.kflux, a.kabs, a.jsrc instead of the
 // per-cell line data and the class profiles.
-template <typename R, int BK, bool AB, bool SUB, class Sink, bool BAND = false>
+// EIG: the interface flux is HLL with the M1 signal speeds (a comparison
+// variant; one face per iteration).
+template <typename R, int BK, bool AB, bool SUB, class Sink, bool BAND = false, bool EIG = false>
 __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigned L,
                                              AdvShared<R>& S, Sink& sink) {
   static_assert(!(BAND && (AB || SUB)), "bands take neither active bins nor substeps");
@@ -480,16 +553,17 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
     // (2) every face of the tile once, in runs of four consecutive faces
     // along a line: waves 0-1 the x-faces (runs along rows), waves 2-3 the
     // y-faces (runs along columns); then the last face of each line.
+    constexpr int FU = kFaceUnroll<R, AB || SUB || EIG || Sink::kHeavy>;
     if (tid < 128) {
       const int r = tid / kRunsX, s = tid % kRunsX;
-      face_run<R, 0, kFaceUnroll<R, AB || SUB || Sink::kHeavy>>(S, r, s * kRun, s * kRun + kRun);
-      if (tid < kTY) face_run<R, 0, 1>(S, tid, kTX, kTX + 1);     // last face of row tid
+      face_run<R, 0, FU, EIG>(S, r, s * kRun, s * kRun + kRun);
+      if (tid < kTY) face_run<R, 0, 1, EIG>(S, tid, kTX, kTX + 1);   // last face of row tid
     } else {
       // a half-wave takes 32 neighbouring columns at one run position, so
       // its reads and flux writes fall in distinct banks
       const int u = tid - 128, c = u % kTX, s = u / kTX;
-      face_run<R, 1, kFaceUnroll<R, AB || SUB || Sink::kHeavy>>(S, c, s * kRun, s * kRun + kRun);
-      if (u < kTX) face_run<R, 1, 1>(S, u, kTY, kTY + 1);         // last face of column u
+      face_run<R, 1, FU, EIG>(S, c, s * kRun, s * kRun + kRun);
+      if (u < kTX) face_run<R, 1, 1, EIG>(S, u, kTY, kTY + 1);       // last face of column u
     }
     __syncthreads();
     // (3) update, causality clamp, implicit source
@@ -536,12 +610,12 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
 template <typename R>
 constexpr int kAdvectWaves = sizeof(R) == 4 ? 4 : 1;
 
-template <typename R, int BK, bool AB, bool SUB>
+template <typename R, int BK, bool AB, bool SUB, bool EIG = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kAdvectWaves<R>)))
 void k_advect_source(GridArgs<R> a) {
   __shared__ AdvShared<R> S;
   WriteSink<R> sink;
-  advect_block<R, BK, AB, SUB>(a, xcd_logical_block(), S, sink);
+  advect_block<R, BK, AB, SUB, WriteSink<R>, false, EIG>(a, xcd_logical_block(), S, sink);
 }
 
 // The step of a grid of broad bands (Section 2.5): a block per tile walks
@@ -1431,6 +1505,10 @@ hipError_t launch_advect(const GridArgs<R>& a, hipStream_t s) {
   const unsigned nbx = (a.nx + kTX - 1) / kTX, nby = (a.ny + kTY - 1) / kTY;
   const unsigned nbz = (a.nb + kBK - 1) / kBK;
   const dim3 g(nbx * nby * nbz), b(256);
+  if (a.flux) {                      // the eigenvalue HLL flux (no runtime controls)
+    hipLaunchKernelGGL((k_advect_source<R, kBK, false, false, true>), g, b, 0, s, a);
+    return hipGetLastError();
+  }
   if (!a.substeps && !a.active && g.x < kFewBlocks) {
     const unsigned n14 = nbx * nby * ((a.nb + 13) / 14), n7 = nbx * nby * ((a.nb + 6) / 7);
     if (n14 >= kRoundsBlocks)

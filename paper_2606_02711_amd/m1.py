@@ -40,7 +40,8 @@ class m1_config(ctypes.Structure):
                 ("c_tilde", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("recoil", ctypes.c_int32), ("doppler", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("fp64_tau", ctypes.c_double),
-                ("active_frac", ctypes.c_double), ("substep_rule", ctypes.c_int32)]
+                ("active_frac", ctypes.c_double), ("substep_rule", ctypes.c_int32),
+                ("flux", ctypes.c_int32)]
 
 
 class m1_fields(ctypes.Structure):
@@ -158,6 +159,7 @@ def check(code):
 
 # ----------------------------------------------------------------- config
 BC = {"vacuum": M1_BC_VACUUM, "reflect": M1_BC_REFLECT}
+FLUX = {"glf": 0, "hll_eig": 1}          # m1_flux
 
 
 def make_config(p, prec="fp64", fp64_tau=float("inf")):
@@ -175,6 +177,7 @@ def make_config(p, prec="fp64", fp64_tau=float("inf")):
     c.fp64_tau = float(fp64_tau)
     c.active_frac = float(p.get("active_frac", 0.0))
     c.substep_rule = int(p.get("substep_rule", 0))
+    c.flux = FLUX[p.get("flux", "glf")]
     return c
 
 

@@ -160,6 +160,10 @@ def test_server_bookkeeping_without_device_work():
     cfg = m1.make_config(dict(small, substep_rule=1), "fp32")
     assert L.m1_server_submit(h, ctypes.byref(cfg), 1, 1e-6, 100, ctypes.byref(rid)) == \
         m1.M1_EUNSUPPORTED
+    # ... and the eigenvalue HLL flux
+    cfg = m1.make_config(dict(small, flux="hll_eig"), "fp32")
+    assert L.m1_server_submit(h, ctypes.byref(cfg), 1, 1e-6, 100, ctypes.byref(rid)) == \
+        m1.M1_EUNSUPPORTED
     m1.check(L.m1_server_stats(h, *(ctypes.byref(x) for x in (q, r, f, rounds, used, largest))))
     assert q.value == 2                      # nothing queued
     m1.check(L.m1_server_free(h))
@@ -174,6 +178,29 @@ def test_empty_and_oversized_grids_rejected(nx, ny, code):
     b = ctypes.c_size_t()
     assert m1.lib().m1_workspace_bytes(ctypes.byref(c), 1, ctypes.byref(b)) == code
     assert len(m1.lib().m1_last_error()) > 0
+
+
+def test_flux_field_validated():
+    """m1_config.flux: 0 (GLF) or 1 (eigenvalue HLL); the HLL variant refuses
+    the runtime controls and band grids, before any device work."""
+    p = inputs.config1()
+    b = ctypes.c_size_t()
+    c = m1.make_config(dict(p, flux="hll_eig"), "fp32")
+    assert c.flux == 1
+    m1.check(m1.lib().m1_workspace_bytes(ctypes.byref(c), 1, ctypes.byref(b)))
+    d = m1.m1_config()
+    m1.check(m1.lib().m1_default_config(ctypes.byref(d)))
+    assert d.flux == 0
+    c.flux = 2
+    assert m1.lib().m1_workspace_bytes(ctypes.byref(c), 1, ctypes.byref(b)) == m1.M1_EINVAL
+    for extra in (dict(active_frac=1e-10), dict(substep_rule=1)):
+        c = m1.make_config(dict(p, flux="hll_eig", **extra), "fp32")
+        assert m1.lib().m1_workspace_bytes(ctypes.byref(c), 1, ctypes.byref(b)) == \
+            m1.M1_EUNSUPPORTED
+    pb = inputs.band_random_small("cart", 8, 8, 1, n_band=2)
+    cb = m1.make_band_config(pb, "fp32")
+    cb.flux = 1
+    assert _band_init_code(pb, cfg=cb) == m1.M1_EUNSUPPORTED
 
 
 def test_empty_batch_rejected():

@@ -519,11 +519,13 @@ def test_frequency_stage_matches_dense_solve_on_8x8():
     assert worst < 1e-11, worst
 
 
-def _brute_force_transport(p, o, E, Fx, Fy):
+def _brute_force_transport(p, o, E, Fx, Fy, flux="glf"):
     """E**, F** of one step written out cell by cell from Section 2.1 (velocity
     zero): ghost cells, MinMod slopes on centroid distances, Levermore closure
     in its chi form, GLF flux blended with the diffusion flux by eps, update,
-    cylindrical hoop term, causality, implicit source."""
+    cylindrical hoop term, causality, implicit source.  flux="hll_eig": the
+    HLL flux with the M1 signal speeds (M.signal_speeds, pinned on its own in
+    test_oracle_hll_pins) in place of the GLF flux, blended the same way."""
     s = o.s
     nx, ny, nb = s.nx, s.ny, s.nb
     cyl = p["geom"] == "cyl"
@@ -631,14 +633,28 @@ def _brute_force_transport(p, o, E, Fx, Fy):
         one_m_eps = tau * tau / (0.2 + tau + tau * tau)       # 1 - eps without cancellation
         FL = (fxL * EL, fyL * EL)
         FR = (fxR * ER, fyR * ER)
-        fe = eps * (0.5 * (FL[d] + FR[d]) - 0.5 * (ER - EL))
-        if tau > 0:
-            fe -= one_m_eps * (eR - eL) / (3 * tau)
         # row d of D E
         PL = (DL[0] * EL, DL[2] * EL) if d == 0 else (DL[2] * EL, DL[1] * EL)
         PR = (DR[0] * ER, DR[2] * ER) if d == 0 else (DR[2] * ER, DR[1] * ER)
-        fxx = 0.5 * (PL[0] + PR[0]) - eps * 0.5 * (FR[0] - FL[0])
-        fyy = 0.5 * (PL[1] + PR[1]) - eps * 0.5 * (FR[1] - FL[1])
+        if flux == "glf":              # HLL with speeds -1, +1
+            sl, sr = -1.0, 1.0
+        else:
+            lL, hL_ = M.signal_speeds(fxL, fyL, d)
+            lR, hR_ = M.signal_speeds(fxR, fyR, d)
+            sl, sr = min(lL, lR, 0.0), max(hL_, hR_, 0.0)
+        GL, GR = (FL[d], PL[0], PL[1]), (FR[d], PR[0], PR[1])
+        UL, UR = (EL, FL[0], FL[1]), (ER, FR[0], FR[1])
+        if sr - sl > 0:
+            cen = [(sr * GL[q] - sl * GR[q]) / (sr - sl) for q in range(3)]
+            dis = [sl * sr * (UR[q] - UL[q]) / (sr - sl) for q in range(3)]
+        else:
+            cen = [0.5 * (GL[q] + GR[q]) for q in range(3)]
+            dis = [0.0, 0.0, 0.0]
+        fe = eps * (cen[0] + dis[0])
+        if tau > 0:
+            fe -= one_m_eps * (eR - eL) / (3 * tau)
+        fxx = cen[1] + eps * dis[1]
+        fyy = cen[2] + eps * dis[2]
         return fe, fxx, fyy
 
     Es = np.zeros_like(E)
@@ -688,21 +704,26 @@ def _brute_force_transport(p, o, E, Fx, Fy):
 @pytest.mark.parametrize("geom,bc", [("cart", ("vacuum",) * 4),
                                      ("cyl", ("reflect", "vacuum", "reflect", "vacuum")),
                                      ("cart", ("reflect", "vacuum", "vacuum", "reflect"))])
-def test_transport_stage_matches_brute_force_on_8x8(geom, bc):
+@pytest.mark.parametrize("flux", ["glf", "hll_eig"])
+def test_transport_stage_matches_brute_force_on_8x8(geom, bc, flux):
     p = inputs.random_small(geom, 8, 8, 31, with_velocity=False, half_width=30.0,
                             log_nHI=(-4.0, -1.0), bc=bc)
+    p["flux"] = flux
     o = M.Oracle(p)
     s = o.s
     rng = np.random.default_rng(9)
     shape = (s.nb, s.ny, s.nx)
     E0 = rng.uniform(0.1, 1.0, shape)
     ang = rng.uniform(0, 2 * np.pi, shape)
-    fr = rng.uniform(0.0, 0.99, shape)
+    # the M1 signal speeds merge as |f| -> 1, where they depend on f like a
+    # cube root: |f| <= 0.6 keeps every reconstructed face state (component-
+    # wise MinMod: |f| <= 0.6 sqrt 2) where the speeds are well conditioned
+    fr = rng.uniform(0.0, 0.99 if flux == "glf" else 0.6, shape)
     X0, Y0 = E0 * fr * np.cos(ang), E0 * fr * np.sin(ang)
     o.set_state(E0, X0, Y0)
     o.step(1)
     Ess, Xss, Yss = o.post_source_state()
-    Eb, Xb, Yb = _brute_force_transport(p, o, E0, X0, Y0)
+    Eb, Xb, Yb = _brute_force_transport(p, o, E0, X0, Y0, flux)
     for a, b in ((Ess, Eb), (Xss, Xb), (Yss, Yb)):
         assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b)), np.max(np.abs(a - b))
 
