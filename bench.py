@@ -503,6 +503,9 @@ def main():
                     help="run only the active-bin workload")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the 64-grid batch workload (profiling)")
+    ap.add_argument("--profile", action="store_true",
+                    help="only the FP32 (and, without --no-fp64, FP64) path on the 512 x 1024 "
+                         "workload from the developed state (for counter runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--fp64-tau", type=float, default=float("inf"),
@@ -543,6 +546,18 @@ def main():
     if args.active_only:
         print(json.dumps({"active_bins": run_active(inputs.config3(), args.active_steps, 100),
                           "substeps": run_substeps(args.substep_steps)}), flush=True)
+        return
+    if args.profile:
+        from paper_2606_02711_amd import m1
+        p = inputs.config2()
+        g = m1.M1Grid(p, prec="fp32")          # its time step sets the state's scale
+        state = inputs.filled_state(p, g.nb, e_peak(p, g.dt), seed=2)
+        g.free()
+        del g
+        out = {"profile": {"fp32": run_path(p, "fp32", args.steps, args.warmup, state=state)}}
+        if not args.no_fp64:
+            out["profile"]["fp64"] = run_path(p, "fp64", args.steps, args.warmup, state=state)
+        print(json.dumps(out), flush=True)
         return
     copy_gbs = copy_bandwidth()
     log(f"[bench] device copy: {copy_gbs:.0f} GB/s")

@@ -100,8 +100,8 @@ typedef struct {
                               which a cell's frequency-step coefficients are
                               computed in double (+inf: none, the default;
                               0: all cells) */
-  double active_frac;      /* active-bin advection (Section 2.1, runtime
-                              controls; the paper uses 1e-10): at the start of
+  double active_frac;      /* active-bin advection (Section 2.2; the paper
+                              uses 1e-10): at the start of
                               every step bin k's energy in the volume,
                               W_k = dnu_k sum_cells dV E_k, is summed in double,
                               and only bins with W_k > active_frac sum_k W_k
@@ -200,15 +200,30 @@ int32_t m1_dynamic_c_tilde_noalloc(const m1_config *cfg, const m1_fields *fields
 
 /* Validates cfg and fields, lays out the caller-owned workspace d_ws of
  * ws_bytes (>= m1_workspace_bytes for the field's class count, 256-byte
- * aligned), runs the set-up kernels (frequency grid, bin-averaged Voigt
- * profile, opacities, velocity gradients, CFL time step) on `stream`
- * (a hipStream_t; NULL = default stream) and sets E = F = 0.  Synchronous.
- * On success *out receives a new handle. */
+ * aligned), runs the set-up kernels on `stream` (a hipStream_t; NULL =
+ * default stream) and sets E = F = 0.  Synchronous.  On success *out
+ * receives a new handle.  The set-up follows the paper: the frequency grid
+ * of Section 2.1 (bins geometric in nu - nu_Lya from dnu_D(T_min)); the
+ * bin-averaged Voigt profile <H>_k of Appendix A (second-order expansion in
+ * a_v, evaluated exactly, no look-up table) per temperature class; the line
+ * opacity alpha = n_HI sigma_0(T), the flux opacity alpha_F,k = alpha <H>_k +
+ * alpha_c (1 - omega g) and the absorption alpha_c (1 - omega) + p_d alpha
+ * <H>_k of Section 2.1 (steps 1 and 2); the emission profile <H>_k / sqrt(pi)
+ * normalised over the grid; the velocity gradients of Appendix A (D : grad u
+ * terms); the CFL time step of Section 2.1. */
 int32_t m1_init(const m1_config *cfg, const m1_fields *fields, void *d_ws,
                 size_t ws_bytes, void *stream, m1_handle **out);
 
-/* Enqueues nsteps RT steps (advection + emission/absorption, force, frequency
- * step).  *t_now (may be NULL) receives the simulated time after them. */
+/* Enqueues nsteps RT steps, each the three operator-split stages of Section
+ * 2.1: (1) the explicit advection step (MinMod reconstruction of E and f,
+ * Levermore closure, corrected GLF flux with the eps(tau) blend, upwind
+ * velocity advection, radiation-pressure work term, hoop pressure in (R, z),
+ * causality clamp), (2) the implicit emission/absorption/destruction step
+ * (BDF1), with the force density of Section 2.3 formed from its result, and
+ * (3) the implicit frequency step of Appendix A (exponential-scheme leakage
+ * coefficients, tridiagonal BDF1 solve per cell, H rescaled by
+ * J_new / J_old).  *t_now (may be NULL) receives the simulated time after
+ * them.  Asynchronous on the handle's stream; M1_ESTATE after a device error. */
 int32_t m1_step(m1_handle *h, int32_t nsteps, double *t_now);
 
 /* Measurement variant of m1_step: records HIP events around every kernel
@@ -218,15 +233,22 @@ int32_t m1_step(m1_handle *h, int32_t nsteps, double *t_now);
  * m1_step; the events add only launch overhead. */
 int32_t m1_step_profiled(m1_handle *h, int32_t nsteps, double *ms);
 
-/* Enqueues a copy of the radiation force density of the last step into
- * caller device arrays of ncell doubles [dyn cm^-3]: total (x, y) and the gas
- * share (line opacity part; may be NULL).  Asynchronous. */
+/* Enqueues a copy of the radiation force density of the last step (Section
+ * 2.3: the momentum the radiation gives the gas and dust per unit volume,
+ * sum_k dnu_k alpha_F,k F**_k in the state variables, equal to the paper's
+ * form in the change of H over the absorption step) into caller device
+ * arrays of ncell doubles [dyn cm^-3]: total (x, y) and the gas share (the
+ * line opacity's part, the paper's eps_gas split; may be NULL).
+ * Asynchronous. */
 int32_t m1_force(m1_handle *h, double *d_fx, double *d_fy, double *d_fx_gas,
                  double *d_fy_gas);
 
 /* Steps until r = ||E^{n+1} - E^n||_2 / ||E^{n+1}||_2 (all cells and bins,
  * FP64 sums) is below rel_tol, checking every check_every steps, or until
- * max_steps steps were taken by this call (then M1_ENOTCONV).  Blocking. */
+ * max_steps steps were taken by this call (then M1_ENOTCONV).  Blocking.
+ * The paper runs its test clouds to a fixed time and reads results once they
+ * have settled (Sections 3.1 and 3.3); this steady-state criterion is the
+ * library's own stopping rule for the same solutions. */
 int32_t m1_solve_steady(m1_handle *h, double rel_tol, int64_t max_steps,
                         int32_t check_every, int64_t *steps_done, double *resid);
 
@@ -271,7 +293,7 @@ int32_t m1_get_state_region(m1_handle *h, int32_t i0, int32_t i1, int32_t j0, in
  * error. */
 int32_t m1_set_c_tilde(m1_handle *h, double c_tilde);
 
-/* Which bins the last step advected (Section 2.1, runtime controls):
+/* Which bins the last step advected (Section 2.2, active bins):
  * flags_host[k] = 1 for an advected bin, 0 otherwise (N_nu int32 entries;
  * may be NULL), *n_active (may be NULL) their count.  With active_frac = 0
  * every bin is reported active; before the first step, none is.  Blocking

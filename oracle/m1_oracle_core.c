@@ -16,7 +16,7 @@
  * Layout of every per-bin array: [k][j][i], cell index c = j*nx + i.
  *
  * One call of oracle_step() advances n -> n+1:
- *   (0) optional active-bin selection (Section 2.1, runtime controls): with
+ *   (0) optional active-bin selection (Section 2.2, active bins): with
  *       active_frac > 0 only bins holding more than that fraction of the
  *       total Lyman-alpha energy in the volume are advected in (1);
  *   (1) advection step per bin (Section 2.1, step 1): MinMod-limited linear
@@ -69,8 +69,8 @@ typedef struct {
   const double *hbar;        /* bin-averaged Voigt <H>_k per class [ncls][nb] */
   const double *phi;         /* bin-averaged emission profile per class [ncls][nb] */
   double active_frac;        /* 0: advect every bin; > 0: only bins whose energy
-                                exceeds this fraction of the total (Section 2.1,
-                                runtime controls) */
+                                exceeds this fraction of the total (Section 2.2,
+                                active bins) */
   int *active;               /* [nb] out: 1 where bin k was advected this step */
   int substep_rule;          /* 1: emission/absorption in substeps under the
                                 10 % energy rule (Section 2.1, step 2) */
@@ -655,7 +655,7 @@ static void frequency_step_cell(const OracleProblem *P, const VelData *V, int i,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Active bins (Section 2.1, runtime controls): the energy of bin k in the
+/* Active bins (Section 2.2, active bins): the energy of bin k in the
  * volume is W_k = dnu_k sum_cells dV E_k (E = 4 pi J / c; constant factors
  * cancel in the ratio), and bin k is advected when W_k > active_frac sum_k W_k.
  * An empty state advects no bin. */

@@ -1555,7 +1555,7 @@ hipError_t launch_freq(const GridArgs<R>& a, hipStream_t s) {
 }
 
 // ------------------------------------------------------------ active bins
-// Section 2.1, runtime controls: bin k is advected when its energy in the
+// Section 2.2 (active bins): bin k is advected when its energy in the
 // volume, W_k = dnu_k sum_c dV_c E_k,c, exceeds active_frac sum_k W_k.  The
 // sums are double and deterministic: fixed partial sums of kEnergyCells
 // cells per block (k_bin_energy), then one block adds them in order and sets

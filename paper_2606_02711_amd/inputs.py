@@ -217,7 +217,7 @@ def uniform_cloud(geom, n, log10_NHI, T, dust_solar, L_box=PC, steps=500, fields
 
 def cone_cloud(n=256, R_cl=PC, tau_cl=1.0e8, tau_cone=1.0e5, T=1.0e4, mu_cone=2 ** -0.5,
                dmu=0.025):
-    """Anisotropic-escape cloud of Section 4 (Test 6): a spherical cloud of
+    """Anisotropic-escape cloud of Section 3.2 (Test 6): a spherical cloud of
     radius R_cl at T with a bipolar low-density cone (half-opening angle
     acos(mu_cone), tanh transition of width dmu in mu = |Z|/r), neutral
     fraction 1 in the shell 0.5 R_cl < r <= R_cl and 1e-4 inside, uniform
@@ -246,7 +246,7 @@ def cone_cloud(n=256, R_cl=PC, tau_cl=1.0e8, tau_cone=1.0e5, T=1.0e4, mu_cone=2 
 
 
 def static_sphere(n=64, R_cl=PC, tau_cl=1.0e6, T=1.0e4, tau_c=0.0, v_exp=0.0):
-    """Uniform cloud of Section 4 (Tests 1, 2, 4 and 5): a uniform sphere of
+    """Uniform cloud of Section 3.1 (Tests 1, 2, 4 and 5): a uniform sphere of
     radius R_cl at T with line-centre depth tau_cl = n_HI sigma0(T) R_cl and
     uniform emission (1 erg/s in the box), vacuum outside; box
     [0, 1.1 R_cl]^2 in (R, Z) with reflecting axis and midplane, outflow at the

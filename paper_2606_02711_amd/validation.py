@@ -1,4 +1,4 @@
-"""Force multipliers of a run (Section 4): M_F = (c/L) int dV |f| and
+"""Force multipliers of a run (Sections 3.1 and 3.2): M_F = (c/L) int dV |f| and
 M_F,radial = (c/L) int dV f . r_hat, r_hat from the cloud centre at the
 origin, and the static-cloud (Test 1) and anisotropic-escape (Test 6) runs on
 the GPU."""
@@ -56,7 +56,7 @@ def run_cone(n=256, prec="fp32", t_max=None, log=None, checkpoints=4, problem=No
 
 
 def energy_budget(p, g):
-    """Steady-state energy budget of a grid g of problem p (Section 4, the
+    """Steady-state energy budget of a grid g of problem p (Section 3.1, the
     escape-fraction test), over the emitted luminosity: (absorbed, escaped
     lower, escaped upper).  Absorbed: c alpha_abs int E dnu over the volume
     (alpha_abs the continuum absorption coefficient; no destruction).

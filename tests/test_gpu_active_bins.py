@@ -1,4 +1,4 @@
-"""GPU parity of active-bin advection (Section 2.1, runtime controls).
+"""GPU parity of active-bin advection (Section 2.2, active bins).
 
 Bin k is advected when its energy in the volume, dnu_k sum_cells dV E_k,
 exceeds active_frac times the total; the others keep their state through the

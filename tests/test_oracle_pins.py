@@ -403,7 +403,7 @@ def test_diffusion_rate_scales_as_inverse_opacity():
 # ------------------------------------------- thin sphere force multiplier
 def test_thin_sphere_force_multiplier():
     """Uniform emission in a thin uniform sphere: M_F -> tau eta / 4 with
-    eta = int H phi dnu -> 1/sqrt(2) (Section 4, Test 1 thin limit)."""
+    eta = int H phi dnu -> 1/sqrt(2) (Section 3.1, Test 1 thin limit)."""
     n, Rcl, T, tau = 32, 1.0, 1.0e4, 0.02
     dx = 1.1 * Rcl / n
     p = make_problem("cyl", n, n, dx, ("reflect", "vacuum", "reflect", "vacuum"),
@@ -728,7 +728,7 @@ def test_transport_stage_matches_brute_force_on_8x8(geom, bc, flux):
         assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b)), np.max(np.abs(a - b))
 
 
-# ------------------------------------------- active bins (runtime controls)
+# ------------------------------------------- active bins (Section 2.2)
 def _active_after_one_step(p, E, Fx=None, Fy=None):
     o = M.Oracle(p)
     z = np.zeros_like(E)
@@ -740,7 +740,7 @@ def _active_after_one_step(p, E, Fx=None, Fy=None):
 def test_active_bins_shares_of_uniform_state():
     """Spatially uniform E_k = a_k: bin k's share of the energy is
     a_k dnu_k / sum_j a_j dnu_j whatever the geometry, so the advected set is
-    fixed in closed form by the bin widths (Section 2.1, runtime controls)."""
+    fixed in closed form by the bin widths (Section 2.2, active bins)."""
     for geom, bc in (("cart", ("vacuum",) * 4), ("cyl", ("reflect", "vacuum", "vacuum", "vacuum"))):
         p = make_problem(geom, 6, 5, 1.0e15, bc, half_width=2.0e2)
         nb = M.frequency_grid(half_width=2.0e2)["nb"]
