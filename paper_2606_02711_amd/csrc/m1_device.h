@@ -170,11 +170,17 @@ __device__ __forceinline__ double fsqrt(double a) {
 __device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double frsq(double x) { return 1.0 / sqrt(x); }
 
+// min(q, 1) for q >= 0: one v_med3_f32 in float (median of q, 1 and 0), where
+// fmin would also canonicalise its argument.
+__device__ __forceinline__ float clamp_unit(float q) {
+  return __builtin_amdgcn_fmed3f(q, 1.0f, 0.0f);
+}
+__device__ __forceinline__ double clamp_unit(double q) { return fmin(q, 1.0); }
+
 template <typename R>
 __device__ __forceinline__ Eddington<R> closure_f(R fx, R fy) {
   const R xx2 = fx * fx, yy2 = fy * fy;
-  R f2 = xx2 + yy2;
-  f2 = fmin(f2, R(1));
+  const R f2 = clamp_unit(xx2 + yy2);
   const R s = fsqrt(R(4) - R(3) * f2);    // in [1, 2]
   const R g = R(3) * frcp(R(2) + s);
   const R iso = (s - R(1)) * R(1.0 / 3.0);
@@ -192,6 +198,24 @@ __device__ __forceinline__ Eddington<R> closure_f(R fx, R fy) {
 template <typename R>
 __device__ __forceinline__ R recip_floor() {
   return sizeof(R) == 4 ? R(7.52316384526264e-37) : R(9.332636185032189e-302);
+}
+
+// The parts of the closure a face and a cell update need, from the squares
+// of the components of a reduced flux with |f| <= 1 (f2 = fx^2 + fy^2):
+// s = sqrt(4 - 3 f2), g = 3/(2 + s) formed as 1/(s/3 + 2/3) (one fused
+// multiply-add and a reciprocal), iso = (s - 1)/3.  Then
+// D = iso I + g f (x) f, D_phiphi = iso.
+template <typename R>
+struct ClosureParts {
+  R s, g, iso;
+};
+template <typename R>
+__device__ __forceinline__ ClosureParts<R> closure_parts(R f2) {
+  ClosureParts<R> c;
+  c.s = fsqrt(R(4) - R(3) * clamp_unit(f2));
+  c.g = frcp(c.s * R(1.0 / 3.0) + R(2.0 / 3.0));
+  c.iso = (c.s - R(1)) * R(1.0 / 3.0);
+  return c;
 }
 
 // Reduced flux f = F/E (0 where E <= 0).
@@ -218,7 +242,10 @@ __device__ __forceinline__ Eddington<R> closure_reduced(R fx, R fy) {
 // Scale s in (0, 1] with |s F| <= E for E > 0 (the causality condition
 // |H|/J <= 1).  The squares of tiny components underflow in float below
 // ~1e-19 (and in double below ~1e-154), which would hide a violation, so
-// small E is checked in double (float) or after scaling by 2^400 (double).
+// small E is checked after an exact rescaling: in float by the power of two
+// that brings the largest of E, |X|, |Y| into [1/2, 1) (the squares of the
+// rescaled values cannot overflow, and one that underflows is negligible
+// against the largest), in double by 2^400.
 template <typename R>
 __device__ __forceinline__ R causal_scale(R E, R X, R Y) {
   const R tiny = sizeof(R) == 4 ? R(1e-18) : R(1e-150);
@@ -228,10 +255,18 @@ __device__ __forceinline__ R causal_scale(R E, R X, R Y) {
     if (q2 > E * E) sc = E * frsq(q2);      // rare: branch, not select
     return sc;
   }
-  const double sc = sizeof(R) == 4 ? 1.0 : 0x1p400;
-  const double e = (double)E * sc, x = (double)X * sc, y = (double)Y * sc;
-  const double q2 = x * x + y * y;
-  return q2 > e * e ? (R)(e / sqrt(q2)) : R(1);
+  if constexpr (sizeof(R) == 4) {
+    const float m = fmaxf(E, fmaxf(fabsf(X), fabsf(Y)));
+    const int ex = __builtin_amdgcn_frexp_expf(m);
+    const float e = __builtin_ldexpf(E, -ex), x = __builtin_ldexpf(X, -ex),
+                y = __builtin_ldexpf(Y, -ex);
+    const float q2 = x * x + y * y;
+    return q2 > e * e ? e * frsq(q2) : 1.0f;
+  } else {
+    const double e = E * 0x1p400, x = X * 0x1p400, y = Y * 0x1p400;
+    const double q2 = x * x + y * y;
+    return q2 > e * e ? e / sqrt(q2) : 1.0;
+  }
 }
 
 // MinMod limiter: the argument of smaller magnitude when a and b share a

@@ -85,36 +85,63 @@ __device__ __forceinline__ void m1_signal_speeds(double fn, double ft, double& l
 
 // Flux of (E, F_x, F_y) through one face with normal n (0: x, 1: y), from
 // the reconstructed states on its two sides (EL, fxL, fyL | ER, fxR, fyR),
-// the cell values eL, eR (diffusion term), the centroid distances
-// hL = x_f - c_L > 0 and hR = x_f - c_R < 0, the flux opacities of the two
-// cells and the face-normal velocity over c.
+// the difference of the cell values dEc = e_R - e_L (diffusion term), the
+// centroid distances hL = x_f - c_L > 0 and hR = x_f - c_R < 0, the flux
+// opacities of the two cells and the face-normal velocity over c.
+// The GLF flux is formed from half the pressure rows and half of eps (both
+// exact halvings):  F_E = (eps/2) (F_nL + F_nR - (E_R - E_L)) - dco dEc,
+// F_F = (P_L + P_R)/2 - (eps/2) (F_R - F_L).
 // EIG: HLL with the M1 signal speeds (m1_signal_speeds, Davis estimates over
 // the two states, clipped at zero) in place of -1, +1: the central part
 // (sR G_L - sL G_R)/(sR - sL) and the dissipation sL sR (U_R - U_L)/(sR - sL),
 // blended with eps as the GLF flux is; where both speeds are zero no wave
 // crosses the face and the flux is the mean of the two states' fluxes.
+template <typename R>
+struct FaceSide {
+  R Fx, Fy;       // F = f E
+  R hPx, hPy;     // half of row n of the pressure tensor P = D E
+};
+
+// One side of a face: F and half of row n of P = D E, with
+// D = iso I + g f (x) f (closure_parts), f2 = |f|^2 <= 1 up to rounding.
+template <typename R, int N>
+__device__ __forceinline__ FaceSide<R> face_side(R E, R fx, R fy, R f2) {
+  FaceSide<R> o;
+  const R s = fsqrt(R(4) - R(3) * clamp_unit(f2));
+  const R hg = frcp(s * R(2.0 / 3.0) + R(4.0 / 3.0));      // g / 2
+  const R e6 = E * R(1.0 / 6.0);
+  const R hiE = fma(s, e6, -e6);                           // iso E / 2 = (s - 1) E / 6
+  o.Fx = fx * E;
+  o.Fy = fy * E;
+  const R t = hg * (N == 0 ? o.Fx : o.Fy);                 // g F_n / 2
+  o.hPx = N == 0 ? t * fx + hiE : t * fx;
+  o.hPy = N == 0 ? t * fy : t * fy + hiE;
+  return o;
+}
+
 template <typename R, int N, bool EIG = false>
-__device__ __forceinline__ Flux3<R> face_flux(R EL, R fxL, R fyL, R ER, R fxR, R fyR, R eL,
-                                              R eR, R hL, R hR, R aFL, R aFR, R un_c) {
+__device__ __forceinline__ Flux3<R> face_flux(R EL, R fxL, R fyL, R ER, R fxR, R fyR, R dEc,
+                                              R hL, R hR, R aFL, R aFR, R un_c) {
   // causality at the interface: |f| > 1 is scaled back to 1
-  const R nL = fxL * fxL + fyL * fyL, nR = fxR * fxR + fyR * fyR;
+  R nL = fxL * fxL + fyL * fyL, nR = fxR * fxR + fyR * fyR;
   if (nL > R(1) || nR > R(1)) [[unlikely]] {    // rare: one branch for both sides
     const R sL = nL > R(1) ? frsq(nL) : R(1), sR = nR > R(1) ? frsq(nR) : R(1);
     fxL *= sL; fyL *= sL; fxR *= sR; fyR *= sR;
+    nL = fxL * fxL + fyL * fyL;
+    nR = fxR * fxR + fyR * fyR;
   }
-  Eddington<R> DL = closure_f(fxL, fyL), DR = closure_f(fxR, fyR);
-  R FxL = fxL * EL, FyL = fyL * EL, FxR = fxR * ER, FyR = fyR * ER;
-  R PxL, PyL, PxR, PyR;       // row n of the pressure tensor, P = D E
-  if (N == 0) { PxL = DL.xx * EL; PyL = DL.xy * EL; PxR = DR.xx * ER; PyR = DR.xy * ER; }
-  else        { PxL = DL.xy * EL; PyL = DL.yy * EL; PxR = DR.xy * ER; PyR = DR.yy * ER; }
+  const FaceSide<R> L = face_side<R, N>(EL, fxL, fyL, nL);
+  const FaceSide<R> Q = face_side<R, N>(ER, fxR, fyR, nR);
   // flux optical depth between the centroids and the blend eps(tau)
-  R tau = aFL * hL - aFR * hR;
-  R inv = frcp(R(0.2) + tau + tau * tau);
-  R eps = (R(0.2) + tau) * inv;
-  R dco = tau * inv * R(1.0 / 3.0);     // (1 - eps) / (3 tau)
-  R FnL = (N == 0) ? FxL : FyL, FnR = (N == 0) ? FxR : FyR;
+  const R tau = aFL * hL - aFR * hR;
+  const R t02 = tau + R(0.2);
+  const R inv = frcp(tau * tau + t02);
+  const R heps = t02 * (R(0.5) * inv);          // eps / 2
+  const R dco = tau * inv * R(1.0 / 3.0);       // (1 - eps) / (3 tau)
+  const R FnL = (N == 0) ? L.Fx : L.Fy, FnR = (N == 0) ? Q.Fx : Q.Fy;
   Flux3<R> r;
   if constexpr (EIG) {
+    const R eps = heps + heps;
     double loL, hiL, loR, hiR;
     m1_signal_speeds(N == 0 ? fxL : fyL, N == 0 ? fyL : fxL, loL, hiL);
     m1_signal_speeds(N == 0 ? fxR : fyR, N == 0 ? fyR : fxR, loR, hiR);
@@ -126,19 +153,19 @@ __device__ __forceinline__ Flux3<R> face_flux(R EL, R fxL, R fyL, R ER, R fxR, R
     } else {
       wl = R(0.5); wr = R(0.5); wd = R(0);
     }
-    r.e = eps * (wl * FnL + wr * FnR + wd * (ER - EL)) - dco * (eR - eL);
-    r.x = wl * PxL + wr * PxR + eps * wd * (FxR - FxL);
-    r.y = wl * PyL + wr * PyR + eps * wd * (FyR - FyL);
+    r.e = eps * (wl * FnL + wr * FnR + wd * (ER - EL)) - dco * dEc;
+    r.x = R(2) * (wl * L.hPx + wr * Q.hPx) + eps * wd * (Q.Fx - L.Fx);
+    r.y = R(2) * (wl * L.hPy + wr * Q.hPy) + eps * wd * (Q.Fy - L.Fy);
   } else {
-    r.e = eps * (R(0.5) * (FnL + FnR) - R(0.5) * (ER - EL)) - dco * (eR - eL);
-    r.x = R(0.5) * (PxL + PxR) - eps * R(0.5) * (FxR - FxL);
-    r.y = R(0.5) * (PyL + PyR) - eps * R(0.5) * (FyR - FyL);
+    r.e = heps * ((FnL + FnR) - (ER - EL)) - dco * dEc;
+    r.x = (L.hPx + Q.hPx) - heps * (Q.Fx - L.Fx);
+    r.y = (L.hPy + Q.hPy) - heps * (Q.Fy - L.Fy);
   }
   // upwind advection by the face velocity with the upstream reconstruction
   const bool up = un_c > R(0);
   r.e += un_c * (up ? EL : ER);
-  r.x += un_c * (up ? FxL : FxR);
-  r.y += un_c * (up ? FyL : FyR);
+  r.x += un_c * (up ? L.Fx : Q.Fx);
+  r.y += un_c * (up ? L.Fy : Q.Fy);
   return r;
 }
 
@@ -161,15 +188,18 @@ constexpr int kPX = kTX + 4, kPY = kTY + 4;   // padded tile, halo 2
 constexpr int kRX = kTX + 2, kRY = kTY + 2;   // opacity ring, halo 1
 // LDS row strides: one word more than a row, odd, so that the four rows a
 // half-wave of row-wise face runs touches fall in distinct banks.
-constexpr int kPS = kPX + 1, kRS = kRX + 1;
+template <typename R> constexpr int kPad = 1;
+template <typename R> constexpr int kPS = kPX + kPad<R>;
+template <typename R> constexpr int kRS = kRX + kPad<R>;
 constexpr int kNXF = kTY * (kTX + 1);         // x-faces of a tile
 constexpr int kNYF = (kTY + 1) * kTX;         // y-faces of a tile
 
 template <typename R>
 struct AdvShared {
-  R E[kPY][kPS], fx[kPY][kPS], fy[kPY][kPS];  // staged state: E and f = F/E
+  R E[kPY][kPS<R>], fx[kPY][kPS<R>], fy[kPY][kPS<R>];  // staged state: E and f = F/E
   int src[kPY * kPX];                          // staging sources (see advect_block)
-  R aF[kRY][kRS];                              // alpha_F of the ring, this bin
+  R aF[kRY][kRS<R>];                           // alpha_F of the ring, this bin
+  R ral[kRX * kRY], racF[kRX * kRY];           // ring: alpha, alpha_cF (fixed over bins)
   R fle[kNXF + kNYF], flx[kNXF + kNYF], fly[kNXF + kNYF];  // face fluxes
   R un[kNXF + kNYF];                           // face-normal velocity / c
   R xidl[kTX + 3], xhp[kTX + 2], xhm[kTX + 2]; // columns x0-1 .. (geometry)
@@ -266,7 +296,7 @@ __device__ __forceinline__ void face_run(AdvShared<R>& S, int line, int c0, int 
     else        { aFL = S.aF[c][line + 1]; aFR = S.aF[c + 1][line + 1]; f = kNXF + c * kTX + line; }
     const Flux3<R> r = face_flux<R, N, EIG>(e1 + sE * hL, x1 + sX * hL, y1 + sY * hL,
                                        e2 + tE * hR, x2 + tX * hR, y2 + tY * hR,
-                                       e1, e2, hL, hR, aFL, aFR, S.un[f]);
+                                       e2 - e1, hL, hR, aFL, aFR, S.un[f]);
     S.fle[f] = r.e; S.flx[f] = r.x; S.fly[f] = r.y;
     e1 = e2; x1 = x2; y1 = y2;
     e2 = e3; x2 = x3; y2 = y3;
@@ -370,14 +400,15 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
   const int tid = threadIdx.x;
   const R inv_c = R(1.0 / kC);
 
-  // ---- once per block: ring opacities (registers), geometry and face
+  // ---- once per block: ring opacities (the class or cell of each entry in
+  //      registers, its alpha and alpha_cF in LDS), geometry and face
   //      velocities (LDS)
-  R ral[kRingPerLane], racF[kRingPerLane];
   int rcls[kRingPerLane];
 #pragma unroll
   for (int m = 0; m < kRingPerLane; ++m) {
     const int e = tid + 256 * m;
-    ral[m] = R(0); racF[m] = R(0); rcls[m] = 0;
+    R al = R(0), acf = R(0);
+    rcls[m] = 0;
     if (e < kRX * kRY) {
       const int ri = e % kRX, rj = e / kRX;
       int si, sj, sgx, sgy;
@@ -385,11 +416,13 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
       if (ghost_source(x0 + ri - 1, y0 + rj - 1, nx, ny, a.bc, 1, si, sj, sgx, sgy, vac) && !vac) {
         const size_t c = (size_t)sj * nx + si;
         if constexpr (BAND) {            // alpha_F = 1 * kappa_F + 0 below
-          ral[m] = R(1); racF[m] = R(0); rcls[m] = (int)c;
+          al = R(1); rcls[m] = (int)c;
         } else {
-          ral[m] = a.alpha[c]; racF[m] = a.acF[c]; rcls[m] = a.cls[c];
+          al = a.alpha[c]; acf = a.acF[c]; rcls[m] = a.cls[c];
         }
       }
+      S.ral[e] = al;
+      S.racF[e] = acf;
     }
   }
   for (int e = tid; e < kTX + 3; e += 256) {
@@ -426,7 +459,7 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
   bool own[2];
   unsigned cidx[2];                 // cell index in a bin plane (< 2^29)
   int ccls[2];
-  R acabs[2], pda[2], em[2], gxx[2], gyy[2], gxy[2], gpp[2], cy[2];
+  R acabs[2], pda[2], em[2], gxx[2], gyy[2], gxy[2], gsum[2], cy[2];
   const int gi = x0 + tx;
   const bool colok = gi < nx;
   const R cxm = colok ? a.cxm[gi] : R(0), cxp = colok ? a.cxp[gi] : R(0);
@@ -448,7 +481,7 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
     gxx[m] = own[m] ? a.grad[c] : R(0);
     gyy[m] = own[m] ? a.grad[nc + c] : R(0);
     gxy[m] = own[m] ? a.grad[2 * nc + c] : R(0);
-    gpp[m] = own[m] ? a.grad[3 * nc + c] : R(0);
+    gsum[m] = own[m] ? gxx[m] + gyy[m] + a.grad[3 * nc + c] : R(0);   // trace part
     cy[m] = own[m] ? a.cy[gj] : R(0);
   }
   const R ctdt = a.ctdt, ctdt_c = a.ctdt_c;
@@ -538,7 +571,7 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
     for (int m = 0; m < kStagePerLane; ++m) {
       const int e = tid + 256 * m, v = sv[m];
       if (e < kPX * kPY) {
-        const int d = e + e / kPX;         // entry (e / kPX, e % kPX) at row stride kPS
+        const int d = e + (e / kPX) * kPad<R>;   // entry (e / kPX, e % kPX) at row stride kPS
         (&S.E[0][0])[d] = v >= 0 ? ev[m] : R(0);
         (&S.fx[0][0])[d] = v < 0 ? R(0) : ((v & 1) ? -xv[m] : xv[m]);
         (&S.fy[0][0])[d] = v < 0 ? R(0) : ((v & 2) ? -yv[m] : yv[m]);
@@ -547,7 +580,7 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
 #pragma unroll
     for (int m = 0; m < kRingPerLane; ++m) {
       const int e = tid + 256 * m;
-      if (e < kRX * kRY) (&S.aF[0][0])[e + e / kRX] = ral[m] * hr[m] + racF[m];
+      if (e < kRX * kRY) (&S.aF[0][0])[e + (e / kRX) * kPad<R>] = S.ral[e] * hr[m] + S.racF[e];
     }
     __syncthreads();
     // (2) every face of the tile once, in runs of four consecutive faces
@@ -577,11 +610,20 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
       R Es = EC - (cxp * S.fle[w + 1] - cxm * S.fle[w] + cy[m] * (S.fle[so + kTX] - S.fle[so]));
       R Xs = fxc * EC - (cxp * S.flx[w + 1] - cxm * S.flx[w] + cy[m] * (S.flx[so + kTX] - S.flx[so]));
       R Ys = fyc * EC - (cxp * S.fly[w + 1] - cxm * S.fly[w] + cy[m] * (S.fly[so + kTX] - S.fly[so]));
-      const R n2 = fxc * fxc + fyc * fyc;
-      const R sc = n2 > R(1) ? frsq(n2) : R(1);
-      const Eddington<R> D = closure_f(fxc * sc, fyc * sc);
-      Es -= ctdt_c * (D.xx * gxx[m] + D.yy * gyy[m] + D.xy * gxy[m] + D.pp * gpp[m]) * EC;
-      Xs += chp * D.pp * EC;
+      // closure of the cell's reduced flux (|f| > 1 scaled back to 1 first);
+      // work term D : grad u = iso (gxx + gyy + gpp) + g (fx^2 gxx + fy^2 gyy
+      // + fx fy gxy), hoop term from D_phiphi = iso
+      R cfx = fxc, cfy = fyc;
+      R xx2 = cfx * cfx, yy2 = cfy * cfy;
+      if (xx2 + yy2 > R(1)) [[unlikely]] {
+        const R sc = frsq(xx2 + yy2);
+        cfx *= sc; cfy *= sc;
+        xx2 = cfx * cfx; yy2 = cfy * cfy;
+      }
+      const ClosureParts<R> D = closure_parts(xx2 + yy2);
+      const R ddu = D.iso * gsum[m] + D.g * (xx2 * gxx[m] + yy2 * gyy[m] + (cfx * cfy) * gxy[m]);
+      Es -= ctdt_c * ddu * EC;
+      Xs += chp * D.iso * EC;
       // causality: E >= 0 and |F| <= E
       const bool pos = Es > R(0);
       const R cl = pos ? causal_scale(Es, Xs, Ys) : R(1);
