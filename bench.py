@@ -140,10 +140,12 @@ def _timed(g, steps):
                 ms_per_step=1e3 * wall / steps)
 
 
-def run_path(p, prec, steps, warmup, fp64_tau=float("inf"), state=None, late=0):
+def run_path(p, prec, steps, warmup, fp64_tau=float("inf"), state=None, late=0, final=False):
     """Times `steps` steps after `warmup` untimed ones, from `state` (physical
     E, F_x, F_y) or from E = F = 0; with late > 0 also `steps` steps starting
-    at step `late`, or right after the first window if that ends later."""
+    at step `late`, or right after the first window if that ends later.  With
+    final, res["final"] holds E, F_x, F_y and the force after the timed
+    window (host arrays, taken after the timing)."""
     import torch
     from paper_2606_02711_amd import m1
     log(f"[bench] init {prec} fp64_tau={fp64_tau} start={'developed' if state else 'empty'}")
@@ -158,6 +160,8 @@ def run_path(p, prec, steps, warmup, fp64_tau=float("inf"), state=None, late=0):
         first = max(late, warmup + steps)
         g.step(first - warmup - steps)
         res["late"] = dict(_timed(g, steps), first_step=first)
+    if final:
+        res["final"] = [t.cpu().numpy() for t in g.state()] + [g.force().cpu().numpy()]
     del g
     torch.cuda.empty_cache()
     return res
@@ -567,8 +571,16 @@ def main():
     r32e = run_path(p, "fp32", args.steps, args.warmup, args.fp64_tau, late=1000)
     # the developed state every timed and compared run below starts from
     state = inputs.filled_state(p, r32e["nb"], e_peak(p, r32e["dt"]), seed=2)
-    r32 = run_path(p, "fp32", args.steps, args.warmup, args.fp64_tau, state=state)
-    r64 = None if args.no_fp64 else run_path(p, "fp64", args.steps, args.warmup, state=state)
+    r32 = run_path(p, "fp32", args.steps, args.warmup, args.fp64_tau, state=state,
+                   final=not args.no_fp64)
+    r64 = None if args.no_fp64 else run_path(p, "fp64", args.steps, args.warmup, state=state,
+                                             final=True)
+    # FP32 against FP64 after the whole timed window (both from the developed
+    # state; the FP64 path meets the oracle step by step, see "errors")
+    long_err = None
+    if r64 is not None:
+        long_err = {"steps": args.warmup + args.steps, "start": "developed state",
+                    "fp32_vs_fp64": error_figures(r32.pop("final"), r64.pop("final"))}
     dom = "advect_source" if r32["ms_advect"] >= r32["ms_freq"] else "freq_step"
     dom_ms = (r32["ms_advect"] if dom == "advect_source" else r32["ms_freq"]) / args.steps
     alg_bytes = 24.0 * r32["cell_bins"]                    # per launch, FP32
@@ -649,6 +661,8 @@ def main():
     g32 = gpu_after(p, "fp32", state, 10)
     g64 = gpu_after(p, "fp64", state, 10)
     out["errors"] = {"steps": 10, "start": "developed state", "fp32_vs_fp64": error_figures(g32, g64)}
+    if long_err is not None:
+        out["errors"]["after_timed_window"] = long_err
     if not args.no_cpu:
         out["cpu_baseline"], ref = cpu_baseline(p, state, 10, 1)
         out["errors"]["fp32_vs_oracle"] = error_figures(g32, ref)

@@ -524,9 +524,9 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
         const R aFC = a.alpha[c] * hC + a.acF[c];
         const R src = em[m] * a.phi[(size_t)cc * nb + k];
         const R kE = acabs[m] + pda[m] * hC;
-        const R dF = frcp(R(1) + ctdt * aFC);
-        sink.put(a, m, k, koff, c, hC, (EC + ctdt * src) * frcp(R(1) + ctdt * kE),
-                 fxc * EC * dF, fyc * EC * dF);
+        const R yF = ctdt * aFC;
+        sink.put(a, m, k, koff, c, hC, decay_1p(EC + ctdt * src, ctdt * kE),
+                 decay_1p(fxc * EC, yF), decay_1p(fyc * EC, yF));
       }
       continue;
     }
@@ -638,9 +638,9 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
       }
       const R src = BAND ? pcell[m] : em[m] * pcell[m];
       const R kE = BAND ? kcell[m] : acabs[m] + pda[m] * hC;
-      const R dF = frcp(R(1) + ctdt * aFC);
-      sink.put(a, m, k, koff, cidx[m], hC, (Es + ctdt * src) * frcp(R(1) + ctdt * kE), Xs * dF,
-               Ys * dF);
+      const R yF = ctdt * aFC;
+      sink.put(a, m, k, koff, cidx[m], hC, decay_1p(Es + ctdt * src, ctdt * kE),
+               decay_1p(Xs, yF), decay_1p(Ys, yF));
     }
     __syncthreads();
   }
