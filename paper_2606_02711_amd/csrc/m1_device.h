@@ -192,18 +192,6 @@ __device__ __forceinline__ Eddington<R> closure_f(R fx, R fy) {
   return d;
 }
 
-// v / (1 + x) for x >= 0, the implicit (BDF1) decay of the source step.  For
-// x < 1 it is formed as v - v x/(1 + x): the rounding of 1 + x then enters
-// only through the change v x/(1 + x), not through the whole of v.  In a cell
-// whose state barely changes between steps the plain product v / (1 + x)
-// repeats the same relative rounding error every step, and in FP32 that
-// error accumulates linearly over a long run.
-template <typename R>
-__device__ __forceinline__ R decay_1p(R v, R x) {
-  const R r = frcp(R(1) + x);
-  return x < R(1) ? v - v * (x * r) : v * r;
-}
-
 // Smallest E whose reciprocal is finite with margin (2^-120 in float,
 // 2^-1000 in double).  Below it (subnormal far-wing values) f = F/E is formed
 // by true division, which stays bounded because |F| <= E.

@@ -169,6 +169,37 @@ __device__ __forceinline__ Flux3<R> face_flux(R EL, R fxL, R fyL, R ER, R fxR, R
   return r;
 }
 
+// Emission/absorption (Section 2.1, step 2: BDF1) after the transport step of
+// one cell.  E0, fx0, fy0: the state at the start of the step (F = f E);
+// dE, dX, dY: the changes of the transport step, so that E* = E0 - dE etc.;
+// Es, Xs, Ys: the post-transport state after the causality clamp; kept: the
+// clamp left it unchanged; s = c_tilde dt S, x = c_tilde dt kappa_E,
+// y = c_tilde dt alpha_F.  Then E** = (E* + s)/(1 + x) and F** = F*/(1 + y).
+// Where the clamp kept the state and x < 1 (y < 1), E** is formed as
+//   E0 - (dE - s + (E* + s) x/(1 + x))
+// (F** as fx0 E0 - (dX + F* y/(1 + y))), so that a step rounds the state once,
+// at its own scale: the changes are summed first.  Rounding it after every
+// partial update repeats nearly the same error each step in a slowly
+// changing field, and in FP32 that error grows linearly over a long run.
+template <typename R>
+__device__ __forceinline__ void source_update(R E0, R fx0, R fy0, R dE, R dX, R dY, R Es, R Xs,
+                                              R Ys, bool kept, R s, R x, R y, R& En, R& Xn,
+                                              R& Yn) {
+  const R rx = frcp(R(1) + x), ry = frcp(R(1) + y);
+  if (kept && x < R(1)) En = E0 - ((dE - s) + (Es + s) * (x * rx));
+  else                  En = x < R(1) ? (Es + s) - (Es + s) * (x * rx) : (Es + s) * rx;
+  if (kept && y < R(1)) {
+    Xn = fx0 * E0 - (dX + Xs * (y * ry));
+    Yn = fy0 * E0 - (dY + Ys * (y * ry));
+  } else if (y < R(1)) {
+    Xn = Xs - Xs * (y * ry);
+    Yn = Ys - Ys * (y * ry);
+  } else {
+    Xn = Xs * ry;
+    Yn = Ys * ry;
+  }
+}
+
 // ---------------------------------------------------------------- K2
 // LDS-tiled advection + emission/absorption.  A block owns a tile of
 // kTX x kTY cells and walks a run of bins.  Per bin: (1) the tile plus two
@@ -524,9 +555,10 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
         const R aFC = a.alpha[c] * hC + a.acF[c];
         const R src = em[m] * a.phi[(size_t)cc * nb + k];
         const R kE = acabs[m] + pda[m] * hC;
-        const R yF = ctdt * aFC;
-        sink.put(a, m, k, koff, c, hC, decay_1p(EC + ctdt * src, ctdt * kE),
-                 decay_1p(fxc * EC, yF), decay_1p(fyc * EC, yF));
+        R En, Xn, Yn;
+        source_update(EC, fxc, fyc, R(0), R(0), R(0), EC, fxc * EC, fyc * EC, true, ctdt * src,
+                      ctdt * kE, ctdt * aFC, En, Xn, Yn);
+        sink.put(a, m, k, koff, c, hC, En, Xn, Yn);
       }
       continue;
     }
@@ -607,9 +639,6 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
       const R EC = S.E[pj][pi], fxc = S.fx[pj][pi], fyc = S.fy[pj][pi];
       const int w = lj * (kTX + 1) + tx;             // west face; east = w + 1
       const int so = kNXF + lj * kTX + tx;           // south face; north = so + kTX
-      R Es = EC - (cxp * S.fle[w + 1] - cxm * S.fle[w] + cy[m] * (S.fle[so + kTX] - S.fle[so]));
-      R Xs = fxc * EC - (cxp * S.flx[w + 1] - cxm * S.flx[w] + cy[m] * (S.flx[so + kTX] - S.flx[so]));
-      R Ys = fyc * EC - (cxp * S.fly[w + 1] - cxm * S.fly[w] + cy[m] * (S.fly[so + kTX] - S.fly[so]));
       // closure of the cell's reduced flux (|f| > 1 scaled back to 1 first);
       // work term D : grad u = iso (gxx + gyy + gpp) + g (fx^2 gxx + fy^2 gyy
       // + fx fy gxy), hoop term from D_phiphi = iso
@@ -622,11 +651,20 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
       }
       const ClosureParts<R> D = closure_parts(xx2 + yy2);
       const R ddu = D.iso * gsum[m] + D.g * (xx2 * gxx[m] + yy2 * gyy[m] + (cfx * cfy) * gxy[m]);
-      Es -= ctdt_c * ddu * EC;
-      Xs += chp * D.iso * EC;
+      // the changes of the transport step (flux divergence, work and hoop
+      // terms), summed before they meet the state
+      const R dE = (cxp * S.fle[w + 1] - cxm * S.fle[w] + cy[m] * (S.fle[so + kTX] - S.fle[so]))
+                   + ctdt_c * ddu * EC;
+      const R dX = (cxp * S.flx[w + 1] - cxm * S.flx[w] + cy[m] * (S.flx[so + kTX] - S.flx[so]))
+                   - chp * D.iso * EC;
+      const R dY = cxp * S.fly[w + 1] - cxm * S.fly[w] + cy[m] * (S.fly[so + kTX] - S.fly[so]);
+      R Es = EC - dE;
+      R Xs = fxc * EC - dX;
+      R Ys = fyc * EC - dY;
       // causality: E >= 0 and |F| <= E
       const bool pos = Es > R(0);
       const R cl = pos ? causal_scale(Es, Xs, Ys) : R(1);
+      const bool kept = pos && cl == R(1);          // no clamp: the usual case
       Xs = pos ? Xs * cl : R(0);
       Ys = pos ? Ys * cl : R(0);
       Es = pos ? Es : R(0);
@@ -638,9 +676,10 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
       }
       const R src = BAND ? pcell[m] : em[m] * pcell[m];
       const R kE = BAND ? kcell[m] : acabs[m] + pda[m] * hC;
-      const R yF = ctdt * aFC;
-      sink.put(a, m, k, koff, cidx[m], hC, decay_1p(Es + ctdt * src, ctdt * kE),
-               decay_1p(Xs, yF), decay_1p(Ys, yF));
+      R En, Xn, Yn;
+      source_update(EC, fxc, fyc, dE, dX, dY, Es, Xs, Ys, kept, ctdt * src, ctdt * kE,
+                    ctdt * aFC, En, Xn, Yn);
+      sink.put(a, m, k, koff, cidx[m], hC, En, Xn, Yn);
     }
     __syncthreads();
   }

@@ -51,11 +51,14 @@ def _linf(a, b):
     return d / m if m > 0 else d
 
 
-def metrics(E, Fx, Fy, force, rE, rFx, rFy, rforce):
+def metrics(E, Fx, Fy, force, rE, rFx, rFy, rforce, bin_floor=BIN_FLOOR):
     """All checks for one comparison.  State arrays [N_nu, ...cells...]
     (any trailing shape); force arrays [n_comp, ...cells...] whose first two
     components form the vector (more components, e.g. the line share, are
-    compared as a second vector)."""
+    compared as a second vector).  bin_floor: bins whose reference maximum is
+    below this share of the largest value are left out of the per-bin check;
+    the worst bin and its maximum relative to the largest value are
+    reported."""
     E, Fx, Fy, rE, rFx, rFy = [np.asarray(x, dtype=np.float64) for x in (E, Fx, Fy, rE, rFx, rFy)]
     force, rforce = np.asarray(force, dtype=np.float64), np.asarray(rforce, dtype=np.float64)
     nb = E.shape[0]
@@ -69,14 +72,22 @@ def metrics(E, Fx, Fy, force, rE, rFx, rFy, rforce):
     }
     # per-bin normalised L-infinity
     worstE = worstF = 0.0
+    kE = kF = -1
     for k in range(nb):
         mk = float(np.max(np.abs(rE[k])))
-        if mk > BIN_FLOOR * Em:
-            worstE = max(worstE, float(np.max(np.abs(E[k] - rE[k]))) / mk)
+        if mk > bin_floor * Em:
+            v = float(np.max(np.abs(E[k] - rE[k]))) / mk
+            if v > worstE:
+                worstE, kE = v, k
         fk = float(np.max(np.hypot(rFx[k], rFy[k])))
-        if fk > BIN_FLOOR * Ftm and Ftm > 0:
-            worstF = max(worstF, float(np.max(dF[k])) / fk)
+        if fk > bin_floor * Ftm and Ftm > 0:
+            v = float(np.max(dF[k])) / fk
+            if v > worstF:
+                worstF, kF = v, k
     out["bin_E"], out["bin_F"] = worstE, worstF
+    out["bin_E_at"] = [kE, float(np.max(np.abs(rE[kE]))) / Em if kE >= 0 and Em > 0 else 0.0]
+    out["bin_F_at"] = [kF, float(np.max(np.hypot(rFx[kF], rFy[kF]))) / Ftm
+                       if kF >= 0 and Ftm > 0 else 0.0]
     # per-cell relative error where E is not negligible
     m = rE > CELL_FLOOR * Em
     out["cell_E"] = float(np.max(np.abs(E[m] - rE[m]) / rE[m])) if m.any() else 0.0
@@ -98,14 +109,14 @@ def metrics(E, Fx, Fy, force, rE, rFx, rFy, rforce):
     return out
 
 
-def check(name, prec, got, ref, bounds=None, **override):
+def check(name, prec, got, ref, bounds=None, bin_floor=BIN_FLOOR, **override):
     """Compares got = (E, Fx, Fy, force) with ref (same layout) and asserts
     the bounds of `prec` (or `bounds`, with single entries overridden by
     keyword).  Returns the metrics."""
     b = dict(BOUNDS[prec] if bounds is None else bounds)
     b.update(override)
-    m = metrics(*got, *ref)
-    line = {"case": name, "prec": prec, **m}
+    m = metrics(*got, *ref, bin_floor=bin_floor)
+    line = {"case": name, "prec": prec, "bin_floor": bin_floor, **m}
     print("   parity", json.dumps(line), flush=True)
     path = os.environ.get("PARITY_LOG")
     if path:

@@ -63,32 +63,43 @@ def test_config2_full_size_from_developed_state(developed, prec, fp64_tau):
                  (E, Fx, Fy, f), (o.E, o.Fx, o.Fy, o.force))
 
 
-# Config 2 as its workload is stated: 1000 steps from E = F = 0, the FP32
-# path against the FP64 path (which meets the oracle step by step: the test
-# above and test_gpu_parity.py).  Measured on the MI355X: relative L2 3.5e-7
-# (E), 3.4e-7 / 4.3e-7 (F_x, F_y), 1.2e-7 (force), well inside the targets
-# 1e-5 and 1e-4; L-infinity 9e-8 (E), 5e-7 (F).  The element-wise figures
-# are larger at the radiation front, whose position differs between the two
-# paths by a fraction of a cell: per bin 7e-5 (E) and 2.5e-4 (F), per cell
-# 1.1e-3 (E, F where E > 1e-6 max E), per-cell force 5.5e-4.  The bounds
-# below keep a margin of about four.
+# Config 2 over 1000 steps, the FP32 path against the FP64 path (which meets
+# the oracle step by step: the test above and test_gpu_parity.py), from
+# E = F = 0 (the workload as stated) and from the developed state.  A step
+# rounds the FP32 state once (source_update), so the error does not grow
+# with the step count.  Measured on the MI355X, relative L2 on E / F / force:
+# from E = F = 0 5.7e-8 / 1.8e-7 / 4.3e-8, per cell up to 3.2e-4 at the
+# radiation front (whose position differs by a fraction of a cell); from the
+# developed state 3.4e-7 / 3.1e-6 / 7.4e-7.  The usual FP32 bounds apply,
+# except per bin from the developed state: there the largest per-bin errors
+# are in the outermost dozen bins at each end of the frequency grid, which
+# hold about 2e-8 of the peak energy, up to 1.1e-3 (E) and 1.3e-3 (F) of
+# their own maxima (errors fall to ~3e-4 a dozen bins in); the bound for
+# that check is 2e-3.
 LONG_STEPS = 1000
 
 
-def test_config2_fp32_against_fp64_over_1000_steps_from_empty():
+@pytest.mark.parametrize("start", ["empty", "developed"])
+def test_config2_fp32_against_fp64_over_1000_steps(start):
     import torch
     from paper_2606_02711_amd import m1
     p = inputs.config2()
+    state = None
     out = {}
     for prec in ("fp64", "fp32"):
-        print(f"[gpu] config 2, {LONG_STEPS} steps from E = F = 0, {prec}", flush=True)
+        print(f"[gpu] config 2, {LONG_STEPS} steps from {start}, {prec}", flush=True)
         g = m1.M1Grid(p, prec=prec)
+        if start == "developed":
+            if state is None:
+                state = inputs.filled_state(p, g.nb, e_peak(p, g.dt), seed=2)
+            g.set_state(*state)
         g.step(LONG_STEPS)
         out[prec] = [t.double().cpu().numpy() for t in g.state()] + [g.force().cpu().numpy()]
         g.free()
         del g
         torch.cuda.empty_cache()
-    m = parity.check("config2 1000 steps fp32 vs fp64", "fp32", out["fp32"], out["fp64"],
-                     bin=1e-3, cell=5e-3, cell_force=2e-3)
-    assert m["l2_E"] < 1e-5 and m["l2_Fx"] < 1e-5 and m["l2_Fy"] < 1e-5
-    assert m["l2_force"] < 1e-4
+    name = f"config2 {LONG_STEPS} steps from {start} fp32 vs fp64"
+    if start == "empty":
+        parity.check(name, "fp32", out["fp32"], out["fp64"])
+    else:
+        parity.check(name, "fp32", out["fp32"], out["fp64"], bin=2e-3)
