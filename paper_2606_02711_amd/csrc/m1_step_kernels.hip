@@ -769,7 +769,9 @@ __device__ __forceinline__ float fexp(float x) {
 // E1(z) = (e^z - 1)/z.  Numerator and denominator are scaled by e^{-m},
 // m = max(A, B, 0) (an exact rewrite), so every exponential is <= 1 and
 // e^{-m} E1(z) <= 2: nothing overflows at any Peclet number.  E1 is taken
-// from its series for |z| < 1/2, else from (e^{z-m} - e^{-m})/z.
+// from its series for |z| < 1/2, else from (e^{z-m} - e^{-m})/z.  Of the
+// three exponents A - m, B - m and -m the one that attains the maximum is
+// exactly 0, so two exponentials give all three factors.
 template <typename T>
 __device__ __forceinline__ void interface_rates(T ql, T Cl, T qr, T Cr, T& gl, T& gr) {
   // No contraction here: A - m must be exactly 0 on the dominant side.  A
@@ -777,9 +779,13 @@ __device__ __forceinline__ void interface_rates(T ql, T Cl, T qr, T Cr, T& gl, T
   // A (large when |A| ~ 1e10) in the exponent.
 #pragma clang fp contract(off)
   const T A = -Cl * ql, B = Cr * qr;
-  T m = A > B ? A : B;
-  m = m > T(0) ? m : T(0);
-  const T eAm = fexp(A - m), eBm = fexp(B - m), em = fexp(-m);
+  const bool Alo = A < B;
+  const T lo = Alo ? A : B, hi = Alo ? B : A;
+  const bool pos = hi >= T(0);           // m = hi, else m = 0
+  const T e1 = fexp(pos ? lo - hi : lo);  // e^{lo - m}
+  const T e2 = fexp(pos ? -hi : hi);      // e^{-m}, else e^{hi - m}
+  const T ehi = pos ? T(1) : e2, em = pos ? e2 : T(1);
+  const T eAm = Alo ? e1 : ehi, eBm = Alo ? ehi : e1;
   // |A|, |B| >= 1/2 on the division branches; den is positive
   const T sA = fabs(A) < T(0.5) ? em * e1_series(A) : (eAm - em) * frcp(A);
   const T sB = fabs(B) < T(0.5) ? em * e1_series(B) : (eBm - em) * frcp(B);
@@ -909,7 +915,25 @@ __device__ __forceinline__ void freq_backward(const GridArgs<R>& a, size_t c, si
                                               R* __restrict__ Eio,
                                               const ZW<R>* __restrict__ zw) {
   double y = 0.0;
-  for (int k = a.nb - 1; k >= 0; --k) {
+  int k = a.nb - 1;
+  // the loads of G bins at a time, then their G dependent steps: one load in
+  // flight per wave would leave this memory-bound sweep waiting on latency
+  constexpr int G = 8;
+  for (; k >= G - 1; k -= G) {
+    ZW<R> v[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const size_t idx = (size_t)(k - j) * nc + c;
+      v[j].z = __builtin_nontemporal_load(&zw[idx].z);
+      v[j].w = __builtin_nontemporal_load(&zw[idx].w);
+    }
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      y = (double)v[j].z + (double)v[j].w * y;
+      __builtin_nontemporal_store((R)(y * a.inv_dnu[k - j]), &Eio[(size_t)(k - j) * nc + c]);
+    }
+  }
+  for (; k >= 0; --k) {
     const size_t idx = (size_t)k * nc + c;
     ZW<R> v;
     v.z = __builtin_nontemporal_load(&zw[idx].z);
