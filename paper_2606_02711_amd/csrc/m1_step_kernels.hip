@@ -804,15 +804,22 @@ struct FreqCell {
   bool recoil, doppler;
   __device__ __forceinline__ void coeffs(const GridArgs<R>& a, int k, R h, R fx, R fy, T& q,
                                          T& C) const {
+    coeffs_of(a.two_nu[k], a.nu_c[k], a.dnu[k], h, fx, fy, q, C);
+  }
+  // The same with bin k's table entries (2/nu_k, nu_k/c, dnu_k) passed in: a
+  // caller whose k is uniform loads them before any divergent branch, so
+  // they stay scalar loads that no vector-memory wait depends on.
+  __device__ __forceinline__ void coeffs_of(double two_nu, double nu_c, double dnu, R h, R fx,
+                                            R fy, T& q, T& C) const {
     const T K = dd * (T)h;
     T Cv = T(0);
-    if (recoil) Cv += K * (hkT - (T)a.two_nu[k]);
+    if (recoil) Cv += K * (hkT - (T)two_nu);
     if (doppler) {
       const Eddington<T> D = closure_reduced<T>((T)fx, (T)fy);
-      Cv += (T)a.nu_c[k] * (D.xx * gxx + D.yy * gyy + D.xy * gxy + D.pp * gpp);
+      Cv += (T)nu_c * (D.xx * gxx + D.yy * gyy + D.xy * gxy + D.pp * gpp);
     }
     C = Cv;
-    const T hdnu = (T)(0.5 * a.dnu[k]);
+    const T hdnu = (T)(0.5 * dnu);
     q = K >= recip_floor<T>() ? hdnu * frcp(K) : (K > T(0) ? hdnu / K : T(0));
   }
 };
@@ -886,8 +893,9 @@ __device__ __forceinline__ void freq_forward(const GridArgs<R>& a, const FreqCel
     }
     double a_k = 0.0, b_next = 0.0;
     if (k + 1 < nb) {
+      const double tn = a.two_nu[k + 1], vc = a.nu_c[k + 1], dn = a.dnu[k + 1];
       T qn, Cn;
-      fc.coeffs(a, k + 1, h1, x1, y1, qn, Cn);
+      fc.coeffs_of(tn, vc, dn, h1, x1, y1, qn, Cn);
       force(k + 1, h1, e1, x1, y1);
       T gl, gr;
       if (qc > T(0) && qn > T(0)) {
