@@ -631,7 +631,17 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
       if (u < kTX) face_run<R, 1, 1, EIG>(S, u, kTY, kTY + 1);       // last face of column u
     }
     __syncthreads();
-    // (3) update, causality clamp, implicit source
+    // (3) update, causality clamp, implicit source.  Both cells' source
+    // coefficients are formed first: a cell-1 value first used after cell 0's
+    // stores would make the wave wait for those stores to complete (stores
+    // and loads share one counter).
+    R srcv[2], kEv[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      srcv[m] = BAND ? pcell[m] : em[m] * pcell[m];
+      kEv[m] = BAND ? kcell[m] : acabs[m] + pda[m] * hcell[m];
+    }
+    asm volatile("" : "+v"(srcv[1]), "+v"(kEv[1]), "+v"(hcell[1]));   // formed here, not later
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       if (!own[m]) continue;
@@ -674,10 +684,8 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
         sink.put(a, m, k, koff, cidx[m], hC, Es, Xs, Ys);
         continue;
       }
-      const R src = BAND ? pcell[m] : em[m] * pcell[m];
-      const R kE = BAND ? kcell[m] : acabs[m] + pda[m] * hC;
       R En, Xn, Yn;
-      source_update(EC, fxc, fyc, dE, dX, dY, Es, Xs, Ys, kept, ctdt * src, ctdt * kE,
+      source_update(EC, fxc, fyc, dE, dX, dY, Es, Xs, Ys, kept, ctdt * srcv[m], ctdt * kEv[m],
                     ctdt * aFC, En, Xn, Yn);
       sink.put(a, m, k, koff, cidx[m], hC, En, Xn, Yn);
     }
