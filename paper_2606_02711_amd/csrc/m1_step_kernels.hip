@@ -630,6 +630,19 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
       face_run<R, 1, FU, EIG>(S, c, s * kRun, s * kRun + kRun);
       if (u < kTX) face_run<R, 1, 1, EIG>(S, u, kTY, kTY + 1);       // last face of column u
     }
+    // The owned cells' staged state and alpha_F, read before the barrier:
+    // the update then reads only the fluxes (rewritten after the next bin's
+    // first barrier), so the next bin's staging may start while slower waves
+    // still update, and no third barrier per bin is needed.
+    R Ec[2], fxs[2], fys[2], aFs[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int lj = ty + kRowsPerPass * m;
+      Ec[m] = S.E[lj + 2][tx + 2];
+      fxs[m] = S.fx[lj + 2][tx + 2];
+      fys[m] = S.fy[lj + 2][tx + 2];
+      aFs[m] = S.aF[lj + 1][tx + 1];
+    }
     __syncthreads();
     // (3) update, causality clamp, implicit source.  Both cells' source
     // coefficients are formed first: a cell-1 value first used after cell 0's
@@ -645,8 +658,8 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       if (!own[m]) continue;
-      const int lj = ty + kRowsPerPass * m, pj = lj + 2, pi = tx + 2;
-      const R EC = S.E[pj][pi], fxc = S.fx[pj][pi], fyc = S.fy[pj][pi];
+      const int lj = ty + kRowsPerPass * m;
+      const R EC = Ec[m], fxc = fxs[m], fyc = fys[m];
       const int w = lj * (kTX + 1) + tx;             // west face; east = w + 1
       const int so = kNXF + lj * kTX + tx;           // south face; north = so + kTX
       // closure of the cell's reduced flux (|f| > 1 scaled back to 1 first);
@@ -679,7 +692,7 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
       Ys = pos ? Ys * cl : R(0);
       Es = pos ? Es : R(0);
       const R hC = hcell[m];
-      const R aFC = S.aF[lj + 1][tx + 1];
+      const R aFC = aFs[m];
       if constexpr (SUB) {
         sink.put(a, m, k, koff, cidx[m], hC, Es, Xs, Ys);
         continue;
@@ -689,7 +702,6 @@ __device__ __forceinline__ void advect_block(const GridArgs<R>& a, const unsigne
                     ctdt * aFC, En, Xn, Yn);
       sink.put(a, m, k, koff, cidx[m], hC, En, Xn, Yn);
     }
-    __syncthreads();
   }
   sink.finish(a, own, cidx);
 }
